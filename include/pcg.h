@@ -1,0 +1,183 @@
+/*
+ * pcg.h -- C ABI of libpcg, a matrix-free, vertical-line-preconditioned
+ * conjugate gradient solver for anisotropic 3D elliptic problems on flat
+ * tensor-product grids, after Mueller, Guo, Scheichl and Shi,
+ * "Matrix-free GPU implementation of a preconditioned conjugate gradient
+ * solver for anisotropic elliptic PDEs" (arXiv 1302.7193).
+ *
+ * The operator is the cell-centred finite-volume discretisation of
+ *     -div(K grad u) + u = f,   K = diag(K_h, K_h, K_v),
+ * on n_x * n_y vertical columns of n_z levels (Sec. 3.1, eqs.
+ * ModelEqnCubedSphere, DiagonalMatrix, TridiagonalMatrix): each column block
+ * A_T is tridiagonal and the coupling to a horizontal neighbour is diagonal.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout.  Every field vector holds n = n_x*n_y*n_z values with cell (i,j,k)
+ *   at index l = (i*n_y + j)*n_z + k: vertical columns are contiguous, k = 0
+ *   is the lowest (finest) level (Sec. 3.2, eq. GlobalColumnReprConversion;
+ *   Sec. 6.1, eq. MemoryMappingCPU).  Batched vectors stack right-hand sides:
+ *   index s*n + l for right-hand side s.
+ * Memory.  Vector arguments are device pointers (HIP device memory of the
+ *   device that was current when the problem was created), owned by the
+ *   caller, 256-byte alignment recommended, never retained after return.
+ *   Host pointers are accepted only where the argument name ends in _host.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
+ *   stream).  pcg_apply/pcg_precond/pcg_csr_* are asynchronous on it;
+ *   pcg_solve and pcg_solve_batched block until the solve has finished.
+ * Errors.  Every call returns a pcg_status; nothing aborts or throws across
+ *   the ABI.  Arguments are validated before any launch; HIP failures map
+ *   to PCG_E_DEVICE.  pcg_last_error() returns the calling thread's last
+ *   message.  A problem handle may be used by one host thread at a time;
+ *   the server API is thread-safe.
+ * Numbers.  FP64 entry points compute in FP64.  FP32 entry points store
+ *   vectors and evaluate the stencil and line solves in FP32; every dot
+ *   product is accumulated in FP64 and every Krylov scalar is FP64.
+ */
+#ifndef PCG_H
+#define PCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PCG_OK = 0,
+    PCG_E_INVALID = -1,   /* bad argument or descriptor; nothing launched  */
+    PCG_E_NOMEM = -2,     /* workspace / arena / budget too small          */
+    PCG_E_DEVICE = -3,    /* HIP runtime error                             */
+    PCG_E_NOCONV = -4,    /* max_iter reached; the result is still filled  */
+    PCG_E_BREAKDOWN = -5, /* <p,Ap> <= 0, <r,z> <= 0 or a non-finite value */
+    PCG_E_AGAIN = -6,     /* request still queued or running               */
+    PCG_E_CANCELLED = -7  /* request cancelled before it ran               */
+} pcg_status;
+
+typedef enum { PCG_BC_DIRICHLET = 0, PCG_BC_PERIODIC = 1 } pcg_bc;
+typedef enum { PCG_F64 = 0, PCG_F32 = 1 } pcg_dtype;
+typedef enum { PCG_PREC_FP64 = 0, PCG_PREC_MIXED = 1 } pcg_precision;
+
+/* Grid and coefficients.  Horizontal cells are dx*dy, the n_z levels span
+ * height H with geometric grading dz[k+1] = grading*dz[k] (finest at k = 0;
+ * Sec. 3.1 asks for the finest spacing near the ground).  Top and bottom
+ * faces are Dirichlet (u = 0); each horizontal direction is Dirichlet or
+ * periodic.  Dirichlet faces use the half-cell distance.  Periodic
+ * directions need at least 3 cells.  1 <= n_z <= 1024. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy;
+    double height;
+    double grading;
+    double k_h, k_v;
+    int32_t bc_x, bc_y; /* pcg_bc */
+} pcg_problem_desc;
+
+typedef struct {
+    double rtol;          /* stop when ||r|| / ||r0|| < rtol ...              */
+    double atol;          /* ... or ||r|| < atol (Alg. InterleavedPCG)       */
+    int32_t max_iter;     /* FP64: iterations; MIXED: inner iterations total */
+    int32_t precision;    /* pcg_precision                                    */
+    double inner_rtol;    /* MIXED: relative tolerance of each FP32 inner solve */
+    int32_t max_outer;    /* MIXED: refinement steps (FP64 residuals)         */
+    int32_t fused;        /* 1: two fused sweeps per iteration (Sec. 4.3);
+                             0: separate operator, preconditioner and BLAS-1
+                                kernels (standard PCG, Sec. 4.1)             */
+    int32_t graph_chunk;  /* >0: iterations per captured HIP graph replay;
+                             0: direct launches; -1: adaptive (last count)  */
+    int32_t profile;      /* 1: time every fused kernel with HIP events
+                             (direct launches); fills the *_kernel_* fields */
+    int32_t true_residual;/* 1: also compute ||b - A x|| / ||r0|| in FP64    */
+} pcg_solve_opts;
+
+typedef struct {
+    int32_t status;            /* pcg_status of the solve                    */
+    int32_t iterations;        /* FP64: iterations; MIXED: inner iterations  */
+    int32_t outer_iterations;  /* MIXED: FP64 residual evaluations - 1       */
+    int32_t launches;          /* kernel launches issued                     */
+    double rel_res_recursive;  /* recursive ||r|| / ||r0|| at exit           */
+    double rel_res_true;       /* FP64 ||b - A x|| / ||r0|| (if requested;
+                                  always for MIXED), else -1                 */
+    double r0_norm;            /* ||b - A x0||                               */
+    double elapsed_ms;         /* host wall time of the call                 */
+    double ms_apply_kernel;    /* profile: summed time of fused apply kernel */
+    double ms_precond_kernel;  /* profile: summed time of fused precond kernel */
+    int32_t n_apply_kernel;    /* profile: launches timed                    */
+    int32_t n_precond_kernel;
+} pcg_result;
+
+typedef struct pcg_problem pcg_problem; /* opaque */
+typedef struct pcg_server pcg_server;   /* opaque */
+
+/* Default options: rtol 1e-8, atol 0, max_iter 10000, FP64, inner_rtol 3e-5,
+ * max_outer 20, fused, graph_chunk -1, no profiling, no true residual. */
+void pcg_default_opts(pcg_solve_opts *opts);
+
+/* Fill a descriptor for the unit square (dx = 1/n_x, dy = 1/n_y), height 1,
+ * K_h = 1 and K_v set from the anisotropy ratio
+ *     gamma2 = (K_v / dzbar^2) / (K_h / dx^2),  dzbar = height / n_z,
+ * i.e. the vertical/horizontal coupling ratio at the mean vertical spacing
+ * (Sec. 3, eq. Anisotropy).  bc applies to both horizontal directions. */
+pcg_status pcg_desc_from_ratio(int32_t nx, int32_t ny, int32_t nz, double grading,
+                               double gamma2, int32_t bc, pcg_problem_desc *out);
+
+/* Validate desc and precompute the column coefficient vectors (Sec. 4.2:
+ * a', b', c', d of length n_z) and the column-block factors on the current
+ * device.  Allocates a few KiB of device memory owned by the handle. */
+pcg_status pcg_problem_create(const pcg_problem_desc *desc, pcg_problem **out);
+void pcg_problem_destroy(pcg_problem *p);
+
+/* Bytes of device workspace pcg_solve needs for these options
+ * (opts may be NULL for the defaults).  nrhs >= 1 for pcg_solve_batched. */
+size_t pcg_workspace_bytes(const pcg_problem *p, const pcg_solve_opts *opts, int32_t nrhs);
+
+/* y = A x, matrix-free: the 7-point stencil is rebuilt from the column
+ * coefficient vectors and per-column geometry (Sec. 4.2, eq. for the
+ * sparse matrix-vector product).  x and y: n values of dtype; must not
+ * overlap.  Asynchronous on stream. */
+pcg_status pcg_apply(pcg_problem *p, int32_t dtype, const void *x, void *y, void *stream);
+
+/* z = M^{-1} r where M is A without the couplings between vertical columns:
+ * one tridiagonal solve per column (Sec. 4.1 and eq.
+ * MatrixFreeTridiagonalSystem).  r and z: n values of dtype; may alias.
+ * Asynchronous on stream. */
+pcg_status pcg_precond(pcg_problem *p, int32_t dtype, const void *r, void *z, void *stream);
+
+/* Solve A x = b.  b, x: n FP64 values; x holds x0 on entry and the solution
+ * on return.  workspace: at least pcg_workspace_bytes(p, opts, 1) bytes of
+ * device memory (contents destroyed).  FP64 precision runs the loop-fused
+ * iteration of Alg. InterleavedPCG (or, with fused = 0, standard PCG);
+ * MIXED runs FP32 inner solves inside FP64 iterative refinement, with the
+ * residual b - A x and the update of x in FP64.  Blocks until done.
+ * Returns PCG_OK, PCG_E_NOCONV or PCG_E_BREAKDOWN with result filled, or an
+ * argument/device error. */
+pcg_status pcg_solve(pcg_problem *p, const double *b, double *x, void *workspace,
+                     size_t workspace_bytes, const pcg_solve_opts *opts,
+                     pcg_result *result, void *stream);
+
+/* Solve A x_s = b_s for nrhs right-hand sides sharing one operator, all
+ * advanced together by single launches that cover every right-hand side
+ * (each with its own scalars and exit test; finished ones drop out).
+ * b, x: nrhs*n FP64 values (index s*n + l).  results: nrhs entries (host).
+ * workspace: pcg_workspace_bytes(p, opts, nrhs). */
+pcg_status pcg_solve_batched(pcg_problem *p, int32_t nrhs, const double *b, double *x,
+                             void *workspace, size_t workspace_bytes,
+                             const pcg_solve_opts *opts, pcg_result *results, void *stream);
+
+/* Assembled-CSR comparator (Sec. 6.2): bytes for the CSR arrays of dtype
+ * (values of dtype, int32 column indices, int32 row offsets), a device-side
+ * assembly into buf, and y = A x from it.  Not used by the solver. */
+size_t pcg_csr_bytes(const pcg_problem *p, int32_t dtype);
+pcg_status pcg_csr_build(pcg_problem *p, int32_t dtype, void *buf, size_t bytes, void *stream);
+pcg_status pcg_csr_apply(pcg_problem *p, int32_t dtype, const void *buf, const void *x,
+                         void *y, void *stream);
+
+/* Thread-local message of the last failing call (NUL-terminated, truncated
+ * to n bytes); returns the full length. */
+size_t pcg_last_error(char *buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCG_H */

@@ -1,0 +1,259 @@
+"""Python binding of libpcg (include/pcg.h): argument marshalling only.
+
+Every entry point of the C ABI is exposed under the same name; device
+vectors are passed as torch tensors (their data pointers) and streams as
+torch streams (default: the current stream).  Torch supplies device memory
+and streams only -- every step of the solver runs in the HIP kernels of
+libpcg.so.  Importing this package fails loudly when libpcg.so has not been
+built; there is no fallback path.
+
+The binding checks tensor sizes, dtypes and devices before a pointer crosses
+the ABI, because the library itself only sees raw pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime libpcg.so links against
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcg.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libpcg.so is not built (%s); run `python -c 'import __graft_entry__ as g; g.build()'`"
+        % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ------------------------------------------------------------- constants --
+PCG_OK, PCG_E_INVALID, PCG_E_NOMEM, PCG_E_DEVICE = 0, -1, -2, -3
+PCG_E_NOCONV, PCG_E_BREAKDOWN, PCG_E_AGAIN, PCG_E_CANCELLED = -4, -5, -6, -7
+PCG_BC_DIRICHLET, PCG_BC_PERIODIC = 0, 1
+PCG_F64, PCG_F32 = 0, 1
+PCG_PREC_FP64, PCG_PREC_MIXED = 0, 1
+STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_NOCONV",
+                -5: "E_BREAKDOWN", -6: "E_AGAIN", -7: "E_CANCELLED"}
+
+
+class pcg_problem_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("height", ctypes.c_double),
+                ("grading", ctypes.c_double), ("k_h", ctypes.c_double), ("k_v", ctypes.c_double),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32)]
+
+
+class pcg_solve_opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("fused", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("true_residual", ctypes.c_int32)]
+
+
+class pcg_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("outer_iterations", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("rel_res_recursive", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("r0_norm", ctypes.c_double), ("elapsed_ms", ctypes.c_double),
+                ("ms_apply_kernel", ctypes.c_double), ("ms_precond_kernel", ctypes.c_double),
+                ("n_apply_kernel", ctypes.c_int32), ("n_precond_kernel", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_S = ctypes.c_int
+_sig = {
+    "pcg_default_opts": (None, [ctypes.POINTER(pcg_solve_opts)]),
+    "pcg_desc_from_ratio": (_S, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_int32,
+                                 ctypes.POINTER(pcg_problem_desc)]),
+    "pcg_problem_create": (_S, [ctypes.POINTER(pcg_problem_desc), ctypes.POINTER(_P)]),
+    "pcg_problem_destroy": (None, [_P]),
+    "pcg_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(pcg_solve_opts), ctypes.c_int32]),
+    "pcg_apply": (_S, [_P, ctypes.c_int32, _P, _P, _P]),
+    "pcg_precond": (_S, [_P, ctypes.c_int32, _P, _P, _P]),
+    "pcg_solve": (_S, [_P, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(pcg_solve_opts),
+                       ctypes.POINTER(pcg_result), _P]),
+    "pcg_solve_batched": (_S, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t,
+                               ctypes.POINTER(pcg_solve_opts), ctypes.POINTER(pcg_result), _P]),
+    "pcg_csr_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
+    "pcg_csr_build": (_S, [_P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    "pcg_csr_apply": (_S, [_P, ctypes.c_int32, _P, _P, _P, _P]),
+    "pcg_last_error": (ctypes.c_size_t, [ctypes.c_char_p, ctypes.c_size_t]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class PCGError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s: %s" % (where, STATUS_NAMES.get(status, status), pcg_last_error()))
+
+
+def _check(status: int, where: str) -> int:
+    if status not in (PCG_OK, PCG_E_NOCONV, PCG_E_BREAKDOWN, PCG_E_AGAIN):
+        raise PCGError(status, where)
+    return status
+
+
+_TORCH_DTYPE = {PCG_F64: torch.float64, PCG_F32: torch.float32}
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream or None
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+def _vec(t, n: int, dtype, what: str) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % what)
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype or t.numel() < n:
+        raise ValueError("%s must be a contiguous %s CUDA tensor with >= %d elements (got %s %s %s)"
+                         % (what, dtype, n, t.dtype, tuple(t.shape), t.device))
+    return t.data_ptr()
+
+
+def _buf(t, nbytes: int, what: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous CUDA tensor" % what)
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError("%s holds %d bytes, %d needed" % (what, t.numel() * t.element_size(), nbytes))
+    return t.data_ptr()
+
+
+# ----------------------------------------------------------- entry points --
+
+def pcg_last_error() -> str:
+    n = _lib.pcg_last_error(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    _lib.pcg_last_error(buf, n + 1)
+    return buf.value.decode(errors="replace")
+
+
+def pcg_default_opts(**overrides) -> pcg_solve_opts:
+    o = pcg_solve_opts()
+    _lib.pcg_default_opts(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def pcg_desc_from_ratio(nx, ny, nz, grading, gamma2, bc=PCG_BC_DIRICHLET) -> pcg_problem_desc:
+    d = pcg_problem_desc()
+    _check(_lib.pcg_desc_from_ratio(nx, ny, nz, grading, gamma2, bc, ctypes.byref(d)),
+           "pcg_desc_from_ratio")
+    return d
+
+
+class Problem:
+    """Owning handle of a pcg_problem (destroyed with the object)."""
+
+    def __init__(self, desc: pcg_problem_desc):
+        self.desc = desc
+        self.n = desc.nx * desc.ny * desc.nz
+        h = _P()
+        _check(_lib.pcg_problem_create(ctypes.byref(desc), ctypes.byref(h)), "pcg_problem_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.pcg_problem_destroy(h)
+            self.handle = None
+
+
+def pcg_problem_create(desc: pcg_problem_desc) -> Problem:
+    return Problem(desc)
+
+
+def pcg_problem_destroy(p: Problem) -> None:
+    if p.handle:
+        _lib.pcg_problem_destroy(p.handle)
+        p.handle = None
+
+
+def pcg_workspace_bytes(p: Problem, opts: pcg_solve_opts | None = None, nrhs: int = 1) -> int:
+    return _lib.pcg_workspace_bytes(p.handle, ctypes.byref(opts) if opts else None, nrhs)
+
+
+def workspace(p: Problem, opts: pcg_solve_opts | None = None, nrhs: int = 1,
+              device="cuda") -> torch.Tensor:
+    """Allocate a workspace tensor of pcg_workspace_bytes() bytes."""
+    return torch.empty(pcg_workspace_bytes(p, opts, nrhs), dtype=torch.uint8, device=device)
+
+
+def pcg_apply(p: Problem, dtype: int, x, y, stream=None) -> int:
+    td = _TORCH_DTYPE[dtype]
+    return _check(_lib.pcg_apply(p.handle, dtype, _vec(x, p.n, td, "x"), _vec(y, p.n, td, "y"),
+                                 _stream(stream)), "pcg_apply")
+
+
+def pcg_precond(p: Problem, dtype: int, r, z, stream=None) -> int:
+    td = _TORCH_DTYPE[dtype]
+    return _check(_lib.pcg_precond(p.handle, dtype, _vec(r, p.n, td, "r"), _vec(z, p.n, td, "z"),
+                                   _stream(stream)), "pcg_precond")
+
+
+def pcg_solve(p: Problem, b, x, ws, opts: pcg_solve_opts | None = None, stream=None):
+    """Returns (status, result dict)."""
+    opts = opts or pcg_default_opts()
+    need = pcg_workspace_bytes(p, opts, 1)
+    res = pcg_result()
+    st = _check(_lib.pcg_solve(p.handle, _vec(b, p.n, torch.float64, "b"),
+                               _vec(x, p.n, torch.float64, "x"), _buf(ws, need, "workspace"),
+                               ws.numel() * ws.element_size(), ctypes.byref(opts),
+                               ctypes.byref(res), _stream(stream)), "pcg_solve")
+    return st, res.as_dict()
+
+
+def pcg_solve_batched(p: Problem, nrhs: int, b, x, ws, opts: pcg_solve_opts | None = None,
+                      stream=None):
+    """Returns (status, [result dict per right-hand side])."""
+    opts = opts or pcg_default_opts()
+    need = pcg_workspace_bytes(p, opts, nrhs)
+    res = (pcg_result * nrhs)()
+    st = _check(_lib.pcg_solve_batched(p.handle, nrhs, _vec(b, nrhs * p.n, torch.float64, "b"),
+                                       _vec(x, nrhs * p.n, torch.float64, "x"),
+                                       _buf(ws, need, "workspace"), ws.numel() * ws.element_size(),
+                                       ctypes.byref(opts), res, _stream(stream)),
+                "pcg_solve_batched")
+    return st, [r.as_dict() for r in res]
+
+
+def pcg_csr_bytes(p: Problem, dtype: int) -> int:
+    return _lib.pcg_csr_bytes(p.handle, dtype)
+
+
+def pcg_csr_build(p: Problem, dtype: int, buf, stream=None) -> int:
+    need = pcg_csr_bytes(p, dtype)
+    return _check(_lib.pcg_csr_build(p.handle, dtype, _buf(buf, need, "csr buffer"),
+                                     buf.numel() * buf.element_size(), _stream(stream)),
+                  "pcg_csr_build")
+
+
+def pcg_csr_apply(p: Problem, dtype: int, buf, x, y, stream=None) -> int:
+    td = _TORCH_DTYPE[dtype]
+    need = pcg_csr_bytes(p, dtype)
+    return _check(_lib.pcg_csr_apply(p.handle, dtype, _buf(buf, need, "csr buffer"),
+                                     _vec(x, p.n, td, "x"), _vec(y, p.n, td, "y"),
+                                     _stream(stream)), "pcg_csr_apply")
+
+
+def solve(desc: pcg_problem_desc, b: torch.Tensor, x0: torch.Tensor | None = None, **opts):
+    """Convenience: create the problem, allocate the workspace, solve once.
+    Returns (x, status, result dict)."""
+    p = Problem(desc)
+    o = pcg_default_opts(**opts)
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    ws = workspace(p, o)
+    st, res = pcg_solve(p, b, x, ws, o)
+    torch.cuda.synchronize()
+    return x, st, res

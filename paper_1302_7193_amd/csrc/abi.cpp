@@ -1,0 +1,401 @@
+// extern "C" entry points of libpcg (declared in include/pcg.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <initializer_list>
+#include <new>
+#include <sstream>
+#include <string>
+
+#include "problem.h"
+
+namespace pcg {
+
+std::string validate(const pcg_problem_desc& d);
+void build_tables(const pcg_problem_desc& d, Geom& g, std::vector<double>& vert,
+                  std::vector<double>& lu);
+size_t workspace_bytes(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs);
+pcg_status solve(pcg_problem* P, const double* b, double* x, void* workspace, size_t ws_bytes,
+                 const pcg_solve_opts& o, int64_t nrhs, pcg_result* res, hipStream_t s);
+
+namespace {
+thread_local std::string g_last_error;
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+std::string hip_msg(hipError_t e, const char* what)
+{
+    std::ostringstream m;
+    m << what << ": " << hipGetErrorName(e) << " (" << hipGetErrorString(e) << ")";
+    return m.str();
+}
+
+// Runs f with the problem's device current and restores the caller's.
+template <typename F>
+pcg_status on_device(int dev, F&& f)
+{
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) {
+        set_error("hipSetDevice failed");
+        return PCG_E_DEVICE;
+    }
+    pcg_status s;
+    try {
+        s = f();
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        s = PCG_E_NOMEM;
+    } catch (...) {
+        set_error("unexpected exception inside libpcg");
+        s = PCG_E_DEVICE;
+    }
+    if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+    return s;
+}
+
+bool valid_dtype(int32_t d) { return d == PCG_F64 || d == PCG_F32; }
+
+// The column kernels move 16-byte vectors: every device pointer crossing the
+// ABI must be 16-byte aligned.
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+pcg_status check_aligned(std::initializer_list<const void*> ptrs, const char* where)
+{
+    for (const void* p : ptrs)
+        if (!aligned16(p)) {
+            set_error(std::string(where) + ": device pointers must be 16-byte aligned");
+            return PCG_E_INVALID;
+        }
+    return PCG_OK;
+}
+
+pcg_status check_opts(const pcg_solve_opts& o)
+{
+    if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || !std::isfinite(o.rtol) || !std::isfinite(o.atol)) {
+        set_error("rtol and atol must be finite and >= 0");
+        return PCG_E_INVALID;
+    }
+    if (o.max_iter < 1) {
+        set_error("max_iter must be >= 1");
+        return PCG_E_INVALID;
+    }
+    if (o.precision != PCG_PREC_FP64 && o.precision != PCG_PREC_MIXED) {
+        set_error("precision must be PCG_PREC_FP64 or PCG_PREC_MIXED");
+        return PCG_E_INVALID;
+    }
+    if (o.precision == PCG_PREC_MIXED &&
+        (!(o.inner_rtol > 0.0 && o.inner_rtol < 1.0) || o.max_outer < 1)) {
+        set_error("mixed precision needs 0 < inner_rtol < 1 and max_outer >= 1");
+        return PCG_E_INVALID;
+    }
+    if (o.precision == PCG_PREC_MIXED && !o.fused) {
+        set_error("mixed precision runs the fused iteration only");
+        return PCG_E_INVALID;
+    }
+    if (o.graph_chunk < -1) {
+        set_error("graph_chunk must be -1, 0 or positive");
+        return PCG_E_INVALID;
+    }
+    return PCG_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace pcg
+
+using namespace pcg;
+
+extern "C" {
+
+void pcg_default_opts(pcg_solve_opts* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rtol = 1e-8;
+    o->atol = 0.0;
+    o->max_iter = 10000;
+    o->precision = PCG_PREC_FP64;
+    o->inner_rtol = 3e-5;
+    o->max_outer = 20;
+    o->fused = 1;
+    o->graph_chunk = -1;
+    o->profile = 0;
+    o->true_residual = 0;
+}
+
+pcg_status pcg_desc_from_ratio(int32_t nx, int32_t ny, int32_t nz, double grading, double gamma2,
+                               int32_t bc, pcg_problem_desc* out)
+{
+    if (!out) {
+        set_error("out is NULL");
+        return PCG_E_INVALID;
+    }
+    if (nx < 1 || ny < 1 || nz < 1 || !(gamma2 > 0.0) || !std::isfinite(gamma2)) {
+        set_error("pcg_desc_from_ratio: sizes must be >= 1 and gamma2 > 0");
+        return PCG_E_INVALID;
+    }
+    pcg_problem_desc d{};
+    d.nx = nx;
+    d.ny = ny;
+    d.nz = nz;
+    d.dx = 1.0 / nx;
+    d.dy = 1.0 / ny;
+    d.height = 1.0;
+    d.grading = grading;
+    d.k_h = 1.0;
+    const double dzbar = d.height / nz;
+    d.k_v = gamma2 * d.k_h * dzbar * dzbar / (d.dx * d.dx);
+    d.bc_x = d.bc_y = bc;
+    const std::string err = validate(d);
+    if (!err.empty()) {
+        set_error(err);
+        return PCG_E_INVALID;
+    }
+    *out = d;
+    return PCG_OK;
+}
+
+pcg_status pcg_problem_create(const pcg_problem_desc* desc, pcg_problem** out)
+{
+    if (!desc || !out) {
+        set_error("desc/out is NULL");
+        return PCG_E_INVALID;
+    }
+    *out = nullptr;
+    const std::string err = validate(*desc);
+    if (!err.empty()) {
+        set_error(err);
+        return PCG_E_INVALID;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("no HIP device");
+        return PCG_E_DEVICE;
+    }
+    pcg_problem* P = new (std::nothrow) pcg_problem();
+    if (!P) {
+        set_error("host allocation failed");
+        return PCG_E_NOMEM;
+    }
+    P->desc = *desc;
+    P->device = dev;
+    build_tables(*desc, P->geom, P->vert64, P->lu64);
+    P->shape[PCG_F64] = default_shape(desc->nz, PCG_F64);
+    P->shape[PCG_F32] = default_shape(desc->nz, PCG_F32);
+    const size_t nv = P->vert64.size(), nl = P->lu64.size();
+    const size_t b64v = al256(8 * nv), b64l = al256(8 * nl), b32v = al256(4 * nv), b32l = al256(4 * nl);
+    hipError_t e = hipMalloc(&P->dev_tables, b64v + b64l + b32v + b32l);
+    if (e != hipSuccess) {
+        set_error(hip_msg(e, "hipMalloc(tables)"));
+        delete P;
+        return PCG_E_NOMEM;
+    }
+    std::vector<char> host(b64v + b64l + b32v + b32l, 0);
+    std::memcpy(host.data(), P->vert64.data(), 8 * nv);
+    std::memcpy(host.data() + b64v, P->lu64.data(), 8 * nl);
+    float* v32 = reinterpret_cast<float*>(host.data() + b64v + b64l);
+    float* l32 = reinterpret_cast<float*>(host.data() + b64v + b64l + b32v);
+    for (size_t i = 0; i < nv; ++i) v32[i] = (float)P->vert64[i];
+    for (size_t i = 0; i < nl; ++i) l32[i] = (float)P->lu64[i];
+    e = hipMemcpy(P->dev_tables, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        set_error(hip_msg(e, "hipMemcpy(tables)"));
+        (void)hipFree(P->dev_tables);
+        delete P;
+        return PCG_E_DEVICE;
+    }
+    char* base = static_cast<char*>(P->dev_tables);
+    P->d_vert64 = reinterpret_cast<const double*>(base);
+    P->d_lu64 = reinterpret_cast<const double*>(base + b64v);
+    P->d_vert32 = reinterpret_cast<const float*>(base + b64v + b64l);
+    P->d_lu32 = reinterpret_cast<const float*>(base + b64v + b64l + b32v);
+    *out = P;
+    return PCG_OK;
+}
+
+void pcg_problem_destroy(pcg_problem* P)
+{
+    if (!P) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(P->device);
+    for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipEvent_t e : P->events) (void)hipEventDestroy(e);
+    if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
+    if (P->pinned_states) (void)hipHostFree(P->pinned_states);
+    if (P->dev_tables) (void)hipFree(P->dev_tables);
+    if (cur >= 0) (void)hipSetDevice(cur);
+    delete P;
+}
+
+size_t pcg_workspace_bytes(const pcg_problem* P, const pcg_solve_opts* opts, int32_t nrhs)
+{
+    if (!P || nrhs < 1) return 0;
+    pcg_solve_opts o;
+    if (opts) o = *opts;
+    else pcg_default_opts(&o);
+    return workspace_bytes(P, o, nrhs);
+}
+
+pcg_status pcg_apply(pcg_problem* P, int32_t dtype, const void* x, void* y, void* stream)
+{
+    if (!P || !x || !y || !valid_dtype(dtype)) {
+        set_error("pcg_apply: NULL argument or bad dtype");
+        return PCG_E_INVALID;
+    }
+    if (x == y) {
+        set_error("pcg_apply: x and y must not overlap");
+        return PCG_E_INVALID;
+    }
+    if (check_aligned({x, y}, "pcg_apply") != PCG_OK) return PCG_E_INVALID;
+    return on_device(P->device, [&]() -> pcg_status {
+        ColArgs a{};
+        a.g = P->geom;
+        a.L = P->shape[dtype].L;
+        a.blocks_per_rhs = std::max<int64_t>(1, std::min(P->block_cap, column_blocks(P->geom, P->shape[dtype])));
+        a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
+        a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
+        a.in0 = x;
+        a.io0 = y;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        hipError_t e = dtype == PCG_F64 ? launch_column<double>(Kind::Apply, a, 1, s)
+                                        : launch_column<float>(Kind::Apply, a, 1, s);
+        if (e != hipSuccess) {
+            set_error(hip_msg(e, "pcg_apply launch"));
+            return PCG_E_DEVICE;
+        }
+        return PCG_OK;
+    });
+}
+
+pcg_status pcg_precond(pcg_problem* P, int32_t dtype, const void* r, void* z, void* stream)
+{
+    if (!P || !r || !z || !valid_dtype(dtype)) {
+        set_error("pcg_precond: NULL argument or bad dtype");
+        return PCG_E_INVALID;
+    }
+    if (check_aligned({r, z}, "pcg_precond") != PCG_OK) return PCG_E_INVALID;
+    return on_device(P->device, [&]() -> pcg_status {
+        ColArgs a{};
+        a.g = P->geom;
+        a.L = P->shape[dtype].L;
+        a.blocks_per_rhs = std::max<int64_t>(1, std::min(P->block_cap, column_blocks(P->geom, P->shape[dtype])));
+        a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
+        a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
+        a.in0 = r;
+        a.io0 = z;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        hipError_t e = dtype == PCG_F64 ? launch_column<double>(Kind::Precond, a, 1, s)
+                                        : launch_column<float>(Kind::Precond, a, 1, s);
+        if (e != hipSuccess) {
+            set_error(hip_msg(e, "pcg_precond launch"));
+            return PCG_E_DEVICE;
+        }
+        return PCG_OK;
+    });
+}
+
+static pcg_status solve_common(pcg_problem* P, int32_t nrhs, const double* b, double* x,
+                               void* workspace, size_t workspace_bytes,
+                               const pcg_solve_opts* opts, pcg_result* results, void* stream)
+{
+    if (!P || !b || !x || !workspace || !results || nrhs < 1) {
+        set_error("pcg_solve: NULL argument or nrhs < 1");
+        return PCG_E_INVALID;
+    }
+    pcg_solve_opts o;
+    if (opts) o = *opts;
+    else pcg_default_opts(&o);
+    pcg_status c = check_opts(o);
+    if (c != PCG_OK) return c;
+    if (nrhs > 1 && !o.fused) {
+        set_error("pcg_solve_batched runs the fused iteration only");
+        return PCG_E_INVALID;
+    }
+    if (static_cast<const void*>(b) == static_cast<const void*>(x)) {
+        set_error("pcg_solve: b and x must not overlap");
+        return PCG_E_INVALID;
+    }
+    if (check_aligned({b, x, workspace}, "pcg_solve") != PCG_OK) return PCG_E_INVALID;
+    for (int32_t i = 0; i < nrhs; ++i) std::memset(&results[i], 0, sizeof(pcg_result));
+    return on_device(P->device, [&]() -> pcg_status {
+        return solve(P, b, x, workspace, workspace_bytes, o, nrhs, results,
+                     static_cast<hipStream_t>(stream));
+    });
+}
+
+pcg_status pcg_solve(pcg_problem* P, const double* b, double* x, void* workspace,
+                     size_t workspace_bytes, const pcg_solve_opts* opts, pcg_result* result,
+                     void* stream)
+{
+    return solve_common(P, 1, b, x, workspace, workspace_bytes, opts, result, stream);
+}
+
+pcg_status pcg_solve_batched(pcg_problem* P, int32_t nrhs, const double* b, double* x,
+                             void* workspace, size_t workspace_bytes, const pcg_solve_opts* opts,
+                             pcg_result* results, void* stream)
+{
+    return solve_common(P, nrhs, b, x, workspace, workspace_bytes, opts, results, stream);
+}
+
+size_t pcg_csr_bytes(const pcg_problem* P, int32_t dtype)
+{
+    if (!P || !valid_dtype(dtype)) return 0;
+    return csr_bytes(P->geom, dtype);
+}
+
+pcg_status pcg_csr_build(pcg_problem* P, int32_t dtype, void* buf, size_t bytes, void* stream)
+{
+    if (!P || !buf || !valid_dtype(dtype)) {
+        set_error("pcg_csr_build: NULL argument or bad dtype");
+        return PCG_E_INVALID;
+    }
+    if (check_aligned({buf}, "pcg_csr_build") != PCG_OK) return PCG_E_INVALID;
+    if (bytes < csr_bytes(P->geom, dtype)) {
+        set_error("pcg_csr_build: buffer smaller than pcg_csr_bytes()");
+        return PCG_E_NOMEM;
+    }
+    return on_device(P->device, [&]() -> pcg_status {
+        hipError_t e = csr_build(P->geom, P->d_vert64, dtype, buf, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) {
+            set_error(hip_msg(e, "pcg_csr_build launch"));
+            return PCG_E_DEVICE;
+        }
+        return PCG_OK;
+    });
+}
+
+pcg_status pcg_csr_apply(pcg_problem* P, int32_t dtype, const void* buf, const void* x, void* y,
+                         void* stream)
+{
+    if (!P || !buf || !x || !y || !valid_dtype(dtype) || x == y) {
+        set_error("pcg_csr_apply: NULL/overlapping argument or bad dtype");
+        return PCG_E_INVALID;
+    }
+    if (check_aligned({buf, x, y}, "pcg_csr_apply") != PCG_OK) return PCG_E_INVALID;
+    return on_device(P->device, [&]() -> pcg_status {
+        hipError_t e = csr_apply(P->geom, dtype, buf, x, y, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) {
+            set_error(hip_msg(e, "pcg_csr_apply launch"));
+            return PCG_E_DEVICE;
+        }
+        return PCG_OK;
+    });
+}
+
+size_t pcg_last_error(char* buf, size_t n)
+{
+    const std::string& m = g_last_error;
+    if (buf && n > 0) {
+        const size_t c = m.size() < n - 1 ? m.size() : n - 1;
+        std::memcpy(buf, m.data(), c);
+        buf[c] = '\0';
+    }
+    return m.size();
+}
+
+}  // extern "C"

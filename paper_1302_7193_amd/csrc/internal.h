@@ -1,0 +1,166 @@
+// Internal declarations of libpcg: problem tables, device solver state,
+// kernel argument blocks and the host-side launchers.  Everything here is
+// private to the library; the public interface is include/pcg.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "pcg.h"
+
+namespace pcg {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlock = 256;        // threads per workgroup of the column kernels
+constexpr int kMaxNz = 1024;       // columns up to 64 lanes x 16 levels
+constexpr int kClasses = 9;        // column classes: Dirichlet faces in x (0..2) x in y (0..2)
+constexpr int kRedSlots = 4;       // doubles per workgroup in the partial-sum buffer
+
+// Solver flags kept in device memory.
+enum : int32_t {
+    kRunning = 0,
+    kConverged = 1,   // exit test met; x still lacks alpha*p
+    kMaxIter = 2,     // iteration limit; x still lacks alpha*p
+    kBreakdown = 3,   // non-positive or non-finite curvature / residual
+};
+
+// Device-resident scalars of one Krylov solve (all FP64, Alg. InterleavedPCG:
+// alpha, beta, kappa_old, sigma, ||r||, ||r0||).  One per right-hand side.
+struct alignas(128) SolverState {
+    double alpha;
+    double beta;
+    double kappa_old;
+    double rnorm;
+    double r0norm;
+    double sigma;
+    double rtol;
+    double atol;
+    double aux;        // free slot (true residual norm, refinement scale)
+    int32_t flag;
+    int32_t iter;      // completed iterations (applications of A to p)
+    int32_t max_iter;
+    int32_t fixed;     // exit correction x += alpha*p applied
+    uint32_t ticket;   // last-workgroup counter of the current reduction
+    int32_t pad[3];
+};
+
+// Per-column geometry of the flat tensor-product grid.  The paper's
+// |T| (cell area) and alpha_{T,T'} (edge length / centre distance) are
+// rebuilt from these in every kernel, once per column (Sec. 4.2).
+struct Geom {
+    int32_t nx, ny, nz, nzp;   // nzp: n_z padded to a multiple of 4
+    int32_t per_x, per_y;
+    int64_t nh;                // columns
+    int64_t n;                 // cells
+    double area;               // |T| = dx*dy
+    double ax, ay;             // alpha_{T,T'} for x and y neighbours
+};
+
+// Column tables in device memory, for one precision T:
+//   vert[4][nzp]     s_k = a_k - b_k - c_k, b_k, c_k, d_k (eq. TridiagonalMatrix)
+//   lu[9][3][nzp]    per column class: l_k, 1/D_k, phi_k of the LU factors of
+//                    the column block A_T (zero beyond n_z)
+template <typename T>
+struct Tables {
+    const T* vert;
+    const T* lu;
+};
+
+// Launch shape of the column kernels: L lanes per column, each lane owns M
+// consecutive levels (L*M >= n_z); 64/L columns per wave; 4 waves per
+// workgroup.
+struct Shape {
+    int L = 16;
+    int M = 4;
+    int cols_per_block() const { return (kWave / L) * (kBlock / kWave); }
+};
+
+struct Launch {
+    Shape shape;
+    int64_t blocks;
+};
+
+// ---------------------------------------------------------------- kernels --
+
+enum class Kind : int {
+    Apply,        // y = A x
+    Precond,      // z = M^{-1} r
+    InitFull,     // r = b - A x, p = q = 0, state reset
+    InitZero,     // r = b, x = 0, p = q = 0, state reset
+    FusedPrec,    // kernel B: r -= alpha q; z = M^{-1} r; R, kappa; exit test; beta
+    FusedApply,   // kernel A: x += alpha p; p = z + beta p; q = A z + beta q; sigma; alpha
+    Fixup,        // x += alpha p once, after the exit test fired
+    Residual64,   // FP64 r = b - A x, ||r||; FP32 copy r * scale  (refinement)
+    Update64,     // FP64 x += scale * (u32 + alpha p32)           (refinement)
+    TrueResidual, // FP64 ||b - A x||
+};
+
+// One argument block serves every column kernel; unused pointers are null.
+// `batch` right-hand sides are stacked with stride n; block b of the grid
+// covers right-hand side b / blocks_per_rhs.
+struct ColArgs {
+    Geom g;
+    int L;
+    int64_t blocks_per_rhs;
+    const void* vert;   // Tables<T>::vert
+    const void* lu;     // Tables<T>::lu
+    const void* in0;    // x (Apply/Init), r (Precond), ...
+    const void* in1;    // b
+    void* io0;          // x / u
+    void* io1;          // r
+    void* io2;          // z
+    void* io3;          // p
+    void* io4;          // q
+    void* out32;        // FP32 vector of the refinement kernels
+    SolverState* st;    // per right-hand side
+    double* part;       // [batch][blocks_per_rhs][kRedSlots]
+    double scale;
+};
+
+// Host launchers (kernels.hip): T = double or float.
+template <typename T>
+hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s);
+
+// Unfused BLAS-1 style kernels with device-resident scalars (blas.hip).
+enum class Blas : int {
+    DotPQ,        // sigma = <p,q>; alpha = rho / sigma
+    DotRZ,        // rho' = <r,z>; beta = rho'/rho; rho = rho'
+    Nrm2R,        // ||r||; exit test; iteration count
+    AxpyXP,       // x += alpha p
+    AxpyRQ,       // r -= alpha q
+    ScalP,        // p = beta p
+    AxpyPZ,       // p += z
+    CopyZP,       // p = z (start)
+    InitDot,      // rho = <r,z>, ||r0|| (start)
+};
+
+struct BlasArgs {
+    int64_t n;
+    int64_t blocks;
+    const double* x;
+    const double* y;
+    double* w0;
+    double* w1;
+    SolverState* st;
+    double* part;
+};
+hipError_t launch_blas(Blas op, const BlasArgs& a, hipStream_t s);
+
+// CSR comparator (csr.hip).
+size_t csr_bytes(const Geom& g, int dtype);
+hipError_t csr_build(const Geom& g, const double* vert64, int dtype, void* buf, hipStream_t s);
+hipError_t csr_apply(const Geom& g, int dtype, const void* buf, const void* x, void* y,
+                     hipStream_t s);
+
+// Shape selection and the number of workgroups for a column kernel.
+Shape default_shape(int nz, int dtype);
+int64_t column_blocks(const Geom& g, const Shape& sh);
+bool shape_supported(int nz, const Shape& sh);
+
+// Error reporting (abi.cpp).
+void set_error(const std::string& msg);
+
+}  // namespace pcg

@@ -1,0 +1,652 @@
+// Column kernels of the line-preconditioned CG solver (gfx950).
+//
+// Work decomposition.  Vertical columns are contiguous in memory (index
+// (i*n_y + j)*n_z + k).  A column is handled by a segment of L lanes of one
+// wavefront; lane l of the segment owns the M consecutive levels
+// k = l*M .. l*M + M-1 (L*M >= n_z), so a wavefront reads 64/L whole columns
+// as one contiguous stretch of memory, each lane with wide vector loads.
+// Vertical neighbours across lane boundaries travel by cross-lane shuffles;
+// horizontal neighbours are the same M levels of the adjacent columns.
+//
+// Line solve.  The tridiagonal block of a column depends on the column only
+// through its class (how many of its four side faces are Dirichlet), so its
+// LU factors l_k, 1/D_k, phi_k are computed once per class on the host.  The
+// two substitution sweeps are first-order linear recurrences,
+//   forward   w_k = r_k - l_k w_{k-1},
+//   backward  z_k = w_k / D_k - phi_k z_{k+1},
+// which each lane runs over its own levels and the segment completes with a
+// log2(L)-step scan of affine maps across lanes -- the sub-structuring of the
+// column system into L pieces plus an L-sized interface problem (Sec. 6.1).
+// L = 1 is the sequential Thomas algorithm of Sec. 4.2.
+//
+// Reductions.  Every workgroup writes its partial sums to a fixed slot; the
+// last workgroup to finish (atomic ticket) adds the slots in a fixed order and
+// performs the scalar step of Alg. InterleavedPCG on the device, so results
+// are bitwise reproducible for a given launch shape and no host round trip is
+// needed between kernels.
+#include "device_common.h"
+
+namespace pcg {
+namespace {
+
+struct Col {
+    int64_t idx;
+    int64_t im, ip, jm, jp;  // neighbour columns, -1 across a Dirichlet face
+    int cls;                 // column class: 3 * (#Dirichlet x faces) + #Dirichlet y faces
+    double alpha_t;          // alpha_T = sum of alpha_{T,T'}, Dirichlet faces twice
+    bool ok;
+};
+
+// Per-column geometry, recomputed from (i, j) (Sec. 4.2: |T| and
+// alpha_{T,T'} are evaluated once per column).  Dirichlet faces use the
+// half-cell distance, i.e. they add 2*alpha_{T,T'} to alpha_T.
+__device__ __forceinline__ Col make_col(const Geom& g, int64_t c)
+{
+    Col o;
+    o.ok = c < g.nh;
+    const int64_t cc = o.ok ? c : 0;
+    o.idx = cc;
+    const int64_t i = cc / g.ny, j = cc - i * g.ny;
+    int cx = 0, cy = 0;
+    if (i > 0) o.im = cc - g.ny;
+    else if (g.per_x) o.im = cc + (int64_t)(g.nx - 1) * g.ny;
+    else { o.im = -1; ++cx; }
+    if (i < g.nx - 1) o.ip = cc + g.ny;
+    else if (g.per_x) o.ip = cc - (int64_t)(g.nx - 1) * g.ny;
+    else { o.ip = -1; ++cx; }
+    if (j > 0) o.jm = cc - 1;
+    else if (g.per_y) o.jm = cc + (g.ny - 1);
+    else { o.jm = -1; ++cy; }
+    if (j < g.ny - 1) o.jp = cc + 1;
+    else if (g.per_y) o.jp = cc - (g.ny - 1);
+    else { o.jp = -1; ++cy; }
+    o.cls = 3 * cx + cy;
+    o.alpha_t = (2 + cx) * g.ax + (2 + cy) * g.ay;
+    return o;
+}
+
+// Load / store the M levels k0..k0+M-1 of column `col`.  V: n_z is a
+// multiple of M and rows are 16-byte aligned, so whole chunks are valid and
+// move as 16-byte vector accesses.
+template <typename T, int M, bool V>
+__device__ __forceinline__ void ld(const T* __restrict__ v, int64_t col, bool ok, int k0,
+                                   int nz, T (&o)[M])
+{
+    if (V) {
+        if (ok && k0 < nz) {
+            const T* p = static_cast<const T*>(__builtin_assume_aligned(v + col * nz + k0, 16));
+#pragma unroll
+            for (int t = 0; t < M; ++t) o[t] = p[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < M; ++t) o[t] = T(0);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            const int k = k0 + t;
+            o[t] = (ok && k < nz) ? v[col * nz + k] : T(0);
+        }
+    }
+}
+
+template <typename T, int M, bool V>
+__device__ __forceinline__ void st(T* __restrict__ v, int64_t col, bool ok, int k0, int nz,
+                                   const T (&o)[M])
+{
+    if (V) {
+        if (ok && k0 < nz) {
+            T* p = static_cast<T*>(__builtin_assume_aligned(v + col * nz + k0, 16));
+#pragma unroll
+            for (int t = 0; t < M; ++t) p[t] = o[t];
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            const int k = k0 + t;
+            if (ok && k < nz) v[col * nz + k] = o[t];
+        }
+    }
+}
+
+// Level table row `comp` (length nzp, zero-padded), levels k0..k0+M-1.
+template <typename T, int M, bool V>
+__device__ __forceinline__ void ld_tab(const T* __restrict__ tab, int comp, int nzp, int k0,
+                                       int nz, T (&o)[M])
+{
+    const T* row = tab + (int64_t)comp * nzp;
+    if (V) {
+        if (k0 < nz) {
+            const T* p = static_cast<const T*>(__builtin_assume_aligned(row + k0, 16));
+#pragma unroll
+            for (int t = 0; t < M; ++t) o[t] = p[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < M; ++t) o[t] = T(0);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < M; ++t) o[t] = (k0 + t < nz) ? row[k0 + t] : T(0);
+    }
+}
+
+// (A x) on this lane's levels (eq. for the matrix-free product, Sec. 4.2,
+// in the unprimed form of eq. TridiagonalMatrix):
+//   y_k = |T| [ s_k x_k + b_k x_{k+1} + c_k x_{k-1} ]
+//       + d_k [ sum_{T'} alpha_{T,T'} x_{T',k} - alpha_T x_k ],   s = a - b - c.
+// xc: this lane's levels of x (zero beyond n_z); x: the whole vector for the
+// horizontal neighbours.
+template <typename T, int M, bool V>
+__device__ __forceinline__ void stencil(const Geom& g, const Col& c, int l, int L, int k0,
+                                        const T* __restrict__ x, const T (&xc)[M],
+                                        const T* __restrict__ vert, T (&y)[M])
+{
+    T below = __shfl_up(xc[M - 1], 1, L);
+    T above = __shfl_down(xc[0], 1, L);
+    if (l == 0) below = T(0);
+    if (l == L - 1) above = T(0);
+
+    T xim[M], xip[M], xjm[M], xjp[M];
+    ld<T, M, V>(x, c.im, c.ok && c.im >= 0, k0, g.nz, xim);
+    ld<T, M, V>(x, c.ip, c.ok && c.ip >= 0, k0, g.nz, xip);
+    ld<T, M, V>(x, c.jm, c.ok && c.jm >= 0, k0, g.nz, xjm);
+    ld<T, M, V>(x, c.jp, c.ok && c.jp >= 0, k0, g.nz, xjp);
+
+    T s[M], bb[M], cc[M], d[M];
+    ld_tab<T, M, V>(vert, 0, g.nzp, k0, g.nz, s);
+    ld_tab<T, M, V>(vert, 1, g.nzp, k0, g.nz, bb);
+    ld_tab<T, M, V>(vert, 2, g.nzp, k0, g.nz, cc);
+    ld_tab<T, M, V>(vert, 3, g.nzp, k0, g.nz, d);
+
+    const T area = T(g.area), ax = T(g.ax), ay = T(g.ay), at = T(c.alpha_t);
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        const T lo = t == 0 ? below : xc[t - 1];
+        const T hi = t == M - 1 ? above : xc[t + 1];
+        const T vertical = area * (s[t] * xc[t] + bb[t] * hi + cc[t] * lo);
+        const T horizontal = d[t] * (ax * (xim[t] + xip[t]) + ay * (xjm[t] + xjp[t]) - at * xc[t]);
+        y[t] = vertical + horizontal;
+    }
+}
+
+// z = M^{-1} r on one column segment (see the file comment).  r: this
+// lane's levels; on return z holds the solution on them.
+template <typename T, int M, bool V>
+__device__ __forceinline__ void line_solve(const Geom& g, const Col& c, int l, int L, int k0,
+                                           const T* __restrict__ lu, const T (&r)[M], T (&z)[M])
+{
+    const T* tab = lu + (int64_t)c.cls * 3 * g.nzp;
+    T lf[M], inv_d[M], phi[M];
+    ld_tab<T, M, V>(tab, 0, g.nzp, k0, g.nz, lf);
+    ld_tab<T, M, V>(tab, 1, g.nzp, k0, g.nz, inv_d);
+    ld_tab<T, M, V>(tab, 2, g.nzp, k0, g.nz, phi);
+
+    // forward substitution, local part: w = Q + P * w_in
+    T P = T(1), Q = T(0);
+    T pi[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        Q = r[t] - lf[t] * Q;
+        P = -lf[t] * P;
+        z[t] = Q;
+        pi[t] = P;
+    }
+    for (int d = 1; d < L; d <<= 1) {   // inclusive scan of (P, Q) across the segment
+        const T Pp = __shfl_up(P, d, L);
+        const T Qp = __shfl_up(Q, d, L);
+        if (l >= d) {
+            Q = P * Qp + Q;
+            P = P * Pp;
+        }
+    }
+    T carry = __shfl_up(Q, 1, L);
+    if (l == 0) carry = T(0);
+#pragma unroll
+    for (int t = 0; t < M; ++t) z[t] += pi[t] * carry;
+
+    // backward substitution, local part from the top of the lane's levels
+    P = T(1);
+    Q = T(0);
+#pragma unroll
+    for (int t = M - 1; t >= 0; --t) {
+        Q = z[t] * inv_d[t] - phi[t] * Q;
+        P = -phi[t] * P;
+        z[t] = Q;
+        pi[t] = P;
+    }
+    for (int d = 1; d < L; d <<= 1) {   // reverse scan across the segment
+        const T Pn = __shfl_down(P, d, L);
+        const T Qn = __shfl_down(Q, d, L);
+        if (l + d < L) {
+            Q = P * Qn + Q;
+            P = P * Pn;
+        }
+    }
+    carry = __shfl_down(Q, 1, L);
+    if (l == L - 1) carry = T(0);
+#pragma unroll
+    for (int t = 0; t < M; ++t) z[t] += pi[t] * carry;
+}
+
+// Tiles (4 waves x 64/L columns each) of this workgroup.
+__device__ __forceinline__ void block_tiles(const Geom& g, int L, int64_t blk, int64_t nblk,
+                                            int64_t& t0, int64_t& t1)
+{
+    const int64_t cols = (int64_t)(kWave / L) * (kBlock / kWave);
+    const int64_t ntiles = (g.nh + cols - 1) / cols;
+    t0 = blk * ntiles / nblk;
+    t1 = (blk + 1) * ntiles / nblk;
+}
+
+struct Lane {
+    int l, seg, wave, k0;
+};
+
+template <int M>
+__device__ __forceinline__ Lane lane_pos(int L)
+{
+    Lane o;
+    const int lane = threadIdx.x & (kWave - 1);
+    o.wave = threadIdx.x / kWave;
+    o.seg = lane / L;
+    o.l = lane - o.seg * L;
+    o.k0 = o.l * M;
+    return o;
+}
+
+__device__ __forceinline__ int64_t tile_col(int64_t tile, const Lane& p, int L)
+{
+    return (tile * (kBlock / kWave) + p.wave) * (kWave / L) + p.seg;
+}
+
+// ---------------------------------------------------------------- kernels --
+
+template <typename T, int M, bool V>
+__global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    if (a.st && a.st[rhs].flag != kRunning) return;   // inside a solve: stop when done
+    const T* x = static_cast<const T*>(a.in0) + rhs * g.n;
+    T* y = static_cast<T*>(a.io0) + rhs * g.n;
+    const T* vert = static_cast<const T*>(a.vert);
+    const Lane p = lane_pos<M>(L);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col(g, tile_col(tile, p, L));
+        T xc[M], yc[M];
+        ld<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+        stencil<T, M, V>(g, c, p.l, L, p.k0, x, xc, vert, yc);
+        st<T, M, V>(y, c.idx, c.ok, p.k0, g.nz, yc);
+    }
+}
+
+template <typename T, int M, bool V>
+__global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    if (a.st && a.st[rhs].flag != kRunning) return;
+    const T* r = static_cast<const T*>(a.in0) + rhs * g.n;
+    T* z = static_cast<T*>(a.io0) + rhs * g.n;
+    const T* lu = static_cast<const T*>(a.lu);
+    const Lane p = lane_pos<M>(L);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col(g, tile_col(tile, p, L));
+        T rc[M], zc[M];
+        ld<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+        line_solve<T, M, V>(g, c, p.l, L, p.k0, lu, rc, zc);
+        st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
+    }
+}
+
+// r = b - A x (ZERO: x = 0, r = b; nothing to copy when b is r), p = q = 0.
+template <typename T, int M, bool V, bool ZERO>
+__global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    const int64_t off = rhs * g.n;
+    T* x = static_cast<T*>(a.io0) + off;
+    const T* b = static_cast<const T*>(a.in1) + off;
+    T* r = static_cast<T*>(a.io1) + off;
+    T* pp = static_cast<T*>(a.io3) + off;
+    T* q = static_cast<T*>(a.io4) + off;
+    const T* vert = static_cast<const T*>(a.vert);
+    const bool in_place = a.in1 == a.io1;   // b already stored in r
+    const Lane p = lane_pos<M>(L);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    T zero[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) zero[i] = T(0);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col(g, tile_col(tile, p, L));
+        if (ZERO) {
+            st<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, zero);
+            if (!in_place) {
+                T bc[M];
+                ld<T, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
+                st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, bc);
+            }
+        } else {
+            T bc[M], rc[M], xc[M], ax[M];
+            ld<T, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
+            ld<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+            stencil<T, M, V>(g, c, p.l, L, p.k0, x, xc, vert, ax);
+#pragma unroll
+            for (int i = 0; i < M; ++i) rc[i] = bc[i] - ax[i];
+            st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+        }
+        st<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, zero);
+        st<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, zero);
+    }
+}
+
+// Kernel B (Alg. InterleavedPrec): r -= alpha q; z = M^{-1} r;
+// R = <r,r>, kappa = <r,z> (FP64 accumulation); last workgroup: exit test, beta.
+template <typename T, int M, bool V>
+__global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    if (s->flag != kRunning) return;
+    const int64_t off = rhs * g.n;
+    T* r = static_cast<T*>(a.io1) + off;
+    T* z = static_cast<T*>(a.io2) + off;
+    const T* q = static_cast<const T*>(a.io4) + off;
+    const T* lu = static_cast<const T*>(a.lu);
+    const T alpha = T(s->alpha);
+    const Lane p = lane_pos<M>(L);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    double acc[2] = {0.0, 0.0};
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col(g, tile_col(tile, p, L));
+        T rc[M], qc[M], zc[M];
+        ld<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+        ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            rc[i] = rc[i] - alpha * qc[i];
+            acc[0] += double(rc[i]) * double(rc[i]);
+        }
+        st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+        line_solve<T, M, V>(g, c, p.l, L, p.k0, lu, rc, zc);
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc[1] += double(rc[i]) * double(zc[i]);
+        st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
+    }
+    double tot[2];
+    if (reduce_last<2>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, tot)) {
+        if (threadIdx.x == 0) finish_prec(s, tot[0], tot[1]);
+    }
+}
+
+// Kernel A (Alg. InterleavedApply): u += alpha p; p = z + beta p;
+// q = A z + beta q; sigma = <p,q> (FP64); last workgroup: alpha.
+template <typename T, int M, bool V>
+__global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    if (s->flag != kRunning) return;
+    const int64_t off = rhs * g.n;
+    T* u = static_cast<T*>(a.io0) + off;
+    const T* z = static_cast<const T*>(a.io2) + off;
+    T* pp = static_cast<T*>(a.io3) + off;
+    T* q = static_cast<T*>(a.io4) + off;
+    const T* vert = static_cast<const T*>(a.vert);
+    const T alpha = T(s->alpha), beta = T(s->beta);
+    const Lane p = lane_pos<M>(L);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    double acc[1] = {0.0};
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col(g, tile_col(tile, p, L));
+        T zc[M], az[M], uc[M], pc[M], qc[M];
+        ld<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
+        stencil<T, M, V>(g, c, p.l, L, p.k0, z, zc, vert, az);
+        ld<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
+        ld<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
+        ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            uc[i] = uc[i] + alpha * pc[i];
+            pc[i] = zc[i] + beta * pc[i];
+            qc[i] = az[i] + beta * qc[i];
+            acc[0] += double(pc[i]) * double(qc[i]);
+        }
+        st<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
+        st<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
+        st<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+    }
+    double tot[1];
+    if (reduce_last<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, tot)) {
+        if (threadIdx.x == 0) finish_apply(s, tot[0]);
+    }
+}
+
+// Exit correction u += alpha p (the fused iteration leaves u one step
+// behind r).  Runs once: the last workgroup marks it done.
+template <typename T, int M, bool V>
+__global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    if (!(s->flag == kConverged || s->flag == kMaxIter) || s->fixed) return;
+    const int64_t off = rhs * g.n;
+    T* u = static_cast<T*>(a.io0) + off;
+    const T* pp = static_cast<const T*>(a.io3) + off;
+    const T alpha = T(s->alpha);
+    const Lane p = lane_pos<M>(L);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col(g, tile_col(tile, p, L));
+        T uc[M], pc[M];
+        ld<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
+        ld<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
+#pragma unroll
+        for (int i = 0; i < M; ++i) uc[i] += alpha * pc[i];
+        st<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
+    }
+    double acc[1] = {0.0}, tot[1];
+    if (reduce_last<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, tot)) {
+        if (threadIdx.x == 0) s->fixed = 1;
+    }
+}
+
+// FP64 true residual: ||b - A x|| into state.aux (T = double only).
+template <int M, bool V>
+__global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    const double* x = static_cast<const double*>(a.in0) + rhs * g.n;
+    const double* b = static_cast<const double*>(a.in1) + rhs * g.n;
+    const double* vert = static_cast<const double*>(a.vert);
+    const Lane p = lane_pos<M>(L);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    double acc[1] = {0.0};
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col(g, tile_col(tile, p, L));
+        double xc[M], ax[M], bc[M];
+        ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+        ld<double, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
+        stencil<double, M, V>(g, c, p.l, L, p.k0, x, xc, vert, ax);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const double d = bc[i] - ax[i];
+            acc[0] += d * d;
+        }
+    }
+    double tot[1];
+    if (reduce_last<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, tot)) {
+        if (threadIdx.x == 0) s->aux = sqrt(tot[0]);
+    }
+}
+
+// Refinement residual: r64 = b - A x in FP64, ||r64|| into state.rnorm
+// (state.r0norm on the first call), FP32 copy r32 = r64 * scale.
+template <int M, bool V>
+__global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    if (s->flag != kRunning) return;
+    const double* x = static_cast<const double*>(a.in0) + rhs * g.n;
+    const double* b = static_cast<const double*>(a.in1) + rhs * g.n;
+    float* r32 = static_cast<float*>(a.out32) + rhs * g.n;
+    const double* vert = static_cast<const double*>(a.vert);
+    const double scale = s->aux;
+    const Lane p = lane_pos<M>(L);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    double acc[1] = {0.0};
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col(g, tile_col(tile, p, L));
+        double xc[M], ax[M], bc[M];
+        float rc[M];
+        ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+        ld<double, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
+        stencil<double, M, V>(g, c, p.l, L, p.k0, x, xc, vert, ax);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const double d = bc[i] - ax[i];
+            acc[0] += d * d;
+            rc[i] = float(d * scale);
+        }
+        // FP32 rows are 16-byte aligned only when M*4 is a multiple of 16
+        st<float, M, (V && (M % 4 == 0))>(r32, c.idx, c.ok, p.k0, g.nz, rc);
+    }
+    double tot[1];
+    if (reduce_last<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, tot)) {
+        if (threadIdx.x == 0) {
+            const double rn = sqrt(tot[0]);
+            s->rnorm = rn;
+            if (s->iter == 0) s->r0norm = rn;
+        }
+    }
+}
+
+// Refinement update: x64 += (1/scale) * u32, u32 being the inner solution.
+template <int M, bool V>
+__global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    if (s->flag != kRunning) return;
+    double* x = static_cast<double*>(a.io0) + rhs * g.n;
+    const float* u32 = static_cast<const float*>(a.out32) + rhs * g.n;
+    const double inv_scale = 1.0 / s->aux;
+    const Lane p = lane_pos<M>(L);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col(g, tile_col(tile, p, L));
+        double xc[M];
+        float uc[M];
+        ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+        ld<float, M, (V && (M % 4 == 0))>(u32, c.idx, c.ok, p.k0, g.nz, uc);
+#pragma unroll
+        for (int i = 0; i < M; ++i) xc[i] += inv_scale * double(uc[i]);
+        st<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+    }
+}
+
+// ---------------------------------------------------------------- dispatch --
+
+template <typename T, int M, bool V>
+hipError_t launch_m(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+{
+    const dim3 grid((unsigned)(a.blocks_per_rhs * batch)), block(kBlock);
+    switch (kind) {
+    case Kind::Apply: hipLaunchKernelGGL((k_apply<T, M, V>), grid, block, 0, s, a); break;
+    case Kind::Precond: hipLaunchKernelGGL((k_precond<T, M, V>), grid, block, 0, s, a); break;
+    case Kind::InitFull: hipLaunchKernelGGL((k_init<T, M, V, false>), grid, block, 0, s, a); break;
+    case Kind::InitZero: hipLaunchKernelGGL((k_init<T, M, V, true>), grid, block, 0, s, a); break;
+    case Kind::FusedPrec: hipLaunchKernelGGL((k_fused_prec<T, M, V>), grid, block, 0, s, a); break;
+    case Kind::FusedApply: hipLaunchKernelGGL((k_fused_apply<T, M, V>), grid, block, 0, s, a); break;
+    case Kind::Fixup: hipLaunchKernelGGL((k_fixup<T, M, V>), grid, block, 0, s, a); break;
+    case Kind::TrueResidual:
+        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((k_true_residual<M, V>), grid, block, 0, s, a);
+        else return hipErrorInvalidValue;
+        break;
+    case Kind::Residual64:
+        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((k_residual64<M, V>), grid, block, 0, s, a);
+        else return hipErrorInvalidValue;
+        break;
+    case Kind::Update64:
+        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((k_update64<M, V>), grid, block, 0, s, a);
+        else return hipErrorInvalidValue;
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int M>
+hipError_t launch_v(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+{
+    // vector path: whole chunks valid and 16-byte aligned rows and chunks
+    const bool vec = (a.g.nz % M == 0) && ((M * sizeof(T)) % 16 == 0) &&
+                     ((a.g.nz * sizeof(T)) % 16 == 0);
+    if (vec) return launch_m<T, M, true>(kind, a, batch, s);
+    return launch_m<T, M, false>(kind, a, batch, s);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+{
+    const int M = a.L > 0 ? (a.g.nz + a.L - 1) / a.L : 0;
+    int Mp = 1;
+    while (Mp < M) Mp <<= 1;
+    switch (Mp) {
+    case 1: return launch_v<T, 1>(kind, a, batch, s);
+    case 2: return launch_v<T, 2>(kind, a, batch, s);
+    case 4: return launch_v<T, 4>(kind, a, batch, s);
+    case 8: return launch_v<T, 8>(kind, a, batch, s);
+    case 16: return launch_v<T, 16>(kind, a, batch, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_column<double>(Kind, const ColArgs&, int64_t, hipStream_t);
+template hipError_t launch_column<float>(Kind, const ColArgs&, int64_t, hipStream_t);
+
+}  // namespace pcg

@@ -1,0 +1,631 @@
+// Solve drivers of libpcg.
+//
+// Fused iteration (Alg. InterleavedPCG): after the start-up kernels the host
+// issues chunks of K iterations -- K x (kernel A, kernel B) and one exit
+// correction -- and reads the device flags once per chunk.  Every kernel
+// returns at once when the flag of its right-hand side is set, so a chunk
+// that overshoots the exit costs only empty launches.  With an adaptive
+// chunk (K = the previous solve's iteration count) a repeated solve issues
+// exactly the launches it needs.  Chunks are captured once as HIP graphs
+// and replayed.
+//
+// Mixed precision: FP64 residual r = b - A x (scaled to FP32), an FP32 inner
+// solve of A d = r to a relative tolerance, FP64 update x += d / scale,
+// repeated until the FP64 residual meets the tolerance.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+#include "problem.h"
+
+namespace pcg {
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int64_t blas_blocks(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>(2048, (n / 2 + kBlock - 1) / kBlock)); }
+
+int64_t blocks_per_rhs(const pcg_problem* P, int dtype)
+{
+    return std::max<int64_t>(1, std::min(P->block_cap, column_blocks(P->geom, P->shape[dtype])));
+}
+
+struct Layout {
+    size_t r = 0, z = 0, p = 0, q = 0;           // FP64 vectors
+    size_t r32 = 0, z32 = 0, p32 = 0, q32 = 0, u32 = 0;
+    size_t part = 0, st = 0, st_o = 0;
+    size_t total = 0;
+};
+
+Layout plan(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
+{
+    Layout w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += al256(bytes);
+        return at;
+    };
+    const size_t n = (size_t)P->geom.n * (size_t)nrhs;
+    if (o.precision == PCG_PREC_MIXED) {
+        w.r32 = take(4 * n);
+        w.z32 = take(4 * n);
+        w.p32 = take(4 * n);
+        w.q32 = take(4 * n);
+        w.u32 = take(4 * n);
+    } else {
+        w.r = take(8 * n);
+        w.z = take(8 * n);
+        w.p = take(8 * n);
+        w.q = take(8 * n);
+    }
+    const int64_t nb = std::max({blocks_per_rhs(P, PCG_F64), blocks_per_rhs(P, PCG_F32),
+                                 blas_blocks(P->geom.n)});
+    w.part = take((size_t)nrhs * nb * kRedSlots * sizeof(double));
+    w.st = take((size_t)nrhs * sizeof(SolverState));
+    w.st_o = take((size_t)nrhs * sizeof(SolverState));
+    w.total = off;
+    return w;
+}
+
+std::string hip_msg(hipError_t e, const char* what)
+{
+    std::ostringstream m;
+    m << what << ": " << hipGetErrorName(e) << " (" << hipGetErrorString(e) << ")";
+    return m.str();
+}
+
+#define PCG_HIP(call, what)                                       \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) {                                   \
+            set_error(hip_msg(e_, what));                         \
+            return PCG_E_DEVICE;                                  \
+        }                                                         \
+    } while (0)
+
+pcg_status ensure_pinned(pcg_problem* P, int64_t nrhs)
+{
+    if (P->pinned_cap >= nrhs) return PCG_OK;
+    if (P->pinned_states) (void)hipHostFree(P->pinned_states);
+    P->pinned_states = nullptr;
+    P->pinned_cap = 0;
+    PCG_HIP(hipHostMalloc((void**)&P->pinned_states, sizeof(SolverState) * (size_t)nrhs, 0),
+            "hipHostMalloc(solver states)");
+    P->pinned_cap = nrhs;
+    return PCG_OK;
+}
+
+SolverState fresh_state(double rtol, double atol, int max_iter, double aux)
+{
+    SolverState s;
+    std::memset(&s, 0, sizeof(s));
+    s.alpha = 0.0;
+    s.beta = 0.0;
+    s.kappa_old = 1.0;
+    s.rtol = rtol;
+    s.atol = atol;
+    s.max_iter = max_iter;
+    s.aux = aux;
+    s.flag = kRunning;
+    return s;
+}
+
+pcg_status upload_states(pcg_problem* P, SolverState* dev, const SolverState* host, int64_t nrhs,
+                         hipStream_t s)
+{
+    if (ensure_pinned(P, nrhs) != PCG_OK) return PCG_E_DEVICE;
+    // the pinned staging buffer is also the read-back target: wait for any
+    // copy still in flight on this stream before overwriting it
+    PCG_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    std::memcpy(P->pinned_states, host, sizeof(SolverState) * (size_t)nrhs);
+    PCG_HIP(hipMemcpyAsync(dev, P->pinned_states, sizeof(SolverState) * (size_t)nrhs,
+                           hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync(states H2D)");
+    PCG_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return PCG_OK;
+}
+
+pcg_status read_states(pcg_problem* P, const SolverState* dev, SolverState* host, int64_t nrhs,
+                       hipStream_t s)
+{
+    if (ensure_pinned(P, nrhs) != PCG_OK) return PCG_E_DEVICE;
+    PCG_HIP(hipMemcpyAsync(P->pinned_states, dev, sizeof(SolverState) * (size_t)nrhs,
+                           hipMemcpyDeviceToHost, s),
+            "hipMemcpyAsync(states D2H)");
+    PCG_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    std::memcpy(host, P->pinned_states, sizeof(SolverState) * (size_t)nrhs);
+    return PCG_OK;
+}
+
+pcg_status ensure_events(pcg_problem* P, size_t count)
+{
+    while (P->events.size() < count) {
+        hipEvent_t e;
+        PCG_HIP(hipEventCreate(&e), "hipEventCreate");
+        P->events.push_back(e);
+    }
+    return PCG_OK;
+}
+
+template <typename T>
+pcg_status launch(Kind k, const ColArgs& a, int64_t nrhs, hipStream_t s, int& count)
+{
+    hipError_t e = launch_column<T>(k, a, nrhs, s);
+    if (e != hipSuccess) {
+        set_error(hip_msg(e, "kernel launch"));
+        return PCG_E_DEVICE;
+    }
+    ++count;
+    return PCG_OK;
+}
+
+// One chunk of the fused iteration: K x (A, B) and the exit correction.
+template <typename T>
+pcg_status issue_chunk(const ColArgs& a, int64_t nrhs, int K, hipStream_t s, int& count)
+{
+    for (int i = 0; i < K; ++i) {
+        if (launch<T>(Kind::FusedApply, a, nrhs, s, count) != PCG_OK) return PCG_E_DEVICE;
+        if (launch<T>(Kind::FusedPrec, a, nrhs, s, count) != PCG_OK) return PCG_E_DEVICE;
+    }
+    return launch<T>(Kind::Fixup, a, nrhs, s, count);
+}
+
+template <typename T>
+pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, int64_t nrhs, int K,
+                       hipGraphExec_t* out)
+{
+    GraphKey key{};
+    key.dtype = dtype;
+    key.kind = 0;
+    key.iters = K;
+    key.nrhs = nrhs;
+    const void* ptrs[8] = {a.io0, a.io1, a.io2, a.io3, a.io4, a.st, a.part, a.lu};
+    std::memcpy(key.ptrs, ptrs, sizeof(ptrs));
+    auto it = P->graphs.find(key);
+    if (it != P->graphs.end()) {
+        *out = it->second;
+        return PCG_OK;
+    }
+    if (!P->capture_stream)
+        PCG_HIP(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking),
+                "hipStreamCreateWithFlags");
+    PCG_HIP(hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeThreadLocal),
+            "hipStreamBeginCapture");
+    int dummy = 0;
+    pcg_status st = issue_chunk<T>(a, nrhs, K, P->capture_stream, dummy);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(P->capture_stream, &graph);
+    if (st != PCG_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    PCG_HIP(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    PCG_HIP(e, "hipGraphInstantiate");
+    P->graphs[key] = exec;
+    *out = exec;
+    return PCG_OK;
+}
+
+struct RunInfo {
+    int launches = 0;
+    double ms_a = 0.0, ms_b = 0.0;
+    int n_a = 0, n_b = 0;
+};
+
+// Fused Krylov engine for nrhs right-hand sides of precision T.  The states
+// at a.st must hold fresh_state() values; `zero_start` selects x0 = 0.
+template <typename T>
+pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a, int64_t nrhs,
+                     bool zero_start, const pcg_solve_opts& o, SolverState* host_states,
+                     RunInfo& info, hipStream_t s)
+{
+    const bool profile = o.profile != 0 && nrhs == 1;
+    int K = o.graph_chunk > 0 ? o.graph_chunk : P->last_iters[prec_slot];
+    if (K <= 0) K = 8;
+    K = std::min(K, std::max(1, o.max_iter));
+    const bool use_graph = o.graph_chunk != 0 && !profile;
+
+    if (launch<T>(zero_start ? Kind::InitZero : Kind::InitFull, a, nrhs, s, info.launches))
+        return PCG_E_DEVICE;
+
+    // profile: launch i of kind is_a[i] is bracketed by events 2i and 2i+1
+    std::vector<char> is_a;
+    auto timed = [&](Kind k, char kind_a) -> pcg_status {
+        const size_t i = is_a.size();
+        if (ensure_events(P, 2 * i + 2) != PCG_OK) return PCG_E_DEVICE;
+        PCG_HIP(hipEventRecord(P->events[2 * i], s), "hipEventRecord");
+        if (launch<T>(k, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
+        PCG_HIP(hipEventRecord(P->events[2 * i + 1], s), "hipEventRecord");
+        is_a.push_back(kind_a);
+        return PCG_OK;
+    };
+    if (profile) {
+        if (timed(Kind::FusedPrec, 0) != PCG_OK) return PCG_E_DEVICE;
+    } else if (launch<T>(Kind::FusedPrec, a, nrhs, s, info.launches)) {
+        return PCG_E_DEVICE;
+    }
+
+    const int max_chunks = o.max_iter / K + 3;
+    int chunks = 0;
+    for (;;) {
+        if (profile) {
+            for (int i = 0; i < K; ++i) {
+                if (timed(Kind::FusedApply, 1) != PCG_OK) return PCG_E_DEVICE;
+                if (timed(Kind::FusedPrec, 0) != PCG_OK) return PCG_E_DEVICE;
+            }
+            if (launch<T>(Kind::Fixup, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
+        } else if (use_graph) {
+            hipGraphExec_t exec;
+            if (chunk_graph<T>(P, dtype, a, nrhs, K, &exec) != PCG_OK) return PCG_E_DEVICE;
+            PCG_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
+            info.launches += 2 * K + 1;
+        } else {
+            if (issue_chunk<T>(a, nrhs, K, s, info.launches)) return PCG_E_DEVICE;
+        }
+        ++chunks;
+        if (read_states(P, a.st, host_states, nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+        bool running = false;
+        for (int64_t i = 0; i < nrhs; ++i) running |= host_states[i].flag == kRunning;
+        if (!running) break;
+        if (chunks >= max_chunks) {
+            set_error("iteration chunks exceeded the iteration limit (internal)");
+            return PCG_E_DEVICE;
+        }
+    }
+    if (profile) {
+        // kernel i spans events[i] .. events[i+1]; count the launches that did work
+        const int done_a = host_states[0].iter;
+        int na = 0, nb = 0;
+        for (size_t i = 0; i < is_a.size(); ++i) {
+            float ms = 0.f;
+            PCG_HIP(hipEventElapsedTime(&ms, P->events[2 * i], P->events[2 * i + 1]),
+                    "hipEventElapsedTime");
+            if (is_a[i] && na < done_a) {
+                info.ms_a += ms;
+                ++na;
+            } else if (!is_a[i] && nb < done_a + 1) {
+                info.ms_b += ms;
+                ++nb;
+            }
+        }
+        info.n_a = na;
+        info.n_b = nb;
+    }
+    int maxit = 0;
+    for (int64_t i = 0; i < nrhs; ++i) maxit = std::max(maxit, host_states[i].iter);
+    if (maxit > 0) P->last_iters[prec_slot] = maxit;
+    return PCG_OK;
+}
+
+pcg_status status_of(const SolverState& s)
+{
+    switch (s.flag) {
+    case kConverged: return PCG_OK;
+    case kMaxIter: return PCG_E_NOCONV;
+    case kBreakdown: return PCG_E_BREAKDOWN;
+    default: return PCG_E_NOCONV;
+    }
+}
+
+ColArgs base_args(const pcg_problem* P, int dtype, char* ws, const Layout& w, int64_t bpr)
+{
+    ColArgs a{};
+    a.g = P->geom;
+    a.L = P->shape[dtype].L;
+    a.blocks_per_rhs = bpr;
+    a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
+    a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
+    a.part = reinterpret_cast<double*>(ws + w.part);
+    return a;
+}
+
+// ------------------------------------------------------------- FP64 fused --
+
+pcg_status solve_fp64(pcg_problem* P, const double* b, double* x, char* ws, const Layout& w,
+                      int64_t nrhs, const pcg_solve_opts& o, pcg_result* res, hipStream_t s)
+{
+    const int64_t bpr = blocks_per_rhs(P, PCG_F64);
+    ColArgs a = base_args(P, PCG_F64, ws, w, bpr);
+    a.in0 = x;
+    a.in1 = b;
+    a.io0 = x;
+    a.io1 = ws + w.r;
+    a.io2 = ws + w.z;
+    a.io3 = ws + w.p;
+    a.io4 = ws + w.q;
+    a.st = reinterpret_cast<SolverState*>(ws + w.st);
+    std::vector<SolverState> hs(nrhs, fresh_state(o.rtol, o.atol, o.max_iter, 1.0));
+    if (upload_states(P, a.st, hs.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+    RunInfo info;
+    pcg_status st = run_fused<double>(P, PCG_F64, 0, a, nrhs, false, o, hs.data(), info, s);
+    if (st != PCG_OK) return st;
+    if (o.true_residual) {
+        ColArgs t = a;
+        t.in0 = x;
+        t.in1 = b;
+        if (launch<double>(Kind::TrueResidual, t, nrhs, s, info.launches)) return PCG_E_DEVICE;
+        if (read_states(P, a.st, hs.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+    }
+    for (int64_t i = 0; i < nrhs; ++i) {
+        pcg_result& r = res[i];
+        r.status = status_of(hs[i]);
+        r.iterations = hs[i].iter;
+        r.outer_iterations = 0;
+        r.launches = info.launches;
+        r.r0_norm = hs[i].r0norm;
+        r.rel_res_recursive = hs[i].r0norm > 0 ? hs[i].rnorm / hs[i].r0norm : 0.0;
+        r.rel_res_true = o.true_residual ? (hs[i].r0norm > 0 ? hs[i].aux / hs[i].r0norm : 0.0) : -1.0;
+        r.ms_apply_kernel = info.ms_a;
+        r.ms_precond_kernel = info.ms_b;
+        r.n_apply_kernel = info.n_a;
+        r.n_precond_kernel = info.n_b;
+    }
+    return PCG_OK;
+}
+
+// ----------------------------------------------------------- FP64 unfused --
+
+pcg_status solve_unfused(pcg_problem* P, const double* b, double* x, char* ws, const Layout& w,
+                         const pcg_solve_opts& o, pcg_result* res, hipStream_t s)
+{
+    const int64_t bpr = blocks_per_rhs(P, PCG_F64);
+    ColArgs a = base_args(P, PCG_F64, ws, w, bpr);
+    SolverState* dst = reinterpret_cast<SolverState*>(ws + w.st);
+    double* r = reinterpret_cast<double*>(ws + w.r);
+    double* z = reinterpret_cast<double*>(ws + w.z);
+    double* p = reinterpret_cast<double*>(ws + w.p);
+    double* q = reinterpret_cast<double*>(ws + w.q);
+    SolverState hs = fresh_state(o.rtol, o.atol, o.max_iter, 1.0);
+    if (upload_states(P, dst, &hs, 1, s) != PCG_OK) return PCG_E_DEVICE;
+    int launches = 0;
+    BlasArgs ba{};
+    ba.n = P->geom.n;
+    ba.blocks = blas_blocks(P->geom.n);
+    ba.st = dst;
+    ba.part = a.part;
+    auto blas = [&](Blas op, const double* xx, const double* yy, double* w0) -> pcg_status {
+        BlasArgs c = ba;
+        c.x = xx;
+        c.y = yy;
+        c.w0 = w0;
+        hipError_t e = launch_blas(op, c, s);
+        if (e != hipSuccess) {
+            set_error(hip_msg(e, "blas launch"));
+            return PCG_E_DEVICE;
+        }
+        ++launches;
+        return PCG_OK;
+    };
+    // start: r = b - A x, z = M^{-1} r, rho = <r,z>, p = z
+    ColArgs init = a;
+    init.in1 = b;
+    init.io0 = x;
+    init.io1 = r;
+    init.io3 = p;
+    init.io4 = q;
+    init.st = dst;
+    if (launch<double>(Kind::InitFull, init, 1, s, launches)) return PCG_E_DEVICE;
+    ColArgs pre = a;
+    pre.in0 = r;
+    pre.io0 = z;
+    pre.st = dst;
+    ColArgs app = a;
+    app.in0 = p;
+    app.io0 = q;
+    app.st = dst;
+    if (launch<double>(Kind::Precond, pre, 1, s, launches)) return PCG_E_DEVICE;
+    if (blas(Blas::InitDot, r, z, nullptr)) return PCG_E_DEVICE;
+    if (blas(Blas::CopyZP, z, nullptr, p)) return PCG_E_DEVICE;
+    int K = o.graph_chunk > 0 ? o.graph_chunk : (P->last_iters[0] > 0 ? P->last_iters[0] : 8);
+    K = std::min(K, std::max(1, o.max_iter));
+    const int max_chunks = o.max_iter / K + 3;
+    for (int chunk = 0;; ++chunk) {
+        for (int i = 0; i < K; ++i) {
+            if (launch<double>(Kind::Apply, app, 1, s, launches)) return PCG_E_DEVICE;  // q = A p
+            if (blas(Blas::DotPQ, p, q, nullptr)) return PCG_E_DEVICE;                  // alpha
+            if (blas(Blas::AxpyXP, p, nullptr, x)) return PCG_E_DEVICE;                 // x += alpha p
+            if (blas(Blas::AxpyRQ, q, nullptr, r)) return PCG_E_DEVICE;                 // r -= alpha q
+            if (blas(Blas::Nrm2R, r, nullptr, nullptr)) return PCG_E_DEVICE;            // ||r||, exit
+            if (launch<double>(Kind::Precond, pre, 1, s, launches)) return PCG_E_DEVICE; // z = M^-1 r
+            if (blas(Blas::DotRZ, r, z, nullptr)) return PCG_E_DEVICE;                  // beta
+            if (blas(Blas::ScalP, nullptr, nullptr, p)) return PCG_E_DEVICE;            // p = beta p
+            if (blas(Blas::AxpyPZ, z, nullptr, p)) return PCG_E_DEVICE;                 // p += z
+        }
+        if (read_states(P, dst, &hs, 1, s) != PCG_OK) return PCG_E_DEVICE;
+        if (hs.flag != kRunning) break;
+        if (chunk + 1 >= max_chunks) {
+            set_error("iteration chunks exceeded the iteration limit (internal)");
+            return PCG_E_DEVICE;
+        }
+    }
+    if (hs.iter > 0) P->last_iters[0] = hs.iter;
+    if (o.true_residual) {
+        ColArgs t = a;
+        t.in0 = x;
+        t.in1 = b;
+        t.st = dst;
+        if (launch<double>(Kind::TrueResidual, t, 1, s, launches)) return PCG_E_DEVICE;
+        if (read_states(P, dst, &hs, 1, s) != PCG_OK) return PCG_E_DEVICE;
+    }
+    res->status = status_of(hs);
+    res->iterations = hs.iter;
+    res->outer_iterations = 0;
+    res->launches = launches;
+    res->r0_norm = hs.r0norm;
+    res->rel_res_recursive = hs.r0norm > 0 ? hs.rnorm / hs.r0norm : 0.0;
+    res->rel_res_true = o.true_residual ? (hs.r0norm > 0 ? hs.aux / hs.r0norm : 0.0) : -1.0;
+    return PCG_OK;
+}
+
+// -------------------------------------------------------- mixed precision --
+
+pcg_status solve_mixed(pcg_problem* P, const double* b, double* x, char* ws, const Layout& w,
+                       int64_t nrhs, const pcg_solve_opts& o, pcg_result* res, hipStream_t s)
+{
+    const int64_t bpr64 = blocks_per_rhs(P, PCG_F64);
+    const int64_t bpr32 = blocks_per_rhs(P, PCG_F32);
+    SolverState* st_in = reinterpret_cast<SolverState*>(ws + w.st);
+    SolverState* st_out = reinterpret_cast<SolverState*>(ws + w.st_o);
+
+    ColArgs outer = base_args(P, PCG_F64, ws, w, bpr64);
+    outer.in0 = x;
+    outer.in1 = b;
+    outer.io0 = x;
+    outer.out32 = ws + w.r32;   // Residual64 writes the inner right-hand side
+    outer.st = st_out;
+
+    ColArgs inner = base_args(P, PCG_F32, ws, w, bpr32);
+    inner.in1 = ws + w.r32;     // b of the inner solve is r32 itself (no copy)
+    inner.io0 = ws + w.u32;
+    inner.io1 = ws + w.r32;
+    inner.io2 = ws + w.z32;
+    inner.io3 = ws + w.p32;
+    inner.io4 = ws + w.q32;
+    inner.st = st_in;
+
+    ColArgs upd = outer;
+    upd.out32 = ws + w.u32;     // Update64 reads the inner solution
+
+    std::vector<SolverState> ho(nrhs), hi(nrhs);
+    std::vector<double> r0(nrhs, 0.0), rn(nrhs, 0.0), scale(nrhs, 1.0);
+    std::vector<char> done(nrhs, 0);
+    std::vector<int> inner_iters(nrhs, 0), outer_steps(nrhs, 0);
+    std::vector<pcg_status> stat(nrhs, PCG_E_NOCONV);
+    RunInfo info;
+    int launches = 0;
+
+    for (int k = 0;; ++k) {
+        for (int64_t i = 0; i < nrhs; ++i) {
+            ho[i] = fresh_state(o.rtol, o.atol, 0, scale[i]);
+            ho[i].flag = done[i] ? kConverged : kRunning;
+        }
+        if (upload_states(P, st_out, ho.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+        if (launch<double>(Kind::Residual64, outer, nrhs, s, launches)) return PCG_E_DEVICE;
+        if (read_states(P, st_out, ho.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+        bool all_done = true;
+        for (int64_t i = 0; i < nrhs; ++i) {
+            if (done[i]) continue;
+            rn[i] = ho[i].rnorm;
+            if (k == 0) r0[i] = rn[i];
+            if (!std::isfinite(rn[i])) {
+                done[i] = 1;
+                stat[i] = PCG_E_BREAKDOWN;
+            } else if (r0[i] == 0.0 || rn[i] / r0[i] < o.rtol || rn[i] < o.atol) {
+                done[i] = 1;
+                stat[i] = PCG_OK;
+            } else if (k >= o.max_outer || inner_iters[i] >= o.max_iter) {
+                done[i] = 1;
+                stat[i] = PCG_E_NOCONV;
+            }
+            all_done &= done[i] != 0;
+        }
+        if (all_done) break;
+        // first step: rescale if the residual left the comfortable FP32 range
+        if (k == 0) {
+            bool redo = false;
+            for (int64_t i = 0; i < nrhs; ++i)
+                if (!done[i] && (rn[i] > 1e20 || rn[i] < 1e-20)) {
+                    scale[i] = 1.0 / rn[i];
+                    redo = true;
+                }
+            if (redo) {
+                for (int64_t i = 0; i < nrhs; ++i) {
+                    ho[i] = fresh_state(o.rtol, o.atol, 0, scale[i]);
+                    ho[i].flag = done[i] ? kConverged : kRunning;
+                }
+                if (upload_states(P, st_out, ho.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+                if (launch<double>(Kind::Residual64, outer, nrhs, s, launches)) return PCG_E_DEVICE;
+            }
+        }
+        // inner FP32 solve A d = r32 to inner_rtol
+        for (int64_t i = 0; i < nrhs; ++i) {
+            const int budget = std::max(1, o.max_iter - inner_iters[i]);
+            hi[i] = fresh_state(o.inner_rtol, 0.0, budget, 1.0);
+            hi[i].flag = done[i] ? kConverged : kRunning;
+        }
+        if (upload_states(P, st_in, hi.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+        pcg_solve_opts io = o;
+        io.max_iter = 1 << 30;
+        io.profile = 0;
+        pcg_status st = run_fused<float>(P, PCG_F32, 1, inner, nrhs, true, io, hi.data(), info, s);
+        if (st != PCG_OK) return st;
+        // x += d / scale
+        for (int64_t i = 0; i < nrhs; ++i) {
+            ho[i] = fresh_state(o.rtol, o.atol, 0, scale[i]);
+            ho[i].flag = done[i] ? kConverged : kRunning;
+        }
+        if (upload_states(P, st_out, ho.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+        if (launch<double>(Kind::Update64, upd, nrhs, s, launches)) return PCG_E_DEVICE;
+        for (int64_t i = 0; i < nrhs; ++i) {
+            if (done[i]) continue;
+            inner_iters[i] += hi[i].iter;
+            outer_steps[i] += 1;
+            if (hi[i].flag == kBreakdown && hi[i].iter == 0) {
+                done[i] = 1;
+                stat[i] = PCG_E_BREAKDOWN;
+                continue;
+            }
+            // next residual is about ||r|| * (inner reduction); keep r32 near unit size
+            const double red = hi[i].r0norm > 0 ? hi[i].rnorm / hi[i].r0norm : 1.0;
+            const double est = rn[i] * std::max(red, 1e-30);
+            if (std::isfinite(est) && est > 0) scale[i] = 1.0 / est;
+        }
+    }
+    for (int64_t i = 0; i < nrhs; ++i) {
+        pcg_result& r = res[i];
+        r.status = stat[i];
+        r.iterations = inner_iters[i];
+        r.outer_iterations = outer_steps[i];
+        r.launches = launches + info.launches;
+        r.r0_norm = r0[i];
+        r.rel_res_recursive = r0[i] > 0 ? rn[i] / r0[i] : 0.0;
+        r.rel_res_true = r.rel_res_recursive;   // the outer residual is the true FP64 one
+        r.ms_apply_kernel = r.ms_precond_kernel = 0.0;
+        r.n_apply_kernel = r.n_precond_kernel = 0;
+    }
+    return PCG_OK;
+}
+
+}  // namespace
+
+size_t workspace_bytes(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
+{
+    return plan(P, o, nrhs).total;
+}
+
+pcg_status solve(pcg_problem* P, const double* b, double* x, void* workspace, size_t ws_bytes,
+                 const pcg_solve_opts& o, int64_t nrhs, pcg_result* res, hipStream_t s)
+{
+    const Layout w = plan(P, o, nrhs);
+    if (ws_bytes < w.total) {
+        std::ostringstream m;
+        m << "workspace of " << ws_bytes << " bytes is smaller than the " << w.total << " needed";
+        set_error(m.str());
+        return PCG_E_NOMEM;
+    }
+    char* ws = static_cast<char*>(workspace);
+    const auto t0 = std::chrono::steady_clock::now();
+    pcg_status st;
+    if (o.precision == PCG_PREC_MIXED) st = solve_mixed(P, b, x, ws, w, nrhs, o, res, s);
+    else if (o.fused) st = solve_fp64(P, b, x, ws, w, nrhs, o, res, s);
+    else st = solve_unfused(P, b, x, ws, w, o, res, s);
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (st != PCG_OK) return st;
+    pcg_status worst = PCG_OK;
+    for (int64_t i = 0; i < nrhs; ++i) {
+        res[i].elapsed_ms = ms;
+        if (res[i].status == PCG_E_BREAKDOWN) worst = PCG_E_BREAKDOWN;
+        else if (res[i].status == PCG_E_NOCONV && worst == PCG_OK) worst = PCG_E_NOCONV;
+    }
+    return worst;
+}
+
+}  // namespace pcg

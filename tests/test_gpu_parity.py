@@ -1,0 +1,330 @@
+"""GPU parity of libpcg against the CPU oracle, through the C ABI.
+
+Tolerances (FP64 unit roundoff u = 1.1e-16, FP32 u = 6.0e-8):
+* operator: elementwise |y_gpu - y_ref| <= 64 u (|A||x|)_i -- a 7-term sum
+  evaluated in a different order from coefficients computed by a different
+  formula (each a few roundings away from the oracle's);
+* line preconditioner: backward error ||M z - r|| / (||M|| ||z||) <= 64 u,
+  which does not depend on the conditioning of the column blocks, plus a
+  loose forward check;
+* solves: at an equal number of iterations the FP64 iterates agree to 1e-10
+  relative (rounding differences amplified by a handful of iterations);
+  mixed precision must reach an FP64 true residual < 1e-8, computed by the
+  oracle's own assembled matrix.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1302_7193_amd as pcg  # noqa: E402
+import synth_inputs as si  # noqa: E402
+
+U64, U32 = 2.0**-53, 2.0**-24
+
+
+def make_desc(nx, ny, nz, g2=1e3, q=1.05, bcx=0, bcy=0, kh=1.0, dx=None, dy=None):
+    d = pcg.pcg_desc_from_ratio(nx, ny, nz, q, g2, 0)
+    d.bc_x, d.bc_y = bcx, bcy
+    if dx is not None:
+        d.dx = dx
+    if dy is not None:
+        d.dy = dy
+    d.k_h = kh
+    return d
+
+
+def grid_of(d):
+    return oracle.Grid(d.nx, d.ny, d.nz, d.dx, d.dy, d.height, d.grading, d.k_h, d.k_v,
+                       d.bc_x == 1, d.bc_y == 1)
+
+
+GRIDS = {
+    "64x64x32-dir": lambda: make_desc(64, 64, 32, 1e4),
+    "13x7x33-dir-ragged": lambda: make_desc(13, 7, 33, 1e3),
+    "9x5x17-per": lambda: make_desc(9, 5, 17, 1e5, bcx=1, bcy=1),
+    "6x11x100-mixedbc": lambda: make_desc(6, 11, 100, 1e2, q=1.1, bcx=1, bcy=0, dx=0.3, dy=0.2),
+    "5x4x1-single-level": lambda: make_desc(5, 4, 1, 1e3),
+    "1x1x40-single-column": lambda: make_desc(1, 1, 40, 1e4),
+    "1x9x8-one-row": lambda: make_desc(1, 9, 8, 1e3),
+    "7x6x1024-tall": lambda: make_desc(7, 6, 1024, 1e4),
+    "3x3x7-per-min": lambda: make_desc(3, 3, 7, 1e3, bcx=1, bcy=1),
+}
+DT = {pcg.PCG_F64: (torch.float64, U64), pcg.PCG_F32: (torch.float32, U32)}
+
+
+def cuda(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+@pytest.mark.parametrize("name", list(GRIDS))
+@pytest.mark.parametrize("dtype", [pcg.PCG_F64, pcg.PCG_F32])
+def test_apply_matches_assembled_operator(name, dtype):
+    d = GRIDS[name]()
+    print("apply", name, dtype, flush=True)
+    p = pcg.Problem(d)
+    tdt, u = DT[dtype]
+    x = si.uniform_pm1(11, p.n)
+    xt = cuda(x, tdt)
+    y = torch.full_like(xt, float("nan"))
+    pcg.pcg_apply(p, dtype, xt, y)
+    torch.cuda.synchronize()
+    A = oracle.assemble(grid_of(d))
+    xr = xt.double().cpu().numpy()           # the input the GPU actually saw
+    ref = A.matvec(xr)
+    absA = oracle.CSR(A.n, A.row_ptr, A.col, np.abs(A.val))
+    bound = 64 * u * absA.matvec(np.abs(xr)) + 1e-300
+    err = np.abs(y.double().cpu().numpy() - ref)
+    assert np.all(err <= bound), (err / bound).max()
+
+
+@pytest.mark.parametrize("name", list(GRIDS))
+@pytest.mark.parametrize("dtype", [pcg.PCG_F64, pcg.PCG_F32])
+def test_line_preconditioner_matches_oracle(name, dtype):
+    d = GRIDS[name]()
+    print("precond", name, dtype, flush=True)
+    p = pcg.Problem(d)
+    tdt, u = DT[dtype]
+    r = cuda(si.uniform_pm1(12, p.n), tdt)
+    z = torch.full_like(r, float("nan"))
+    pcg.pcg_precond(p, dtype, r, z)
+    torch.cuda.synchronize()
+    A = oracle.assemble(grid_of(d))
+    M = oracle.line_blocks(A, d.nz)
+    rr, zz = r.double().cpu().numpy(), z.double().cpu().numpy()
+    Mz = M.di * zz
+    Mz[1:] += M.lo[1:] * zz[:-1]
+    Mz[:-1] += M.up[:-1] * zz[1:]
+    normM = np.abs(M.di).max() + np.abs(M.lo).max() + np.abs(M.up).max()
+    back = np.linalg.norm(Mz - rr) / (normM * np.linalg.norm(zz))
+    assert back <= 64 * u * (4 if dtype == pcg.PCG_F32 else 1), back
+    zo = oracle.line_solve(M, rr)
+    fwd = np.linalg.norm(zz - zo) / np.linalg.norm(zo)
+    assert fwd <= (1e-9 if dtype == pcg.PCG_F64 else 1e-3), fwd
+
+
+@pytest.mark.parametrize("name", ["64x64x32-dir", "13x7x33-dir-ragged", "9x5x17-per",
+                                  "6x11x100-mixedbc", "5x4x1-single-level", "1x1x40-single-column"])
+@pytest.mark.parametrize("dtype", [pcg.PCG_F64, pcg.PCG_F32])
+def test_csr_comparator_matches_oracle(name, dtype):
+    d = GRIDS[name]()
+    print("csr", name, dtype, flush=True)
+    p = pcg.Problem(d)
+    tdt, u = DT[dtype]
+    A = oracle.assemble(grid_of(d))
+    nnz = A.val.size
+    vs = 8 if dtype == pcg.PCG_F64 else 4
+    al = lambda v: (v + 255) // 256 * 256
+    assert pcg.pcg_csr_bytes(p, dtype) == al(vs * nnz) + al(4 * nnz) + al(4 * (p.n + 1))
+    buf = torch.zeros(pcg.pcg_csr_bytes(p, dtype), dtype=torch.uint8, device="cuda")
+    pcg.pcg_csr_build(p, dtype, buf)
+    x = cuda(si.uniform_pm1(13, p.n), tdt)
+    y = torch.empty_like(x)
+    pcg.pcg_csr_apply(p, dtype, buf, x, y)
+    torch.cuda.synchronize()
+    xr = x.double().cpu().numpy()
+    absA = oracle.CSR(A.n, A.row_ptr, A.col, np.abs(A.val))
+    err = np.abs(y.double().cpu().numpy() - A.matvec(xr))
+    assert np.all(err <= 64 * u * absA.matvec(np.abs(xr)) + 1e-300)
+    rowp = buf[al(vs * nnz) + al(4 * nnz):].view(torch.int32)[: p.n + 1].cpu().numpy()
+    np.testing.assert_array_equal(rowp, A.row_ptr.astype(np.int32))
+
+
+SOLVE_GRIDS = ["64x64x32-dir", "13x7x33-dir-ragged", "9x5x17-per", "6x11x100-mixedbc",
+               "5x4x1-single-level", "1x1x40-single-column", "3x3x7-per-min"]
+
+
+def oracle_run(d, b, rtol=1e-8, max_iter=10000):
+    A = oracle.assemble(grid_of(d))
+    M = oracle.line_blocks(A, d.nz)
+    return A, oracle.pcg(A, M, b, rtol=rtol, max_iter=max_iter)
+
+
+def gpu_solve(d, b, **kw):
+    p = pcg.Problem(d)
+    o = pcg.pcg_default_opts(**kw)
+    bt = cuda(b)
+    x = torch.zeros_like(bt)
+    ws = pcg.workspace(p, o)
+    st, res = pcg.pcg_solve(p, bt, x, ws, o)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), st, res
+
+
+@pytest.mark.parametrize("name", SOLVE_GRIDS)
+@pytest.mark.parametrize("fused", [1, 0])
+def test_fp64_solve_equal_iterations(name, fused):
+    d = GRIDS[name]()
+    print("solve", name, "fused" if fused else "unfused", flush=True)
+    b = si.rhs_uniform(d.nx, d.ny, d.nz, 3)
+    A, ref = oracle_run(d, b, rtol=1e-8)
+    k = ref["iterations"]
+    x, st, res = gpu_solve(d, b, rtol=0.0, max_iter=k, fused=fused, graph_chunk=3)
+    assert res["iterations"] == k and st == pcg.PCG_E_NOCONV
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+    assert err <= 1e-10, err
+
+
+@pytest.mark.parametrize("name", SOLVE_GRIDS)
+@pytest.mark.parametrize("fused", [1, 0])
+def test_fp64_solve_converges_like_oracle(name, fused):
+    d = GRIDS[name]()
+    print("converge", name, fused, flush=True)
+    b = si.rhs_uniform(d.nx, d.ny, d.nz, 4)
+    A, ref = oracle_run(d, b, rtol=1e-8)
+    x, st, res = gpu_solve(d, b, rtol=1e-8, fused=fused, true_residual=1)
+    assert st == pcg.PCG_OK
+    assert abs(res["iterations"] - ref["iterations"]) <= 1
+    true = oracle.residual_norm(A, b, x) / np.linalg.norm(b)
+    assert true < 1.05e-8, true
+    # both residuals carry an absolute rounding floor of ~n u ||A|| ||x|| / ||b||
+    assert abs(res["rel_res_true"] - true) <= 1e-3 * true + 1e-13
+
+
+def test_fused_and_unfused_iterates_agree():
+    d = GRIDS["64x64x32-dir"]()
+    b = si.rhs_uniform(64, 64, 32, 5)
+    xf, _, rf = gpu_solve(d, b, rtol=0.0, max_iter=4, fused=1)
+    xu, _, ru = gpu_solve(d, b, rtol=0.0, max_iter=4, fused=0)
+    assert rf["iterations"] == ru["iterations"] == 4
+    assert np.linalg.norm(xf - xu) <= 1e-11 * np.linalg.norm(xu)
+
+
+def test_graph_and_direct_launches_bitwise_equal():
+    d = GRIDS["13x7x33-dir-ragged"]()
+    b = si.rhs_uniform(d.nx, d.ny, d.nz, 6)
+    xg, _, rg = gpu_solve(d, b, graph_chunk=2)
+    xd, _, rd = gpu_solve(d, b, graph_chunk=0)
+    xp, _, rp = gpu_solve(d, b, graph_chunk=0, profile=1)
+    assert rg["iterations"] == rd["iterations"] == rp["iterations"]
+    assert np.array_equal(xg, xd) and np.array_equal(xg, xp)
+    assert rp["n_apply_kernel"] == rp["iterations"] and rp["n_precond_kernel"] == rp["iterations"] + 1
+    assert rp["ms_apply_kernel"] > 0 and rp["ms_precond_kernel"] > 0
+
+
+def test_repeated_solves_bitwise_reproducible():
+    d = GRIDS["64x64x32-dir"]()
+    p = pcg.Problem(d)
+    o = pcg.pcg_default_opts()
+    b = cuda(si.rhs_uniform(64, 64, 32, 7))
+    ws = pcg.workspace(p, o)
+    outs = []
+    for _ in range(6):
+        x = torch.zeros_like(b)
+        pcg.pcg_solve(p, b, x, ws, o)
+        outs.append(x.cpu())
+    for o2 in outs[1:]:
+        assert torch.equal(outs[0], o2)
+
+
+def test_zero_rhs_and_failure_statuses():
+    d = GRIDS["13x7x33-dir-ragged"]()
+    n = d.nx * d.ny * d.nz
+    x, st, res = gpu_solve(d, np.zeros(n))
+    assert st == pcg.PCG_OK and res["iterations"] == 0 and not x.any()
+    b = si.rhs_uniform(d.nx, d.ny, d.nz, 8)
+    b[17] = np.nan
+    x, st, res = gpu_solve(d, b)
+    assert st == pcg.PCG_E_BREAKDOWN
+    x, st, res = gpu_solve(d, si.rhs_uniform(d.nx, d.ny, d.nz, 8), max_iter=1)
+    assert st == pcg.PCG_E_NOCONV and res["iterations"] == 1 and res["rel_res_recursive"] < 1
+    p = pcg.Problem(d)
+    o = pcg.pcg_default_opts()
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        pcg.pcg_solve(p, cuda(b), torch.zeros(n, dtype=torch.float64, device="cuda"), small, o)
+    bt, xt = cuda(b), torch.zeros(n, dtype=torch.float64, device="cuda")   # keep both alive
+    st = pcg._lib.pcg_solve(p.handle, bt.data_ptr(), xt.data_ptr(), small.data_ptr(), 16, None,
+                            pcg.ctypes.byref(pcg.pcg_result()), None)
+    assert st == pcg.PCG_E_NOMEM
+    st = pcg._lib.pcg_solve(p.handle, bt.data_ptr(), bt.data_ptr(), small.data_ptr(), 16, None,
+                            pcg.ctypes.byref(pcg.pcg_result()), None)
+    assert st == pcg.PCG_E_INVALID and "overlap" in pcg.pcg_last_error()
+    st = pcg._lib.pcg_solve(p.handle, bt.data_ptr() + 8, xt.data_ptr(), small.data_ptr(), 16,
+                            None, pcg.ctypes.byref(pcg.pcg_result()), None)
+    assert st == pcg.PCG_E_INVALID and "aligned" in pcg.pcg_last_error()
+
+
+def test_no_horizontal_coupling_converges_in_one_iteration():
+    d = make_desc(9, 7, 24, 1e3, kh=0.0)
+    x, st, res = gpu_solve(d, si.rhs_uniform(9, 7, 24, 9), rtol=1e-12)
+    assert st == pcg.PCG_OK and res["iterations"] == 1
+
+
+@pytest.mark.parametrize("name", ["64x64x32-dir", "9x5x17-per", "6x11x100-mixedbc"])
+def test_mixed_precision_reaches_fp64_tolerance(name):
+    d = GRIDS[name]()
+    print("mixed", name, flush=True)
+    b = si.rhs_smooth_noise(d.nx, d.ny, d.nz, 2)
+    A, ref = oracle_run(d, b, rtol=1e-12)
+    x, st, res = gpu_solve(d, b, precision=pcg.PCG_PREC_MIXED, rtol=1e-8)
+    assert st == pcg.PCG_OK, res
+    true = oracle.residual_norm(A, b, x) / np.linalg.norm(b)
+    assert true < 1e-8, true
+    assert abs(res["rel_res_true"] - true) <= 1e-4 * true + 1e-13
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+    print("mixed %s: outer %d inner %d true residual %.2e error vs FP64 oracle %.2e"
+          % (name, res["outer_iterations"], res["iterations"], true, err))
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("precision", [pcg.PCG_PREC_FP64, pcg.PCG_PREC_MIXED])
+def test_batched_equals_single_solves(precision):
+    d = GRIDS["13x7x33-dir-ragged"]()
+    p = pcg.Problem(d)
+    n = p.n
+    nrhs = 5
+    B = np.stack([si.rhs_uniform(d.nx, d.ny, d.nz, 100 + s) for s in range(nrhs)])
+    B[2] *= 1e-3            # different scales and one zero right-hand side
+    B[4] = 0.0
+    o = pcg.pcg_default_opts(precision=precision)
+    bt = cuda(B.ravel())
+    x = torch.zeros_like(bt)
+    ws = pcg.workspace(p, o, nrhs)
+    st, res = pcg.pcg_solve_batched(p, nrhs, bt, x, ws, o)
+    torch.cuda.synchronize()
+    X = x.cpu().numpy().reshape(nrhs, n)
+    A = oracle.assemble(grid_of(d))
+    for s in range(nrhs):
+        xs, sts, rs = gpu_solve(d, B[s], precision=precision)
+        assert res[s]["status"] == sts == pcg.PCG_OK
+        assert res[s]["iterations"] == rs["iterations"]
+        np.testing.assert_array_equal(X[s], xs)
+        if B[s].any():
+            assert oracle.residual_norm(A, B[s], X[s]) / np.linalg.norm(B[s]) < 1.05e-8
+
+
+def test_full_size_periodic_workload_sampled():
+    """512 x 512 x 128 periodic, anisotropy 1e5: operator rows sampled against
+    the oracle's row formula, and the converged solution's residual from the
+    oracle's assembled matrix."""
+    d = make_desc(512, 512, 128, 1e5, bcx=1, bcy=1)
+    g = grid_of(d)
+    p = pcg.Problem(d)
+    n = p.n
+    x = si.uniform_pm1(21, n)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    pcg.pcg_apply(p, pcg.PCG_F64, cuda(x), y)
+    yh = y.cpu().numpy()
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        i, j, k = rng.integers(512), rng.integers(512), rng.integers(128)
+        if rng.random() < 0.3:
+            i = rng.choice([0, 511])
+        if rng.random() < 0.3:
+            k = rng.choice([0, 127])
+        ref = oracle.row_apply(g, int(i), int(j), int(k), x)
+        assert abs(yh[(i * 512 + j) * 128 + k] - ref) <= 1e-12 * (abs(ref) + 1e4)
+    b = si.rhs_uniform(512, 512, 128, 1)
+    xs, st, res = gpu_solve(d, b, true_residual=1)
+    assert st == pcg.PCG_OK
+    A = oracle.assemble(g)
+    true = oracle.residual_norm(A, b, xs) / np.linalg.norm(b)
+    print("512x512x128: %d iterations, true residual %.3e (GPU %.3e)"
+          % (res["iterations"], true, res["rel_res_true"]))
+    assert true < 1.05e-8
