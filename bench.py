@@ -1,0 +1,364 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-free line-preconditioned CG solver on one MI355X.
+
+Main timed loop (the `value`): full FP64 solves of the 512 x 512 x 128
+periodic problem (anisotropy ratio 1e5, vertical grading 1.05, right-hand
+side U[-1, 1) from seed 1) to relative residual 1e-8 with the two fused
+sweeps per iteration.  One step = one complete solve (start-up kernels, all
+iterations, exit correction, flag read-backs) with b already in HBM.
+value = unknowns * iterations / wall time of the timed steps.
+
+Every fused kernel in the timed steps is bracketed by HIP events on the
+stream it runs on; the dominant kernel's mean duration and its algorithmic
+bytes per launch give the `roofline` object.  `cpu_baseline` times the
+CPU oracle (plain C, one thread) on a bounded sample of the same workload.
+Extras (not timed in `value`): production graph path, unfused comparator,
+matrix-free vs CSR operator, the 64 x 64 x 32 latency case, mixed precision
+vs FP64 at 1024 x 1024 x 128, and a plain copy kernel as the HBM ceiling.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "unknowns·iter/s + HBM GB/s; mixed vs FP64 @1e-8 resid; served p50/p99 latency"
+PEAK_HBM_GBPS = 8000.0
+# Algorithmic bytes per unknown per launch (FP64): every vector touched once.
+BYTES = {"fused_apply": 56, "fused_prec": 32, "iteration": 88, "unfused_iteration": 160,
+         "apply": 16, "precond": 16}
+KERNEL_SYMBOL = {"fused_apply": "k_fused_apply<double, 4, true>",
+                 "fused_prec": "k_fused_prec<double, 4, true>"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device_common.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1302_7193_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload_tag: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload_tag))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_main(pcg, si, torch, steps, warmup):
+    nx, ny, nz = 512, 512, 128
+    desc = pcg.pcg_desc_from_ratio(nx, ny, nz, 1.05, 1e5, pcg.PCG_BC_PERIODIC)
+    P = pcg.Problem(desc)
+    n = P.n
+    b = torch.from_numpy(si.rhs_uniform(nx, ny, nz, 1)).cuda()
+    x = torch.empty_like(b)
+    opts = pcg.pcg_default_opts(rtol=1e-8, profile=1, x0_zero=1, graph_chunk=-1)
+    ws = pcg.workspace(P, opts)
+    for _ in range(warmup):
+        st, r = pcg.pcg_solve(P, b, x, ws, opts)
+        assert st == pcg.PCG_OK, r
+    torch.cuda.synchronize()
+    iters = launches = 0
+    ms = {"fused_apply": 0.0, "fused_prec": 0.0}
+    cnt = {"fused_apply": 0, "fused_prec": 0}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, r = pcg.pcg_solve(P, b, x, ws, opts)
+        iters += r["iterations"]
+        launches += r["launches"]
+        ms["fused_apply"] += r["ms_apply_kernel"]
+        ms["fused_prec"] += r["ms_precond_kernel"]
+        cnt["fused_apply"] += r["n_apply_kernel"]
+        cnt["fused_prec"] += r["n_precond_kernel"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert st == pcg.PCG_OK, r
+    return dict(P=P, b=b, x=x, n=n, steps=steps, iters=iters, elapsed=elapsed, ms=ms, cnt=cnt,
+                launches=launches, last=r)
+
+
+def cuda_time(torch, fn, reps):
+    """Mean ms per call of fn() with events on the current stream."""
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def timed_solves(pcg, torch, P, b, x, ws, opts, reps):
+    st, r = pcg.pcg_solve(P, b, x, ws, opts)          # warm (graph capture, chunk length)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for _ in range(reps):
+        st, r = pcg.pcg_solve(P, b, x, ws, opts)
+        its += r["iterations"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt / reps * 1e3, its / reps, st, r
+
+
+def extras(pcg, si, torch, main):
+    out = {}
+    P, b, x, n = main["P"], main["b"], main["x"], main["n"]
+
+    # production path: HIP graph chunks, no per-kernel events
+    o = pcg.pcg_default_opts(x0_zero=1, graph_chunk=-1)
+    ws = pcg.workspace(P, o)
+    ms, its, st, r = timed_solves(pcg, torch, P, b, x, ws, o, 20)
+    out["fused_fp64_graph"] = dict(ms_per_solve=ms, iterations=its,
+                                   unknowns_iter_per_s=n * its / (ms * 1e-3),
+                                   algorithmic_GBps=BYTES["iteration"] * n * its / (ms * 1e-3) / 1e9)
+    log("graph path: %.3f ms/solve, %.1f it" % (ms, its))
+
+    # unfused standard PCG (separate operator / preconditioner / BLAS-1 sweeps)
+    o = pcg.pcg_default_opts(x0_zero=1, fused=0, graph_chunk=-1)
+    ms, its, st, r = timed_solves(pcg, torch, P, b, x, ws, o, 10)
+    out["unfused_fp64"] = dict(ms_per_solve=ms, iterations=its,
+                               unknowns_iter_per_s=n * its / (ms * 1e-3),
+                               algorithmic_GBps=BYTES["unfused_iteration"] * n * its / (ms * 1e-3) / 1e9)
+    out["fused_over_unfused_time_per_iteration"] = (
+        (out["fused_fp64_graph"]["ms_per_solve"] / out["fused_fp64_graph"]["iterations"]) /
+        (ms / its))
+    log("unfused: %.3f ms/solve" % ms)
+
+    # operator alone: matrix-free vs assembled CSR; line preconditioner alone
+    y = torch.empty_like(b)
+    t_mf = cuda_time(torch, lambda: pcg.pcg_apply(P, pcg.PCG_F64, b, y), 50)
+    t_pc = cuda_time(torch, lambda: pcg.pcg_precond(P, pcg.PCG_F64, b, y), 50)
+    csr = torch.empty(pcg.pcg_csr_bytes(P, pcg.PCG_F64), dtype=torch.uint8, device="cuda")
+    pcg.pcg_csr_build(P, pcg.PCG_F64, csr)
+    t_csr = cuda_time(torch, lambda: pcg.pcg_csr_apply(P, pcg.PCG_F64, csr, b, y), 20)
+    nnz_bytes = csr.numel() - 4 * (n + 1)           # values + column indices (+ padding)
+    csr_bytes = nnz_bytes + 4 * (n + 1) + 16 * n    # + row offsets + x + y
+    out["operator_fp64"] = dict(
+        matrix_free_us=t_mf * 1e3, matrix_free_GBps=BYTES["apply"] * n / (t_mf * 1e-3) / 1e9,
+        csr_us=t_csr * 1e3, csr_GBps=csr_bytes / (t_csr * 1e-3) / 1e9,
+        csr_bytes_per_unknown=csr_bytes / n, csr_over_matrix_free_time=t_csr / t_mf,
+        line_precond_us=t_pc * 1e3, line_precond_GBps=BYTES["precond"] * n / (t_pc * 1e-3) / 1e9)
+    del csr
+    log("operator: MF %.1f us, CSR %.1f us, precond %.1f us" % (t_mf * 1e3, t_csr * 1e3, t_pc * 1e3))
+    del ws
+
+    # small Dirichlet problem: latency-bound (fits in cache)
+    d1 = pcg.pcg_desc_from_ratio(64, 64, 32, 1.05, 1e4, pcg.PCG_BC_DIRICHLET)
+    P1 = pcg.Problem(d1)
+    b1 = torch.from_numpy(si.rhs_uniform(64, 64, 32, 0)).cuda()
+    x1 = torch.empty_like(b1)
+    o = pcg.pcg_default_opts(x0_zero=1, graph_chunk=-1)
+    ws1 = pcg.workspace(P1, o)
+    ms, its, st, r = timed_solves(pcg, torch, P1, b1, x1, ws1, o, 50)
+    out["small_64x64x32_fp64"] = dict(ms_per_solve=ms, iterations=its,
+                                      us_per_iteration=ms * 1e3 / max(its, 1),
+                                      unknowns_iter_per_s=P1.n * its / (ms * 1e-3))
+    log("64x64x32: %.3f ms/solve, %.1f it" % (ms, its))
+    del P1, b1, x1, ws1
+
+    # mixed precision vs plain FP64 on 1024 x 1024 x 128
+    d3 = pcg.pcg_desc_from_ratio(1024, 1024, 128, 1.05, 1e4, pcg.PCG_BC_DIRICHLET)
+    P3 = pcg.Problem(d3)
+    log("generating 1024x1024x128 right-hand side")
+    b3 = torch.from_numpy(si.rhs_smooth_noise(1024, 1024, 128, 2)).cuda()
+    x3 = torch.empty_like(b3)
+    res3 = {}
+    for name, o in (("fp64", pcg.pcg_default_opts(x0_zero=1, true_residual=1)),
+                    ("mixed", pcg.pcg_default_opts(x0_zero=1, precision=pcg.PCG_PREC_MIXED))):
+        ws3 = pcg.workspace(P3, o)
+        ms, its, st, r = timed_solves(pcg, torch, P3, b3, x3, ws3, o, 5)
+        res3[name] = dict(ms_per_solve=ms, iterations=its, outer=r["outer_iterations"],
+                          status=pcg.STATUS_NAMES[st], rel_res_true=r["rel_res_true"])
+        del ws3
+        log("1024x1024x128 %s: %.3f ms/solve" % (name, ms))
+    res3["mixed_speedup_over_fp64"] = res3["fp64"]["ms_per_solve"] / res3["mixed"]["ms_per_solve"]
+    res3["unknowns"] = P3.n
+    out["mixed_1024x1024x128"] = res3
+    del P3, b3, x3
+
+    # plain copy kernel: attainable HBM bandwidth
+    a = torch.empty(1 << 29, dtype=torch.float64, device="cuda")   # 4 GiB
+    c = torch.empty_like(a)
+    t_cp = cuda_time(torch, lambda: c.copy_(a), 10)
+    out["hbm_copy_probe_GBps"] = 2 * a.numel() * 8 / (t_cp * 1e-3) / 1e9
+    del a, c
+    return out
+
+
+def cpu_baseline(n_iter=2):
+    """Oracle (plain C, FP64, one thread) on the same 512 x 512 x 128 problem:
+    assembly, then a fixed number of PCG iterations."""
+    import oracle
+    import synth_inputs as si
+    g = oracle.grid_from_ratio(512, 512, 128, 1e5, q=1.05, periodic=True)
+    b = si.rhs_uniform(512, 512, 128, 1)
+    t0 = time.perf_counter()
+    A = oracle.assemble(g)
+    M = oracle.line_blocks(A, g.nz)
+    t1 = time.perf_counter()
+    res = oracle.pcg(A, M, b, rtol=0.0, max_iter=n_iter)
+    t2 = time.perf_counter()
+    return dict(value=g.n * res["iterations"] / (t2 - t1), unit="unknowns·iter/s", cores=1,
+                kind="oracle",
+                sample="512x512x128 periodic FP64: CSR assembly (%.1f s, not in value) then %d PCG "
+                       "iterations incl. start-up residual/preconditioner (%.1f s)"
+                       % (t1 - t0, res["iterations"], t2 - t1))
+
+
+def copy_probe(gib=1, reps=5):
+    """Plain device copy of a known size (for calibrating HBM byte counters)."""
+    import torch
+    torch.cuda.set_device(0)
+    a = torch.ones((gib << 30) // 8, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": a.numel() * 8,
+                      "reps": reps}))
+
+
+def summarize_rocprof(directory, kernel_filter="k_fused|k_init|k_fixup|copy|elementwise"):
+    """Condense rocprofv3 CSV output (kernel stats and/or counter collection)
+    found under `directory` into a few lines of text."""
+    import csv
+    import glob
+    import re
+    lines = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)):
+        lines.append("# kernel stats: %s" % os.path.relpath(path, directory))
+        lines.append("name | calls | total_ms | avg_us | min_us | max_us | pct")
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                lines.append("%s | %s | %.3f | %.2f | %.2f | %.2f | %s" % (
+                    row["Name"], row["Calls"], float(row["TotalDurationNs"]) / 1e6,
+                    float(row["AverageNs"]) / 1e3, float(row["MinNs"]) / 1e3,
+                    float(row["MaxNs"]) / 1e3, row.get("Percentage", "")))
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"),
+                                 recursive=True)):
+        agg = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                name = row["Kernel_Name"]
+                if not re.search(kernel_filter, name):
+                    continue
+                key = (name, row["Counter_Name"], row.get("Grid_Size", ""))
+                v = agg.setdefault(key, [0, 0.0])
+                v[0] += 1
+                v[1] += float(row["Counter_Value"])
+        lines.append("# counters: %s" % os.path.relpath(path, directory))
+        lines.append("kernel | counter | grid | dispatches | mean_per_dispatch")
+        for (name, cn, grid), (c, tot) in sorted(agg.items()):
+            lines.append("%s | %s | %s | %d | %.1f" % (name, cn, grid, c, tot / c))
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the timed loop (for profiler runs): no extras, no CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (counter calibration)")
+    ap.add_argument("--summarize-rocprof", metavar="DIR",
+                    help="print a text summary of rocprofv3 CSV output under DIR and exit")
+    args = ap.parse_args()
+    if args.summarize_rocprof:
+        summarize_rocprof(args.summarize_rocprof)
+        return
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the solver has no multi-GPU path "
+              "(each GPU would solve its own column blocks; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1302_7193_amd as pcg
+    import synth_inputs as si
+    torch.cuda.set_device(0)
+
+    log("main loop: %d warm-up + %d timed solves of 512x512x128" % (args.warmup, args.steps))
+    m = run_main(pcg, si, torch, args.steps, args.warmup)
+    n, iters, el = m["n"], m["iters"], m["elapsed"]
+    value = n * iters / el
+    kern = {}
+    for k in ("fused_apply", "fused_prec"):
+        avg = m["ms"][k] / max(m["cnt"][k], 1)
+        achieved = BYTES[k] * n / (avg * 1e-3) / 1e9
+        kern[k] = dict(avg_ms=avg, launches=m["cnt"][k], achieved_GBps=achieved,
+                       total_ms=m["ms"][k], symbol=KERNEL_SYMBOL[k])
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    traffic = measured_traffic(dom, "512x512x128")
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "unknowns·iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "512x512x128 periodic, anisotropy 1e5, grading 1.05, "
+                               "U[-1,1) seed 1, FP64 fused PCG to rel. residual 1e-8",
+                   "nx": 512, "ny": 512, "nz": 128, "unknowns": n,
+                   "iterations_per_solve": iters / args.steps},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom],
+                     "achieved": kern[dom]["achieved_GBps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": kern[dom]["achieved_GBps"] / PEAK_HBM_GBPS,
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": BYTES[dom] * n,
+                     "avg_launch_ms": kern[dom]["avg_ms"]},
+        "kernels": kern,
+        "algorithmic_GBps_per_iteration": BYTES["iteration"] * n * iters / el / 1e9,
+        "kernel_source_sha256_16": kernel_source_hash(),
+    }
+    if not args.main_only:
+        try:
+            line["extras"] = extras(pcg, si, torch, m)
+        except Exception as e:  # report, keep the main line
+            line["extras_error"] = repr(e)
+        if not args.no_cpu_baseline:
+            log("cpu baseline (oracle)")
+            line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -20,7 +20,8 @@
  *   index s*n + l for right-hand side s.
  * Memory.  Vector arguments are device pointers (HIP device memory of the
  *   device that was current when the problem was created), owned by the
- *   caller, 256-byte alignment recommended, never retained after return.
+ *   caller, 16-byte aligned (PCG_E_INVALID otherwise), never retained after
+ *   return.
  *   Host pointers are accepted only where the argument name ends in _host.
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
  *   stream).  pcg_apply/pcg_precond/pcg_csr_* are asynchronous on it;
@@ -89,6 +90,7 @@ typedef struct {
     int32_t profile;      /* 1: time every fused kernel with HIP events
                              (direct launches); fills the *_kernel_* fields */
     int32_t true_residual;/* 1: also compute ||b - A x|| / ||r0|| in FP64    */
+    int32_t x0_zero;      /* 1: start from x0 = 0 without reading x          */
 } pcg_solve_opts;
 
 typedef struct {
@@ -111,7 +113,8 @@ typedef struct pcg_problem pcg_problem; /* opaque */
 typedef struct pcg_server pcg_server;   /* opaque */
 
 /* Default options: rtol 1e-8, atol 0, max_iter 10000, FP64, inner_rtol 3e-5,
- * max_outer 20, fused, graph_chunk -1, no profiling, no true residual. */
+ * max_outer 20, fused, graph_chunk -1, no profiling, no true residual, x0
+ * read from x. */
 void pcg_default_opts(pcg_solve_opts *opts);
 
 /* Fill a descriptor for the unit square (dx = 1/n_x, dy = 1/n_y), height 1,
@@ -122,9 +125,12 @@ void pcg_default_opts(pcg_solve_opts *opts);
 pcg_status pcg_desc_from_ratio(int32_t nx, int32_t ny, int32_t nz, double grading,
                                double gamma2, int32_t bc, pcg_problem_desc *out);
 
-/* Validate desc and precompute the column coefficient vectors (Sec. 4.2:
- * a', b', c', d of length n_z) and the column-block factors on the current
- * device.  Allocates a few KiB of device memory owned by the handle. */
+/* Validate desc and precompute, on the current device, the vertical
+ * coefficient vectors a, b, c, d of length n_z (Sec. 3.1, eq.
+ * TridiagonalMatrix; Sec. 4.2: only O(n_z) numbers describe the vertical
+ * discretisation) and the LU factors of the column block for each of the
+ * at most nine column classes (number of Dirichlet side faces).  Allocates
+ * a few KiB of device memory owned by the handle. */
 pcg_status pcg_problem_create(const pcg_problem_desc *desc, pcg_problem **out);
 void pcg_problem_destroy(pcg_problem *p);
 
@@ -164,6 +170,39 @@ pcg_status pcg_solve(pcg_problem *p, const double *b, double *x, void *workspace
 pcg_status pcg_solve_batched(pcg_problem *p, int32_t nrhs, const double *b, double *x,
                              void *workspace, size_t workspace_bytes,
                              const pcg_solve_opts *opts, pcg_result *results, void *stream);
+
+/* Launch parameters of the column kernels for one precision.
+ *   lanes_per_column  L: a column is handled by L lanes of a 64-wide
+ *                     wavefront, each owning ceil(n_z/L) (rounded up to a
+ *                     power of two, at most 16) consecutive levels; the
+ *                     line solve combines the L pieces with a log2(L)-step
+ *                     in-wave scan (the sub-structuring of Sec. 6.1).
+ *                     Power of two, 1 <= L <= 64, 16*L >= n_z.
+ *   block_cap         workgroups per right-hand side (>= 1, <= 16384);
+ *                     each walks a contiguous range of column tiles.
+ *   reduction         0: the last workgroup of each reduction totals the
+ *                     partial sums and performs the scalar step inside the
+ *                     kernel (device-scope fences in every workgroup);
+ *                     1: a separate one-workgroup launch does it.
+ * Both reductions add the same numbers in the same order; changing L or
+ * block_cap changes the summation order (results stay within rounding). */
+typedef struct {
+    int32_t lanes_per_column;
+    int32_t block_cap;
+    int32_t reduction;
+} pcg_tuning;
+
+pcg_status pcg_get_tuning(const pcg_problem *p, int32_t dtype, pcg_tuning *out);
+pcg_status pcg_set_tuning(pcg_problem *p, int32_t dtype, const pcg_tuning *t);
+
+/* Autotuner: times fused iterations (kernels A and B over nrhs right-hand
+ * sides, on synthetic vectors) for every supported lanes_per_column, a
+ * ladder of block caps and both reduction modes, keeps the fastest for
+ * (p, dtype) and returns it in best (may be NULL).  A set-up utility: it
+ * allocates (and frees) its own device scratch of about 5 vectors of
+ * nrhs*n values of dtype.  Blocks. */
+pcg_status pcg_autotune(pcg_problem *p, int32_t dtype, int32_t nrhs, void *stream,
+                        pcg_tuning *best);
 
 /* Assembled-CSR comparator (Sec. 6.2): bytes for the CSR arrays of dtype
  * (values of dtype, int32 column indices, int32 row offsets), a device-side

@@ -47,7 +47,16 @@ class pcg_solve_opts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("fused", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("true_residual", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("true_residual", ctypes.c_int32),
+                ("x0_zero", ctypes.c_int32)]
+
+
+class pcg_tuning(ctypes.Structure):
+    _fields_ = [("lanes_per_column", ctypes.c_int32), ("block_cap", ctypes.c_int32),
+                ("reduction", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class pcg_result(ctypes.Structure):
@@ -82,6 +91,9 @@ _sig = {
     "pcg_csr_build": (_S, [_P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "pcg_csr_apply": (_S, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "pcg_last_error": (ctypes.c_size_t, [ctypes.c_char_p, ctypes.c_size_t]),
+    "pcg_get_tuning": (_S, [_P, ctypes.c_int32, ctypes.POINTER(pcg_tuning)]),
+    "pcg_set_tuning": (_S, [_P, ctypes.c_int32, ctypes.POINTER(pcg_tuning)]),
+    "pcg_autotune": (_S, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(pcg_tuning)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -245,6 +257,26 @@ def pcg_csr_apply(p: Problem, dtype: int, buf, x, y, stream=None) -> int:
     return _check(_lib.pcg_csr_apply(p.handle, dtype, _buf(buf, need, "csr buffer"),
                                      _vec(x, p.n, td, "x"), _vec(y, p.n, td, "y"),
                                      _stream(stream)), "pcg_csr_apply")
+
+
+def pcg_get_tuning(p: Problem, dtype: int) -> pcg_tuning:
+    t = pcg_tuning()
+    _check(_lib.pcg_get_tuning(p.handle, dtype, ctypes.byref(t)), "pcg_get_tuning")
+    return t
+
+
+def pcg_set_tuning(p: Problem, dtype: int, t: pcg_tuning | None = None, **fields) -> None:
+    t = t or pcg_get_tuning(p, dtype)
+    for k, v in fields.items():
+        setattr(t, k, v)
+    _check(_lib.pcg_set_tuning(p.handle, dtype, ctypes.byref(t)), "pcg_set_tuning")
+
+
+def pcg_autotune(p: Problem, dtype: int, nrhs: int = 1, stream=None) -> pcg_tuning:
+    t = pcg_tuning()
+    _check(_lib.pcg_autotune(p.handle, dtype, nrhs, _stream(stream), ctypes.byref(t)),
+           "pcg_autotune")
+    return t
 
 
 def solve(desc: pcg_problem_desc, b: torch.Tensor, x0: torch.Tensor | None = None, **opts):

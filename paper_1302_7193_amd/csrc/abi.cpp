@@ -16,6 +16,8 @@ std::string validate(const pcg_problem_desc& d);
 void build_tables(const pcg_problem_desc& d, Geom& g, std::vector<double>& vert,
                   std::vector<double>& lu);
 size_t workspace_bytes(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs);
+int64_t blocks_per_rhs(const pcg_problem* P, int dtype);
+pcg_status autotune(pcg_problem* P, int dtype, int64_t nrhs, hipStream_t s, Tuning* best);
 pcg_status solve(pcg_problem* P, const double* b, double* x, void* workspace, size_t ws_bytes,
                  const pcg_solve_opts& o, int64_t nrhs, pcg_result* res, hipStream_t s);
 
@@ -125,6 +127,7 @@ void pcg_default_opts(pcg_solve_opts* o)
     o->graph_chunk = -1;
     o->profile = 0;
     o->true_residual = 0;
+    o->x0_zero = 0;
 }
 
 pcg_status pcg_desc_from_ratio(int32_t nx, int32_t ny, int32_t nz, double grading, double gamma2,
@@ -184,8 +187,11 @@ pcg_status pcg_problem_create(const pcg_problem_desc* desc, pcg_problem** out)
     P->desc = *desc;
     P->device = dev;
     build_tables(*desc, P->geom, P->vert64, P->lu64);
-    P->shape[PCG_F64] = default_shape(desc->nz, PCG_F64);
-    P->shape[PCG_F32] = default_shape(desc->nz, PCG_F32);
+    for (int d = 0; d < 2; ++d) {
+        P->tune[d].shape = default_shape(desc->nz, d);
+        P->tune[d].block_cap = 2048;
+        P->tune[d].red_mode = 1;
+    }
     const size_t nv = P->vert64.size(), nl = P->lu64.size();
     const size_t b64v = al256(8 * nv), b64l = al256(8 * nl), b32v = al256(4 * nv), b32l = al256(4 * nl);
     hipError_t e = hipMalloc(&P->dev_tables, b64v + b64l + b32v + b32l);
@@ -255,8 +261,8 @@ pcg_status pcg_apply(pcg_problem* P, int32_t dtype, const void* x, void* y, void
     return on_device(P->device, [&]() -> pcg_status {
         ColArgs a{};
         a.g = P->geom;
-        a.L = P->shape[dtype].L;
-        a.blocks_per_rhs = std::max<int64_t>(1, std::min(P->block_cap, column_blocks(P->geom, P->shape[dtype])));
+        a.L = P->tune[dtype].shape.L;
+        a.blocks_per_rhs = blocks_per_rhs(P, dtype);
         a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
         a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
         a.in0 = x;
@@ -282,8 +288,8 @@ pcg_status pcg_precond(pcg_problem* P, int32_t dtype, const void* r, void* z, vo
     return on_device(P->device, [&]() -> pcg_status {
         ColArgs a{};
         a.g = P->geom;
-        a.L = P->shape[dtype].L;
-        a.blocks_per_rhs = std::max<int64_t>(1, std::min(P->block_cap, column_blocks(P->geom, P->shape[dtype])));
+        a.L = P->tune[dtype].shape.L;
+        a.blocks_per_rhs = blocks_per_rhs(P, dtype);
         a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
         a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
         a.in0 = r;
@@ -340,6 +346,58 @@ pcg_status pcg_solve_batched(pcg_problem* P, int32_t nrhs, const double* b, doub
                              pcg_result* results, void* stream)
 {
     return solve_common(P, nrhs, b, x, workspace, workspace_bytes, opts, results, stream);
+}
+
+pcg_status pcg_get_tuning(const pcg_problem* P, int32_t dtype, pcg_tuning* out)
+{
+    if (!P || !out || !valid_dtype(dtype)) {
+        set_error("pcg_get_tuning: NULL argument or bad dtype");
+        return PCG_E_INVALID;
+    }
+    out->lanes_per_column = P->tune[dtype].shape.L;
+    out->block_cap = (int32_t)P->tune[dtype].block_cap;
+    out->reduction = P->tune[dtype].red_mode;
+    return PCG_OK;
+}
+
+pcg_status pcg_set_tuning(pcg_problem* P, int32_t dtype, const pcg_tuning* t)
+{
+    if (!P || !t || !valid_dtype(dtype)) {
+        set_error("pcg_set_tuning: NULL argument or bad dtype");
+        return PCG_E_INVALID;
+    }
+    Shape sh;
+    sh.L = t->lanes_per_column;
+    if (!shape_supported(P->geom.nz, sh)) {
+        set_error("pcg_set_tuning: lanes_per_column must be a power of two in [1, 64] with "
+                  "16 * lanes_per_column >= n_z");
+        return PCG_E_INVALID;
+    }
+    if (t->block_cap < 1 || t->block_cap > kMaxBlocks || (t->reduction != 0 && t->reduction != 1)) {
+        set_error("pcg_set_tuning: block_cap must be in [1, 16384] and reduction 0 or 1");
+        return PCG_E_INVALID;
+    }
+    sh.M = 1;
+    while (sh.M * sh.L < P->geom.nz) sh.M <<= 1;
+    P->tune[dtype].shape = sh;
+    P->tune[dtype].block_cap = t->block_cap;
+    P->tune[dtype].red_mode = t->reduction;
+    return PCG_OK;
+}
+
+pcg_status pcg_autotune(pcg_problem* P, int32_t dtype, int32_t nrhs, void* stream,
+                        pcg_tuning* best)
+{
+    if (!P || !valid_dtype(dtype) || nrhs < 1) {
+        set_error("pcg_autotune: NULL problem, bad dtype or nrhs < 1");
+        return PCG_E_INVALID;
+    }
+    pcg_status st = on_device(P->device, [&]() -> pcg_status {
+        Tuning t;
+        return autotune(P, dtype, nrhs, static_cast<hipStream_t>(stream), &t);
+    });
+    if (st == PCG_OK && best) return pcg_get_tuning(P, dtype, best);
+    return st;
 }
 
 size_t pcg_csr_bytes(const pcg_problem* P, int32_t dtype)

@@ -1,13 +1,43 @@
 // Unfused comparator: the standard PCG iteration of Sec. 4.1 as separate
 // sweeps over memory -- three axpy, one scal, two dot and one nrm2 per
 // iteration (Tab. BLASoperations) beside the operator and preconditioner
-// kernels.  FP64.  Scalars stay in device memory: each reduction's last
-// workgroup performs the scalar step it enables, so no host round trip is
-// needed between kernels.
+// kernels.  FP64.  Scalars stay in device memory: the scalar step each
+// reduction enables runs on the device (in the last workgroup, or in a
+// one-workgroup finalize launch), so no host round trip is needed between
+// kernels.
 #include "device_common.h"
 
 namespace pcg {
 namespace {
+
+// Scalar step that a reduction enables (standard PCG, Sec. 4.1).
+template <Blas OP>
+__device__ inline void blas_finish(SolverState* s, const double (&tot)[2])
+{
+    if (OP == Blas::DotPQ) {          // alpha = rho / <p, Ap>
+        if (!(tot[0] > 0.0) || !isfinite(tot[0])) { s->flag = kBreakdown; return; }
+        s->sigma = tot[0];
+        s->alpha = s->kappa_old / tot[0];
+    } else if (OP == Blas::Nrm2R) {   // exit test on the updated residual
+        const double rn = sqrt(tot[0]);
+        s->rnorm = rn;
+        s->iter += 1;
+        if (!isfinite(rn)) s->flag = kBreakdown;
+        else if (rn / s->r0norm < s->rtol || rn < s->atol) s->flag = kConverged;
+        else if (s->iter >= s->max_iter) s->flag = kMaxIter;
+    } else if (OP == Blas::DotRZ) {   // beta = rho' / rho
+        if (!(tot[0] > 0.0) || !isfinite(tot[0])) { s->flag = kBreakdown; return; }
+        s->beta = tot[0] / s->kappa_old;
+        s->kappa_old = tot[0];
+    } else if (OP == Blas::InitDot) { // start: rho = <r,z>, ||r0||
+        const double rn = sqrt(tot[1]);
+        s->r0norm = s->rnorm = rn;
+        s->kappa_old = tot[0];
+        if (!isfinite(rn) || !isfinite(tot[0])) s->flag = kBreakdown;
+        else if (rn == 0.0 || rn < s->atol) s->flag = kConverged;
+        else if (!(tot[0] > 0.0)) s->flag = kBreakdown;
+    }
+}
 
 template <Blas OP>
 __global__ __launch_bounds__(kBlock) void k_blas(BlasArgs a)
@@ -59,32 +89,20 @@ __global__ __launch_bounds__(kBlock) void k_blas(BlasArgs a)
                              OP == Blas::Nrm2R;
     if constexpr (reduces) {
         double tot[2];
-        if (reduce_last<2>(acc, a.part, blk, nb, &s->ticket, tot) && threadIdx.x == 0) {
-            if (OP == Blas::DotPQ) {          // alpha = rho / <p, Ap>
-                if (!(tot[0] > 0.0) || !isfinite(tot[0])) { s->flag = kBreakdown; return; }
-                s->sigma = tot[0];
-                s->alpha = s->kappa_old / tot[0];
-            } else if (OP == Blas::Nrm2R) {   // exit test on the updated residual
-                const double rn = sqrt(tot[0]);
-                s->rnorm = rn;
-                s->iter += 1;
-                if (!isfinite(rn)) s->flag = kBreakdown;
-                else if (rn / s->r0norm < s->rtol || rn < s->atol) s->flag = kConverged;
-                else if (s->iter >= s->max_iter) s->flag = kMaxIter;
-            } else if (OP == Blas::DotRZ) {   // beta = rho' / rho
-                if (!(tot[0] > 0.0) || !isfinite(tot[0])) { s->flag = kBreakdown; return; }
-                s->beta = tot[0] / s->kappa_old;
-                s->kappa_old = tot[0];
-            } else {                          // start: rho = <r,z>, ||r0||
-                const double rn = sqrt(tot[1]);
-                s->r0norm = s->rnorm = rn;
-                s->kappa_old = tot[0];
-                if (!isfinite(rn) || !isfinite(tot[0])) s->flag = kBreakdown;
-                else if (rn == 0.0 || rn < s->atol) s->flag = kConverged;
-                else if (!(tot[0] > 0.0)) s->flag = kBreakdown;
-            }
-        }
+        if (publish<2>(acc, a.part, blk, nb, &s->ticket, a.red_mode, tot) && threadIdx.x == 0)
+            blas_finish<OP>(s, tot);
     }
+}
+
+// Mode-1 reductions of the BLAS-1 kernels (one workgroup).
+template <Blas OP>
+__global__ __launch_bounds__(kBlock) void k_blas_finalize(BlasArgs a)
+{
+    SolverState* s = a.st;
+    if (s->flag != kRunning) return;
+    double tot[2];
+    sum_partials<2, false>(a.part, a.blocks, tot);
+    if (threadIdx.x == 0) blas_finish<OP>(s, tot);
 }
 
 }  // namespace
@@ -92,9 +110,14 @@ __global__ __launch_bounds__(kBlock) void k_blas(BlasArgs a)
 hipError_t launch_blas(Blas op, const BlasArgs& a, hipStream_t s)
 {
     const dim3 grid((unsigned)a.blocks), block(kBlock);
+    const bool fin = a.red_mode != 0 && (op == Blas::DotPQ || op == Blas::DotRZ ||
+                                         op == Blas::Nrm2R || op == Blas::InitDot);
     switch (op) {
-#define PCG_BLAS_CASE(X) \
-    case Blas::X: hipLaunchKernelGGL((k_blas<Blas::X>), grid, block, 0, s, a); break;
+#define PCG_BLAS_CASE(X)                                                                \
+    case Blas::X:                                                                       \
+        hipLaunchKernelGGL((k_blas<Blas::X>), grid, block, 0, s, a);                    \
+        if (fin) hipLaunchKernelGGL((k_blas_finalize<Blas::X>), dim3(1), block, 0, s, a); \
+        break;
         PCG_BLAS_CASE(DotPQ)
         PCG_BLAS_CASE(DotRZ)
         PCG_BLAS_CASE(Nrm2R)

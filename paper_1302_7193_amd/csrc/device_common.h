@@ -24,15 +24,12 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Block-reduce NV sums, publish them in slot `blk` of `part`, and return
-// true in the workgroup that finished last, with the fixed-order totals of
-// all `nblk` slots in tot (identical in every thread of that workgroup).
+// Sum NV per-thread values over the workgroup in a fixed order; the totals
+// are returned in every thread.
 template <int NV>
-__device__ __forceinline__ bool reduce_last(double (&v)[NV], double* part, int64_t blk,
-                                            int64_t nblk, uint32_t* ticket, double (&tot)[NV])
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (&out)[NV])
 {
     __shared__ double sm[kBlock / kWave][NV];
-    __shared__ int is_last;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
@@ -41,14 +38,61 @@ __device__ __forceinline__ bool reduce_last(double (&v)[NV], double* part, int64
         for (int i = 0; i < NV; ++i) sm[wave][i] = v[i];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) s += sm[w][i];
+        out[i] = s;
+    }
+    __syncthreads();
+}
+
+// Fixed-order total of the nblk published partial sums (every thread gets
+// it).  COHERENT: read with device-scope atomic loads (partials written by
+// other workgroups of the running kernel).
+template <int NV, bool COHERENT>
+__device__ __forceinline__ void sum_partials(const double* part, int64_t nblk, double (&tot)[NV])
+{
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int64_t b = threadIdx.x; b < nblk; b += kBlock) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            double s = 0.0;
-            for (int w = 0; w < kBlock / kWave; ++w) s += sm[w][i];
-            __hip_atomic_store(&part[blk * kRedSlots + i], s, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            const double* q = &part[b * kRedSlots + i];
+            acc[i] += COHERENT ? __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : *q;
         }
+    }
+    block_sum<NV>(acc, tot);
+}
+
+// Publish this workgroup's sums of v in slot blk of part.
+//   mode 0: the workgroup that finishes last (atomic ticket) totals all slots
+//           and returns true with the totals in tot -- the scalar step then
+//           runs inside this kernel, at the price of device-scope fences in
+//           every workgroup;
+//   mode 1: plain stores only; a separate finalize launch totals the slots.
+// Both modes add the same numbers in the same order.
+template <int NV>
+__device__ __forceinline__ bool publish(double (&v)[NV], double* part, int64_t blk, int64_t nblk,
+                                        uint32_t* ticket, int mode, double (&tot)[NV])
+{
+    double bs[NV];
+    block_sum<NV>(v, bs);
+    if (mode != 0) {
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) part[blk * kRedSlots + i] = bs[i];
+        }
+        return false;
+    }
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            __hip_atomic_store(&part[blk * kRedSlots + i], bs[i], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         const uint32_t t = atomicAdd(ticket, 1u);
         is_last = (t == (uint32_t)(nblk - 1));
@@ -57,29 +101,7 @@ __device__ __forceinline__ bool reduce_last(double (&v)[NV], double* part, int64
     __syncthreads();
     if (!is_last) return false;
     __threadfence();
-    double acc[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int64_t b = threadIdx.x; b < nblk; b += kBlock) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i)
-            acc[i] += __hip_atomic_load(&part[b * kRedSlots + i], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = wave_sum(acc[i]);
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) sm[wave][i] = acc[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double s = 0.0;
-        for (int w = 0; w < kBlock / kWave; ++w) s += sm[w][i];
-        tot[i] = s;
-    }
+    sum_partials<NV, true>(part, nblk, tot);
     if (threadIdx.x == 0) *ticket = 0u;
     return true;
 }

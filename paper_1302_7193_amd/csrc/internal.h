@@ -18,6 +18,7 @@ constexpr int kBlock = 256;        // threads per workgroup of the column kernel
 constexpr int kMaxNz = 1024;       // columns up to 64 lanes x 16 levels
 constexpr int kClasses = 9;        // column classes: Dirichlet faces in x (0..2) x in y (0..2)
 constexpr int kRedSlots = 4;       // doubles per workgroup in the partial-sum buffer
+constexpr int64_t kMaxBlocks = 16384;   // workgroups per right-hand side (partial-sum slots)
 
 // Solver flags kept in device memory.
 enum : int32_t {
@@ -78,9 +79,11 @@ struct Shape {
     int cols_per_block() const { return (kWave / L) * (kBlock / kWave); }
 };
 
-struct Launch {
+// Tunable launch parameters of one precision (see pcg_tuning).
+struct Tuning {
     Shape shape;
-    int64_t blocks;
+    int64_t block_cap = 2048;   // workgroups per right-hand side
+    int red_mode = 1;           // reduction mode (ColArgs::red_mode)
 };
 
 // ---------------------------------------------------------------- kernels --
@@ -94,7 +97,7 @@ enum class Kind : int {
     FusedApply,   // kernel A: x += alpha p; p = z + beta p; q = A z + beta q; sigma; alpha
     Fixup,        // x += alpha p once, after the exit test fired
     Residual64,   // FP64 r = b - A x, ||r||; FP32 copy r * scale  (refinement)
-    Update64,     // FP64 x += scale * (u32 + alpha p32)           (refinement)
+    Update64,     // FP64 x += u32 / scale                         (refinement)
     TrueResidual, // FP64 ||b - A x||
 };
 
@@ -117,12 +120,18 @@ struct ColArgs {
     void* out32;        // FP32 vector of the refinement kernels
     SolverState* st;    // per right-hand side
     double* part;       // [batch][blocks_per_rhs][kRedSlots]
-    double scale;
+    int red_mode;       // 0: last workgroup finishes reductions; 1: finalize launch
+    int x0_zero;        // refinement kernels: x is zero (not read)
 };
 
-// Host launchers (kernels.hip): T = double or float.
+// Host launchers (kernels.hip): T = double or float.  launch_column issues
+// the kernel and, for mode-1 reductions, its finalize launch;
+// launch_column_main / launch_column_finalize issue them separately.
 template <typename T>
 hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s);
+template <typename T>
+hipError_t launch_column_main(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s);
+hipError_t launch_column_finalize(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s);
 
 // Unfused BLAS-1 style kernels with device-resident scalars (blas.hip).
 enum class Blas : int {
@@ -146,6 +155,7 @@ struct BlasArgs {
     double* w1;
     SolverState* st;
     double* part;
+    int red_mode;       // as ColArgs::red_mode
 };
 hipError_t launch_blas(Blas op, const BlasArgs& a, hipStream_t s);
 

@@ -390,8 +390,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
         st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
     }
     double tot[2];
-    if (reduce_last<2>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
-                       &s->ticket, tot)) {
+    if (publish<2>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, a.red_mode, tot)) {
         if (threadIdx.x == 0) finish_prec(s, tot[0], tot[1]);
     }
 }
@@ -438,8 +438,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
         st<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
     }
     double tot[1];
-    if (reduce_last<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
-                       &s->ticket, tot)) {
+    if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, a.red_mode, tot)) {
         if (threadIdx.x == 0) finish_apply(s, tot[0]);
     }
 }
@@ -471,10 +471,12 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
         for (int i = 0; i < M; ++i) uc[i] += alpha * pc[i];
         st<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
     }
-    double acc[1] = {0.0}, tot[1];
-    if (reduce_last<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
-                       &s->ticket, tot)) {
-        if (threadIdx.x == 0) s->fixed = 1;
+    if (a.red_mode == 0) {   // mode 1: the finalize launch marks it done
+        double acc[1] = {0.0}, tot[1];
+        if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, 0, tot)) {
+            if (threadIdx.x == 0) s->fixed = 1;
+        }
     }
 }
 
@@ -507,14 +509,15 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
         }
     }
     double tot[1];
-    if (reduce_last<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
-                       &s->ticket, tot)) {
+    if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, a.red_mode, tot)) {
         if (threadIdx.x == 0) s->aux = sqrt(tot[0]);
     }
 }
 
-// Refinement residual: r64 = b - A x in FP64, ||r64|| into state.rnorm
-// (state.r0norm on the first call), FP32 copy r32 = r64 * scale.
+// Refinement residual: r64 = b - A x in FP64 (r64 = b when a.x0_zero),
+// ||r64|| into state.rnorm (state.r0norm on the first call), FP32 copy
+// r32 = r64 * scale.
 template <int M, bool V>
 __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
 {
@@ -537,9 +540,14 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
         const Col c = make_col(g, tile_col(tile, p, L));
         double xc[M], ax[M], bc[M];
         float rc[M];
-        ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
         ld<double, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
-        stencil<double, M, V>(g, c, p.l, L, p.k0, x, xc, vert, ax);
+        if (a.x0_zero) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) ax[i] = 0.0;
+        } else {
+            ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+            stencil<double, M, V>(g, c, p.l, L, p.k0, x, xc, vert, ax);
+        }
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             const double d = bc[i] - ax[i];
@@ -550,8 +558,8 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
         st<float, M, (V && (M % 4 == 0))>(r32, c.idx, c.ok, p.k0, g.nz, rc);
     }
     double tot[1];
-    if (reduce_last<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
-                       &s->ticket, tot)) {
+    if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, a.red_mode, tot)) {
         if (threadIdx.x == 0) {
             const double rn = sqrt(tot[0]);
             s->rnorm = rn;
@@ -560,7 +568,8 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
     }
 }
 
-// Refinement update: x64 += (1/scale) * u32, u32 being the inner solution.
+// Refinement update: x64 += (1/scale) * u32, u32 being the inner solution
+// (x64 = u32 / scale when a.x0_zero: x is not read).
 template <int M, bool V>
 __global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
 {
@@ -580,12 +589,68 @@ __global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
         const Col c = make_col(g, tile_col(tile, p, L));
         double xc[M];
         float uc[M];
-        ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+        if (a.x0_zero) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) xc[i] = 0.0;
+        } else {
+            ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+        }
         ld<float, M, (V && (M % 4 == 0))>(u32, c.idx, c.ok, p.k0, g.nz, uc);
 #pragma unroll
         for (int i = 0; i < M; ++i) xc[i] += inv_scale * double(uc[i]);
         st<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
     }
+}
+
+// Mode-1 reductions: one workgroup per right-hand side totals the published
+// partial sums in the same order as mode 0 and performs the scalar step.
+template <Kind K>
+__global__ __launch_bounds__(kBlock) void k_finalize(ColArgs a)
+{
+    const int64_t rhs = blockIdx.x;
+    SolverState* s = a.st + rhs;
+    const double* part = a.part + rhs * a.blocks_per_rhs * kRedSlots;
+    if (K == Kind::Fixup) {
+        if (threadIdx.x == 0 && (s->flag == kConverged || s->flag == kMaxIter)) s->fixed = 1;
+        return;
+    }
+    if (K != Kind::TrueResidual && s->flag != kRunning) return;   // main kernel skipped
+    if (K == Kind::FusedPrec) {
+        double tot[2];
+        sum_partials<2, false>(part, a.blocks_per_rhs, tot);
+        if (threadIdx.x == 0) finish_prec(s, tot[0], tot[1]);
+    } else {
+        double tot[1];
+        sum_partials<1, false>(part, a.blocks_per_rhs, tot);
+        if (threadIdx.x == 0) {
+            if (K == Kind::FusedApply) finish_apply(s, tot[0]);
+            else if (K == Kind::TrueResidual) s->aux = sqrt(tot[0]);
+            else if (K == Kind::Residual64) {
+                s->rnorm = sqrt(tot[0]);
+                if (s->iter == 0) s->r0norm = s->rnorm;
+            }
+        }
+    }
+}
+
+bool has_finalize(Kind k)
+{
+    return k == Kind::FusedPrec || k == Kind::FusedApply || k == Kind::Fixup ||
+           k == Kind::TrueResidual || k == Kind::Residual64;
+}
+
+hipError_t launch_finalize(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+{
+    const dim3 grid((unsigned)batch), block(kBlock);
+    switch (kind) {
+    case Kind::FusedPrec: hipLaunchKernelGGL((k_finalize<Kind::FusedPrec>), grid, block, 0, s, a); break;
+    case Kind::FusedApply: hipLaunchKernelGGL((k_finalize<Kind::FusedApply>), grid, block, 0, s, a); break;
+    case Kind::Fixup: hipLaunchKernelGGL((k_finalize<Kind::Fixup>), grid, block, 0, s, a); break;
+    case Kind::TrueResidual: hipLaunchKernelGGL((k_finalize<Kind::TrueResidual>), grid, block, 0, s, a); break;
+    case Kind::Residual64: hipLaunchKernelGGL((k_finalize<Kind::Residual64>), grid, block, 0, s, a); break;
+    default: return hipSuccess;
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- dispatch --
@@ -631,7 +696,7 @@ hipError_t launch_v(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
 }  // namespace
 
 template <typename T>
-hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+hipError_t launch_column_main(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
 {
     const int M = a.L > 0 ? (a.g.nz + a.L - 1) / a.L : 0;
     int Mp = 1;
@@ -646,7 +711,23 @@ hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t
     }
 }
 
+hipError_t launch_column_finalize(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+{
+    if (a.red_mode == 0 || !has_finalize(kind)) return hipSuccess;
+    return launch_finalize(kind, a, batch, s);
+}
+
+template <typename T>
+hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+{
+    hipError_t e = launch_column_main<T>(kind, a, batch, s);
+    if (e != hipSuccess) return e;
+    return launch_column_finalize(kind, a, batch, s);
+}
+
 template hipError_t launch_column<double>(Kind, const ColArgs&, int64_t, hipStream_t);
 template hipError_t launch_column<float>(Kind, const ColArgs&, int64_t, hipStream_t);
+template hipError_t launch_column_main<double>(Kind, const ColArgs&, int64_t, hipStream_t);
+template hipError_t launch_column_main<float>(Kind, const ColArgs&, int64_t, hipStream_t);
 
 }  // namespace pcg

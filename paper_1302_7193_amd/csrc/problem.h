@@ -15,14 +15,18 @@ struct GraphKey {
     int dtype;
     int kind;             // 0: fused iteration chunk, 1: unfused iteration chunk
     int iters;
+    int L;
+    int red_mode;
+    int64_t bpr;
     int64_t nrhs;
     const void* ptrs[8];
     bool operator<(const GraphKey& o) const
     {
-        return std::tie(dtype, kind, iters, nrhs, ptrs[0], ptrs[1], ptrs[2], ptrs[3], ptrs[4],
-                        ptrs[5], ptrs[6], ptrs[7]) <
-               std::tie(o.dtype, o.kind, o.iters, o.nrhs, o.ptrs[0], o.ptrs[1], o.ptrs[2],
-                        o.ptrs[3], o.ptrs[4], o.ptrs[5], o.ptrs[6], o.ptrs[7]);
+        return std::tie(dtype, kind, iters, L, red_mode, bpr, nrhs, ptrs[0], ptrs[1], ptrs[2],
+                        ptrs[3], ptrs[4], ptrs[5], ptrs[6], ptrs[7]) <
+               std::tie(o.dtype, o.kind, o.iters, o.L, o.red_mode, o.bpr, o.nrhs, o.ptrs[0],
+                        o.ptrs[1], o.ptrs[2], o.ptrs[3], o.ptrs[4], o.ptrs[5], o.ptrs[6],
+                        o.ptrs[7]);
     }
 };
 
@@ -38,8 +42,7 @@ struct pcg_problem {
     const double* d_lu64 = nullptr;
     const float* d_vert32 = nullptr;
     const float* d_lu32 = nullptr;
-    pcg::Shape shape[2];                   // launch shape per dtype
-    int64_t block_cap = 2048;              // workgroups per right-hand side
+    pcg::Tuning tune[2];                   // launch parameters per dtype
     int last_iters[2] = {0, 0};            // adaptive chunk length per precision
     pcg::SolverState* pinned_states = nullptr;  // host-pinned staging of solver states
     int64_t pinned_cap = 0;

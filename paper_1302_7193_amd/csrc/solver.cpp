@@ -28,10 +28,15 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int64_t blas_blocks(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>(2048, (n / 2 + kBlock - 1) / kBlock)); }
 
+}  // namespace
+
 int64_t blocks_per_rhs(const pcg_problem* P, int dtype)
 {
-    return std::max<int64_t>(1, std::min(P->block_cap, column_blocks(P->geom, P->shape[dtype])));
+    const Tuning& t = P->tune[dtype];
+    return std::max<int64_t>(1, std::min(t.block_cap, column_blocks(P->geom, t.shape)));
 }
+
+namespace {
 
 struct Layout {
     size_t r = 0, z = 0, p = 0, q = 0;           // FP64 vectors
@@ -62,8 +67,8 @@ Layout plan(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
         w.p = take(8 * n);
         w.q = take(8 * n);
     }
-    const int64_t nb = std::max({blocks_per_rhs(P, PCG_F64), blocks_per_rhs(P, PCG_F32),
-                                 blas_blocks(P->geom.n)});
+    // partial-sum slots for any tuning (block caps never exceed kMaxBlocks)
+    const int64_t nb = std::max(kMaxBlocks, blas_blocks(P->geom.n));
     w.part = take((size_t)nrhs * nb * kRedSlots * sizeof(double));
     w.st = take((size_t)nrhs * sizeof(SolverState));
     w.st_o = take((size_t)nrhs * sizeof(SolverState));
@@ -182,6 +187,9 @@ pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, int64_t nrhs
     key.dtype = dtype;
     key.kind = 0;
     key.iters = K;
+    key.L = a.L;
+    key.red_mode = a.red_mode;
+    key.bpr = a.blocks_per_rhs;
     key.nrhs = nrhs;
     const void* ptrs[8] = {a.io0, a.io1, a.io2, a.io3, a.io4, a.st, a.part, a.lu};
     std::memcpy(key.ptrs, ptrs, sizeof(ptrs));
@@ -241,8 +249,10 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a,
         const size_t i = is_a.size();
         if (ensure_events(P, 2 * i + 2) != PCG_OK) return PCG_E_DEVICE;
         PCG_HIP(hipEventRecord(P->events[2 * i], s), "hipEventRecord");
-        if (launch<T>(k, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
+        PCG_HIP(launch_column_main<T>(k, a, nrhs, s), "kernel launch");
         PCG_HIP(hipEventRecord(P->events[2 * i + 1], s), "hipEventRecord");
+        PCG_HIP(launch_column_finalize(k, a, nrhs, s), "finalize launch");
+        ++info.launches;
         is_a.push_back(kind_a);
         return PCG_OK;
     };
@@ -318,7 +328,8 @@ ColArgs base_args(const pcg_problem* P, int dtype, char* ws, const Layout& w, in
 {
     ColArgs a{};
     a.g = P->geom;
-    a.L = P->shape[dtype].L;
+    a.L = P->tune[dtype].shape.L;
+    a.red_mode = P->tune[dtype].red_mode;
     a.blocks_per_rhs = bpr;
     a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
     a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
@@ -344,7 +355,7 @@ pcg_status solve_fp64(pcg_problem* P, const double* b, double* x, char* ws, cons
     std::vector<SolverState> hs(nrhs, fresh_state(o.rtol, o.atol, o.max_iter, 1.0));
     if (upload_states(P, a.st, hs.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
     RunInfo info;
-    pcg_status st = run_fused<double>(P, PCG_F64, 0, a, nrhs, false, o, hs.data(), info, s);
+    pcg_status st = run_fused<double>(P, PCG_F64, 0, a, nrhs, o.x0_zero != 0, o, hs.data(), info, s);
     if (st != PCG_OK) return st;
     if (o.true_residual) {
         ColArgs t = a;
@@ -390,6 +401,7 @@ pcg_status solve_unfused(pcg_problem* P, const double* b, double* x, char* ws, c
     ba.blocks = blas_blocks(P->geom.n);
     ba.st = dst;
     ba.part = a.part;
+    ba.red_mode = a.red_mode;
     auto blas = [&](Blas op, const double* xx, const double* yy, double* w0) -> pcg_status {
         BlasArgs c = ba;
         c.x = xx;
@@ -411,7 +423,8 @@ pcg_status solve_unfused(pcg_problem* P, const double* b, double* x, char* ws, c
     init.io3 = p;
     init.io4 = q;
     init.st = dst;
-    if (launch<double>(Kind::InitFull, init, 1, s, launches)) return PCG_E_DEVICE;
+    if (launch<double>(o.x0_zero ? Kind::InitZero : Kind::InitFull, init, 1, s, launches))
+        return PCG_E_DEVICE;
     ColArgs pre = a;
     pre.in0 = r;
     pre.io0 = z;
@@ -507,6 +520,7 @@ pcg_status solve_mixed(pcg_problem* P, const double* b, double* x, char* ws, con
             ho[i].flag = done[i] ? kConverged : kRunning;
         }
         if (upload_states(P, st_out, ho.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+        outer.x0_zero = upd.x0_zero = (k == 0 && o.x0_zero) ? 1 : 0;   // x not read yet
         if (launch<double>(Kind::Residual64, outer, nrhs, s, launches)) return PCG_E_DEVICE;
         if (read_states(P, st_out, ho.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
         bool all_done = true;
@@ -590,6 +604,138 @@ pcg_status solve_mixed(pcg_problem* P, const double* b, double* x, char* ws, con
         r.ms_apply_kernel = r.ms_precond_kernel = 0.0;
         r.n_apply_kernel = r.n_precond_kernel = 0;
     }
+    return PCG_OK;
+}
+
+// Time fused iterations of precision T with the problem's current tuning on
+// the workspace vectors (r holds a synthetic right-hand side).  Each rep
+// restarts from x0 = 0 and times the first iteration's kernels B and A, so
+// the timed work never depends on convergence.  Returns ms per iteration.
+template <typename T>
+pcg_status time_tuning(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const Layout& w,
+                       void* u, hipStream_t s, float* ms_per_iter)
+{
+    const int64_t bpr = blocks_per_rhs(P, dtype);
+    ColArgs a = base_args(P, dtype, ws, w, bpr);
+    const bool f64 = dtype == PCG_F64;
+    a.io0 = u;
+    a.io1 = ws + (f64 ? w.r : w.r32);
+    a.io2 = ws + (f64 ? w.z : w.z32);
+    a.io3 = ws + (f64 ? w.p : w.p32);
+    a.io4 = ws + (f64 ? w.q : w.q32);
+    a.in1 = a.io1;                      // zero start in place: r keeps its data
+    a.st = reinterpret_cast<SolverState*>(ws + w.st);
+    const int reps = 4;
+    if (ensure_events(P, 2 * reps) != PCG_OK) return PCG_E_DEVICE;
+    std::vector<SolverState> hs(nrhs, fresh_state(0.0, 0.0, 1 << 30, 1.0));
+    int cnt = 0;
+    for (int i = -1; i < reps; ++i) {   // rep -1 warms up
+        if (upload_states(P, a.st, hs.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+        if (launch<T>(Kind::InitZero, a, nrhs, s, cnt)) return PCG_E_DEVICE;
+        if (i >= 0) PCG_HIP(hipEventRecord(P->events[2 * i], s), "hipEventRecord");
+        if (launch<T>(Kind::FusedPrec, a, nrhs, s, cnt)) return PCG_E_DEVICE;
+        if (launch<T>(Kind::FusedApply, a, nrhs, s, cnt)) return PCG_E_DEVICE;
+        if (i >= 0) PCG_HIP(hipEventRecord(P->events[2 * i + 1], s), "hipEventRecord");
+    }
+    PCG_HIP(hipEventSynchronize(P->events[2 * reps - 1]), "hipEventSynchronize");
+    float total = 0.f;
+    for (int i = 0; i < reps; ++i) {
+        float ms = 0.f;
+        PCG_HIP(hipEventElapsedTime(&ms, P->events[2 * i], P->events[2 * i + 1]),
+                "hipEventElapsedTime");
+        total += ms;
+    }
+    std::vector<SolverState> out(nrhs);
+    if (read_states(P, a.st, out.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+    for (int64_t i = 0; i < nrhs; ++i)
+        if (out[i].flag != kRunning || out[i].iter != 1) {
+            set_error("autotune: the synthetic first iteration did not complete (internal)");
+            return PCG_E_DEVICE;
+        }
+    *ms_per_iter = total / reps;
+    return PCG_OK;
+}
+
+struct DeviceBuffer {
+    void* p = nullptr;
+    ~DeviceBuffer()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const Layout& w,
+                       void* u, hipStream_t s, Tuning* best);
+
+}  // namespace
+
+pcg_status autotune(pcg_problem* P, int dtype, int64_t nrhs, hipStream_t s, Tuning* best)
+{
+    pcg_solve_opts o;
+    pcg_default_opts(&o);
+    o.precision = dtype == PCG_F64 ? PCG_PREC_FP64 : PCG_PREC_MIXED;
+    const Layout w = plan(P, o, nrhs);
+    const size_t ubytes = al256((size_t)P->geom.n * nrhs * (dtype == PCG_F64 ? 8 : 4));
+    DeviceBuffer buf;
+    hipError_t e = hipMalloc(&buf.p, w.total + ubytes);
+    if (e != hipSuccess) {
+        set_error(hip_msg(e, "pcg_autotune: hipMalloc(scratch)"));
+        return PCG_E_NOMEM;
+    }
+    char* ws = static_cast<char*>(buf.p);
+    pcg_status st = autotune_in(P, dtype, nrhs, ws, w, ws + w.total, s, best);
+    (void)hipStreamSynchronize(s);
+    return st;
+}
+
+namespace {
+
+pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const Layout& w,
+                       void* u, hipStream_t s, Tuning* best)
+{
+    // synthetic right-hand side: every 32-bit word 0x3f800000 (1.0f; as FP64
+    // words a positive number near 2^-7), so the iteration does real work
+    const size_t vec_bytes = (size_t)P->geom.n * nrhs * (dtype == PCG_F64 ? 8 : 4);
+    PCG_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ws + (dtype == PCG_F64 ? w.r : w.r32)),
+                              0x3f800000, vec_bytes / 4, s),
+            "hipMemsetD32Async");
+    const Tuning saved = P->tune[dtype];
+    Tuning best_t = saved;
+    float best_ms = 1e30f;
+    const int nz = P->geom.nz;
+    for (int L = 1; L <= kWave; L <<= 1) {
+        Shape sh;
+        sh.L = L;
+        if (!shape_supported(nz, sh)) continue;
+        sh.M = 1;
+        while (sh.M * L < nz) sh.M <<= 1;
+        if (sh.M * L >= 2 * nz && L > 1 && sh.M > 1) continue;   // lanes idle: skip
+        for (int64_t total = 512; total <= 16384; total <<= 1) {
+            const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(kMaxBlocks, total / nrhs));
+            for (int mode = 0; mode < 2; ++mode) {
+                Tuning t;
+                t.shape = sh;
+                t.block_cap = cap;
+                t.red_mode = mode;
+                P->tune[dtype] = t;
+                if (column_blocks(P->geom, sh) < cap && total > 512) continue;  // no change
+                float ms = 0.f;
+                pcg_status st = dtype == PCG_F64
+                                    ? time_tuning<double>(P, dtype, nrhs, ws, w, u, s, &ms)
+                                    : time_tuning<float>(P, dtype, nrhs, ws, w, u, s, &ms);
+                if (st != PCG_OK) {
+                    P->tune[dtype] = saved;
+                    return st;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_t = t;
+                }
+            }
+        }
+    }
+    P->tune[dtype] = best_t;
+    if (best) *best = best_t;
     return PCG_OK;
 }
 

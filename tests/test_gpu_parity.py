@@ -328,3 +328,125 @@ def test_full_size_periodic_workload_sampled():
     print("512x512x128: %d iterations, true residual %.3e (GPU %.3e)"
           % (res["iterations"], true, res["rel_res_true"]))
     assert true < 1.05e-8
+
+
+# ------------------------------------------------------------ tunings --
+
+def _lane_counts(nz):
+    return [L for L in (1, 2, 4, 8, 16, 32, 64) if 16 * L >= nz]
+
+
+@pytest.mark.parametrize("name", ["64x64x32-dir", "13x7x33-dir-ragged", "6x11x100-mixedbc"])
+@pytest.mark.parametrize("dtype", [pcg.PCG_F64, pcg.PCG_F32])
+def test_every_lane_count_and_tiny_block_caps(name, dtype):
+    """Operator and line solve for every supported L, with block caps small
+    enough that each workgroup walks many tiles."""
+    d = GRIDS[name]()
+    print("tunings", name, dtype, flush=True)
+    p = pcg.Problem(d)
+    tdt, u = DT[dtype]
+    A = oracle.assemble(grid_of(d))
+    M = oracle.line_blocks(A, d.nz)
+    absA = oracle.CSR(A.n, A.row_ptr, A.col, np.abs(A.val))
+    x = cuda(si.uniform_pm1(31, p.n), tdt)
+    xr = x.double().cpu().numpy()
+    ref = A.matvec(xr)
+    bound = 64 * u * absA.matvec(np.abs(xr)) + 1e-300
+    zo = oracle.line_solve(M, xr)
+    for L in _lane_counts(d.nz):
+        for cap in (1, 3, 2048):
+            pcg.pcg_set_tuning(p, dtype, lanes_per_column=L, block_cap=cap, reduction=1)
+            y = torch.full_like(x, float("nan"))
+            pcg.pcg_apply(p, dtype, x, y)
+            z = torch.full_like(x, float("nan"))
+            pcg.pcg_precond(p, dtype, x, z)
+            torch.cuda.synchronize()
+            err = np.abs(y.double().cpu().numpy() - ref)
+            assert np.all(err <= bound), (L, cap, (err / bound).max())
+            fwd = np.linalg.norm(z.double().cpu().numpy() - zo) / np.linalg.norm(zo)
+            assert fwd <= (1e-9 if dtype == pcg.PCG_F64 else 1e-3), (L, cap, fwd)
+
+
+@pytest.mark.parametrize("precision", [pcg.PCG_PREC_FP64, pcg.PCG_PREC_MIXED])
+def test_reduction_modes_bitwise_identical(precision):
+    d = GRIDS["13x7x33-dir-ragged"]()
+    b = cuda(si.rhs_uniform(d.nx, d.ny, d.nz, 41))
+    outs = []
+    for mode in (0, 1, 0, 1):
+        for cap in (5,):
+            p = pcg.Problem(d)
+            for dt in (pcg.PCG_F64, pcg.PCG_F32):
+                pcg.pcg_set_tuning(p, dt, block_cap=cap, reduction=mode)
+            o = pcg.pcg_default_opts(precision=precision)
+            x = torch.zeros_like(b)
+            st, r = pcg.pcg_solve(p, b, x, pcg.workspace(p, o), o)
+            assert st == pcg.PCG_OK
+            outs.append((x.cpu(), r["iterations"]))
+    for xo, it in outs[1:]:
+        assert it == outs[0][1] and torch.equal(xo, outs[0][0])
+
+
+@pytest.mark.parametrize("L,cap,mode", [(4, 1, 0), (8, 7, 1), (16, 64, 0), (64, 2048, 1)])
+def test_fp64_solve_parity_under_tunings(L, cap, mode):
+    d = GRIDS["6x11x100-mixedbc"]()
+    b = si.rhs_uniform(d.nx, d.ny, d.nz, 42)
+    A, ref = oracle_run(d, b, rtol=1e-8)
+    k = ref["iterations"]
+    p = pcg.Problem(d)
+    if 16 * L < d.nz:
+        pytest.skip("lane count too small for n_z")
+    pcg.pcg_set_tuning(p, pcg.PCG_F64, lanes_per_column=L, block_cap=cap, reduction=mode)
+    o = pcg.pcg_default_opts(rtol=0.0, max_iter=k)
+    bt = cuda(b)
+    x = torch.zeros_like(bt)
+    st, r = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
+    assert r["iterations"] == k
+    err = np.linalg.norm(x.cpu().numpy() - ref["x"]) / np.linalg.norm(ref["x"])
+    assert err <= 1e-10, err
+
+
+def test_set_tuning_rejects_bad_values():
+    p = pcg.Problem(GRIDS["7x6x1024-tall"]())
+    for bad in (dict(lanes_per_column=32), dict(lanes_per_column=3), dict(block_cap=0),
+                dict(block_cap=20000), dict(reduction=2)):
+        with pytest.raises(pcg.PCGError):
+            pcg.pcg_set_tuning(p, pcg.PCG_F64, **bad)
+    t = pcg.pcg_get_tuning(p, pcg.PCG_F64)
+    assert t.lanes_per_column == 64
+
+
+@pytest.mark.parametrize("dtype,nrhs", [(pcg.PCG_F64, 1), (pcg.PCG_F32, 3)])
+def test_autotune_picks_a_valid_tuning_and_solves(dtype, nrhs):
+    d = GRIDS["64x64x32-dir"]()
+    p = pcg.Problem(d)
+    t = pcg.pcg_autotune(p, dtype, nrhs)
+    assert 16 * t.lanes_per_column >= d.nz and t.block_cap >= 1 and t.reduction in (0, 1)
+    assert pcg.pcg_get_tuning(p, dtype).as_dict() == t.as_dict()
+    b = si.rhs_uniform(d.nx, d.ny, d.nz, 43)
+    prec = pcg.PCG_PREC_FP64 if dtype == pcg.PCG_F64 else pcg.PCG_PREC_MIXED
+    o = pcg.pcg_default_opts(precision=prec)
+    bt = cuda(b)
+    x = torch.zeros_like(bt)
+    st, r = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
+    assert st == pcg.PCG_OK
+    A = oracle.assemble(grid_of(d))
+    assert oracle.residual_norm(A, b, x.cpu().numpy()) / np.linalg.norm(b) < 1.05e-8
+
+
+def test_mixed_precision_zero_start_ignores_x():
+    d = GRIDS["9x5x17-per"]()
+    b = si.rhs_smooth_noise(d.nx, d.ny, d.nz, 2)
+    p = pcg.Problem(d)
+    o = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED, x0_zero=1)
+    bt = cuda(b)
+    x = torch.full_like(bt, 1e30)          # garbage that must not be read
+    st, r = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
+    assert st == pcg.PCG_OK
+    A = oracle.assemble(grid_of(d))
+    true = oracle.residual_norm(A, b, x.cpu().numpy()) / np.linalg.norm(b)
+    assert true < 1e-8 and abs(r["r0_norm"] - np.linalg.norm(b)) < 1e-12 * np.linalg.norm(b)
+    o.precision = pcg.PCG_PREC_FP64
+    x.fill_(1e30)
+    st, r = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
+    assert st == pcg.PCG_OK
+    assert oracle.residual_norm(A, b, x.cpu().numpy()) / np.linalg.norm(b) < 1.05e-8
