@@ -32,8 +32,18 @@ if ROOT not in sys.path:
 METRIC = "unknowns·iter/s + HBM GB/s; mixed vs FP64 @1e-8 resid; served p50/p99 latency"
 PEAK_HBM_GBPS = 8000.0
 # Algorithmic bytes per unknown per launch (FP64): every vector touched once.
+# The first kernel B of a zero-start solve reads b instead of r and q (24 B),
+# the first kernel A reads only z (32 B).
 BYTES = {"fused_apply": 56, "fused_prec": 32, "iteration": 88, "unfused_iteration": 160,
-         "apply": 16, "precond": 16}
+         "apply": 16, "precond": 16, "fused_apply_first": 32, "fused_prec_first": 24}
+
+
+def solve_kernel_bytes(kernel, iterations, n):
+    """Algorithmic bytes of all launches of a fused kernel in one zero-start
+    solve of `iterations` iterations (A runs k times, B k+1 times)."""
+    if kernel == "fused_apply":
+        return n * (BYTES["fused_apply_first"] + BYTES["fused_apply"] * (iterations - 1))
+    return n * (BYTES["fused_prec_first"] + BYTES["fused_prec"] * iterations)
 KERNEL_SYMBOL = {"fused_apply": "k_fused_apply<double, 4, true>",
                  "fused_prec": "k_fused_prec<double, 4, true>"}
 
@@ -315,10 +325,13 @@ def main():
     n, iters, el = m["n"], m["iters"], m["elapsed"]
     value = n * iters / el
     kern = {}
+    its_per_solve = iters // args.steps
     for k in ("fused_apply", "fused_prec"):
         avg = m["ms"][k] / max(m["cnt"][k], 1)
-        achieved = BYTES[k] * n / (avg * 1e-3) / 1e9
+        per_launch = solve_kernel_bytes(k, its_per_solve, n) * args.steps / max(m["cnt"][k], 1)
+        achieved = per_launch / (avg * 1e-3) / 1e9
         kern[k] = dict(avg_ms=avg, launches=m["cnt"][k], achieved_GBps=achieved,
+                       algorithmic_bytes_per_launch=per_launch,
                        total_ms=m["ms"][k], symbol=KERNEL_SYMBOL[k])
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     traffic = measured_traffic(dom, "512x512x128")
@@ -343,7 +356,7 @@ def main():
                      "achieved": kern[dom]["achieved_GBps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": kern[dom]["achieved_GBps"] / PEAK_HBM_GBPS,
                      "traffic": traffic,
-                     "algorithmic_bytes_per_launch": BYTES[dom] * n,
+                     "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes_per_launch"],
                      "avg_launch_ms": kern[dom]["avg_ms"]},
         "kernels": kern,
         "algorithmic_GBps_per_iteration": BYTES["iteration"] * n * iters / el / 1e9,

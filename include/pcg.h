@@ -212,6 +212,61 @@ pcg_status pcg_csr_build(pcg_problem *p, int32_t dtype, void *buf, size_t bytes,
 pcg_status pcg_csr_apply(pcg_problem *p, int32_t dtype, const void *buf, const void *x,
                          void *y, void *stream);
 
+/* ------------------------------------------------------------ serving --
+ * Continuous batching of independent solves with different grids and
+ * coefficients.  pcg_submit queues a request and returns at once; worker
+ * threads (max_active of them, one HIP stream each) admit queued requests in
+ * arrival order whenever a worker is idle and the request's device bytes
+ * (pcg_request_bytes) keep the admitted total within hbm_budget_bytes and
+ * fit in the caller's device arena; an admitted request is copied in, solved
+ * by the fused iteration from x0 = 0 (HIP-graph-captured chunks), copied out
+ * and its memory released, which admits the next.  Requests overlap on the
+ * device.  A request's arithmetic depends only on its own descriptor and
+ * options, so its result is the same alone and in any mix.  The library
+ * allocates no device memory for requests beyond the arena (it does create
+ * small per-shape problem tables).  All server calls are thread-safe. */
+typedef struct {
+    size_t hbm_budget_bytes; /* admitted requests' bytes stay within this (and the arena) */
+    int32_t max_active;      /* requests solved concurrently, 1..64                  */
+    int32_t reserved;
+} pcg_server_opts;
+
+typedef struct {
+    uint64_t submitted, completed, cancelled, rejected;
+    int32_t queued, active;
+    size_t bytes_in_use, peak_bytes_in_use;
+} pcg_server_stats;
+
+/* Device bytes one request needs: b, x and its workspace (0 if invalid). */
+size_t pcg_request_bytes(const pcg_problem_desc *desc, const pcg_solve_opts *opts);
+
+/* arena: caller-owned device memory, 256-byte aligned, arena_bytes long;
+ * it must outlive the server.  Starts the worker threads on the current
+ * device. */
+pcg_status pcg_server_create(const pcg_server_opts *opts, void *arena, size_t arena_bytes,
+                             pcg_server **out);
+
+/* Queue a solve.  b_host (read) and x_host (written) are host arrays of
+ * n FP64 values that must stay valid until pcg_poll/pcg_wait reports the
+ * ticket finished (pinned memory makes the copies faster).  opts may be
+ * NULL (defaults); the solve always starts from x0 = 0.  PCG_E_NOMEM if the
+ * request can never fit the budget or the arena. */
+pcg_status pcg_submit(pcg_server *s, const pcg_problem_desc *desc, const pcg_solve_opts *opts,
+                      const double *b_host, double *x_host, uint64_t *ticket);
+
+/* PCG_E_AGAIN while queued or running; otherwise the solve's status with
+ * *out filled (elapsed_ms = submission to completion) and the ticket
+ * released; PCG_E_CANCELLED for a cancelled request. */
+pcg_status pcg_poll(pcg_server *s, uint64_t ticket, pcg_result *out);
+pcg_status pcg_wait(pcg_server *s, uint64_t ticket, pcg_result *out); /* blocking poll */
+
+/* Cancel a request that is still queued (PCG_E_AGAIN once it runs). */
+pcg_status pcg_cancel(pcg_server *s, uint64_t ticket);
+pcg_status pcg_server_query(pcg_server *s, pcg_server_stats *out);
+
+/* Cancels queued requests, waits for running ones, stops the workers. */
+void pcg_server_destroy(pcg_server *s);
+
 /* Thread-local message of the last failing call (NUL-terminated, truncated
  * to n bytes); returns the full length. */
 size_t pcg_last_error(char *buf, size_t n);

@@ -59,6 +59,21 @@ class pcg_tuning(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class pcg_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class pcg_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("cancelled", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("queued", ctypes.c_int32), ("active", ctypes.c_int32),
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes_in_use", ctypes.c_size_t)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class pcg_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("outer_iterations", ctypes.c_int32), ("launches", ctypes.c_int32),
@@ -94,6 +109,17 @@ _sig = {
     "pcg_get_tuning": (_S, [_P, ctypes.c_int32, ctypes.POINTER(pcg_tuning)]),
     "pcg_set_tuning": (_S, [_P, ctypes.c_int32, ctypes.POINTER(pcg_tuning)]),
     "pcg_autotune": (_S, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(pcg_tuning)]),
+    "pcg_request_bytes": (ctypes.c_size_t, [ctypes.POINTER(pcg_problem_desc),
+                                            ctypes.POINTER(pcg_solve_opts)]),
+    "pcg_server_create": (_S, [ctypes.POINTER(pcg_server_opts), _P, ctypes.c_size_t,
+                               ctypes.POINTER(_P)]),
+    "pcg_submit": (_S, [_P, ctypes.POINTER(pcg_problem_desc), ctypes.POINTER(pcg_solve_opts),
+                        _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "pcg_poll": (_S, [_P, ctypes.c_uint64, ctypes.POINTER(pcg_result)]),
+    "pcg_wait": (_S, [_P, ctypes.c_uint64, ctypes.POINTER(pcg_result)]),
+    "pcg_cancel": (_S, [_P, ctypes.c_uint64]),
+    "pcg_server_query": (_S, [_P, ctypes.POINTER(pcg_server_stats)]),
+    "pcg_server_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -289,3 +315,101 @@ def solve(desc: pcg_problem_desc, b: torch.Tensor, x0: torch.Tensor | None = Non
     st, res = pcg_solve(p, b, x, ws, o)
     torch.cuda.synchronize()
     return x, st, res
+
+
+# ---------------------------------------------------------------- serving --
+
+def pcg_request_bytes(desc: pcg_problem_desc, opts: pcg_solve_opts | None = None) -> int:
+    return _lib.pcg_request_bytes(ctypes.byref(desc), ctypes.byref(opts) if opts else None)
+
+
+def _host_vec(a, n: int, what: str) -> int:
+    """Host FP64 array (numpy or CPU torch tensor) of at least n values."""
+    if isinstance(a, torch.Tensor):
+        if a.is_cuda or a.dtype != torch.float64 or not a.is_contiguous() or a.numel() < n:
+            raise ValueError("%s must be a contiguous CPU float64 tensor with >= %d values" % (what, n))
+        return a.data_ptr()
+    import numpy as np
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous \
+            or a.size < n:
+        raise ValueError("%s must be a contiguous float64 array with >= %d values" % (what, n))
+    return a.ctypes.data
+
+
+class Server:
+    """Owning handle of a pcg_server.  Keeps every submitted request's host
+    arrays alive until the request is collected."""
+
+    def __init__(self, arena: torch.Tensor, hbm_budget_bytes: int, max_active: int = 4):
+        self.arena = arena
+        o = pcg_server_opts(hbm_budget_bytes=hbm_budget_bytes, max_active=max_active)
+        h = _P()
+        nbytes = arena.numel() * arena.element_size()
+        _check(_lib.pcg_server_create(ctypes.byref(o), _buf(arena, nbytes, "arena"), nbytes,
+                                      ctypes.byref(h)), "pcg_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.pcg_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        self.close()
+
+
+def pcg_server_create(arena: torch.Tensor, hbm_budget_bytes: int, max_active: int = 4) -> Server:
+    return Server(arena, hbm_budget_bytes, max_active)
+
+
+def pcg_server_destroy(s: Server) -> None:
+    s.close()
+
+
+def pcg_submit(s: Server, desc: pcg_problem_desc, b_host, x_host,
+               opts: pcg_solve_opts | None = None) -> int:
+    n = desc.nx * desc.ny * desc.nz
+    t = ctypes.c_uint64()
+    _check(_lib.pcg_submit(s.handle, ctypes.byref(desc), ctypes.byref(opts) if opts else None,
+                           _host_vec(b_host, n, "b_host"), _host_vec(x_host, n, "x_host"),
+                           ctypes.byref(t)), "pcg_submit")
+    s._keep[t.value] = (b_host, x_host)
+    return t.value
+
+
+def pcg_poll(s: Server, ticket: int):
+    """Returns (status, result dict or None); status PCG_E_AGAIN while pending."""
+    r = pcg_result()
+    st = _lib.pcg_poll(s.handle, ticket, ctypes.byref(r))
+    if st == PCG_E_AGAIN:
+        return st, None
+    s._keep.pop(ticket, None)
+    if st == PCG_E_CANCELLED:
+        return st, None
+    _check(st, "pcg_poll")
+    return st, r.as_dict()
+
+
+def pcg_wait(s: Server, ticket: int):
+    r = pcg_result()
+    st = _lib.pcg_wait(s.handle, ticket, ctypes.byref(r))
+    s._keep.pop(ticket, None)
+    if st == PCG_E_CANCELLED:
+        return st, None
+    _check(st, "pcg_wait")
+    return st, r.as_dict()
+
+
+def pcg_cancel(s: Server, ticket: int) -> int:
+    st = _lib.pcg_cancel(s.handle, ticket)
+    if st == PCG_OK:
+        s._keep.pop(ticket, None)
+    return st
+
+
+def pcg_server_query(s: Server) -> dict:
+    st = pcg_server_stats()
+    _check(_lib.pcg_server_query(s.handle, ctypes.byref(st)), "pcg_server_query")
+    return st.as_dict()

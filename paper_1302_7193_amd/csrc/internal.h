@@ -45,7 +45,8 @@ struct alignas(128) SolverState {
     int32_t max_iter;
     int32_t fixed;     // exit correction x += alpha*p applied
     uint32_t ticket;   // last-workgroup counter of the current reduction
-    int32_t pad[3];
+    int32_t zero_start;// x0 = 0: the first kernel B reads b, x is not read
+    int32_t pad[2];
 };
 
 // Per-column geometry of the flat tensor-product grid.  The paper's
@@ -91,8 +92,8 @@ struct Tuning {
 enum class Kind : int {
     Apply,        // y = A x
     Precond,      // z = M^{-1} r
-    InitFull,     // r = b - A x, p = q = 0, state reset
-    InitZero,     // r = b, x = 0, p = q = 0, state reset
+    InitFull,     // r = b - A x
+    InitZero,     // r = b, x = 0, p = q = 0 (unfused start)
     FusedPrec,    // kernel B: r -= alpha q; z = M^{-1} r; R, kappa; exit test; beta
     FusedApply,   // kernel A: x += alpha p; p = z + beta p; q = A z + beta q; sigma; alpha
     Fixup,        // x += alpha p once, after the exit test fired

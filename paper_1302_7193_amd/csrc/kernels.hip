@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
     }
 }
 
-// r = b - A x (ZERO: x = 0, r = b; nothing to copy when b is r), p = q = 0.
+// r = b - A x; ZERO: x = 0, r = b (nothing to copy when b is r), p = q = 0.
 template <typename T, int M, bool V, bool ZERO>
 __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
 {
@@ -347,24 +347,29 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
             for (int i = 0; i < M; ++i) rc[i] = bc[i] - ax[i];
             st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
         }
-        st<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, zero);
-        st<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, zero);
+        if (ZERO) {   // the unfused iteration reads p and q; the fused one does not
+            st<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, zero);
+            st<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, zero);
+        }
     }
 }
 
 // Kernel B (Alg. InterleavedPrec): r -= alpha q; z = M^{-1} r;
-// R = <r,r>, kappa = <r,z> (FP64 accumulation); last workgroup: exit test, beta.
-template <typename T, int M, bool V>
-__global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
+// R = <r,r>, kappa = <r,z> (FP64 accumulation); scalar step: exit test, beta.
+// FIRST (no iteration done yet): alpha = 0 and q is unset, so q is not read;
+// with a zero start r is taken from b (no start-up kernel), and not stored
+// when b is r itself.
+template <typename T, int M, bool V, bool FIRST>
+__device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s, int64_t rhs,
+                                                int64_t blk, double (&acc)[2])
 {
     const Geom& g = a.g;
     const int L = a.L;
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
-    SolverState* s = a.st + rhs;
-    if (s->flag != kRunning) return;
     const int64_t off = rhs * g.n;
+    const bool from_b = FIRST && s->zero_start;
+    const T* src = static_cast<const T*>(from_b ? a.in1 : a.io1) + off;
     T* r = static_cast<T*>(a.io1) + off;
+    const bool store_r = !(from_b && a.in1 == a.io1);
     T* z = static_cast<T*>(a.io2) + off;
     const T* q = static_cast<const T*>(a.io4) + off;
     const T* lu = static_cast<const T*>(a.lu);
@@ -372,41 +377,53 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
     const Lane p = lane_pos<M>(L);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
-    double acc[2] = {0.0, 0.0};
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col(g, tile_col(tile, p, L));
-        T rc[M], qc[M], zc[M];
-        ld<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
-        ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+        T rc[M], zc[M];
+        ld<T, M, V>(src, c.idx, c.ok, p.k0, g.nz, rc);
+        if (!FIRST) {
+            T qc[M];
+            ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-            rc[i] = rc[i] - alpha * qc[i];
-            acc[0] += double(rc[i]) * double(rc[i]);
+            for (int i = 0; i < M; ++i) rc[i] = rc[i] - alpha * qc[i];
         }
-        st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc[0] += double(rc[i]) * double(rc[i]);
+        if (!FIRST || store_r) st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
         line_solve<T, M, V>(g, c, p.l, L, p.k0, lu, rc, zc);
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[1] += double(rc[i]) * double(zc[i]);
         st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
     }
+}
+
+template <typename T, int M, bool V>
+__global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
+{
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    if (s->flag != kRunning) return;
+    double acc[2] = {0.0, 0.0};
+    if (s->iter == 0) fused_prec_body<T, M, V, true>(a, s, rhs, blk, acc);
+    else fused_prec_body<T, M, V, false>(a, s, rhs, blk, acc);
     double tot[2];
     if (publish<2>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
-                       &s->ticket, a.red_mode, tot)) {
+                   &s->ticket, a.red_mode, tot)) {
         if (threadIdx.x == 0) finish_prec(s, tot[0], tot[1]);
     }
 }
 
 // Kernel A (Alg. InterleavedApply): u += alpha p; p = z + beta p;
-// q = A z + beta q; sigma = <p,q> (FP64); last workgroup: alpha.
-template <typename T, int M, bool V>
-__global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
+// q = A z + beta q; sigma = <p,q> (FP64); scalar step: alpha.
+// FIRST: alpha = 0 and p = q = 0, so p = z, q = A z, and u keeps x0 (written
+// as zero for a zero start); u, p and q are not read.
+template <typename T, int M, bool V, bool FIRST>
+__device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* s, int64_t rhs,
+                                                 int64_t blk, double (&acc)[1])
 {
     const Geom& g = a.g;
     const int L = a.L;
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
-    SolverState* s = a.st + rhs;
-    if (s->flag != kRunning) return;
     const int64_t off = rhs * g.n;
     T* u = static_cast<T*>(a.io0) + off;
     const T* z = static_cast<const T*>(a.io2) + off;
@@ -414,38 +431,67 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
     T* q = static_cast<T*>(a.io4) + off;
     const T* vert = static_cast<const T*>(a.vert);
     const T alpha = T(s->alpha), beta = T(s->beta);
+    const bool zero_u = FIRST && s->zero_start;
     const Lane p = lane_pos<M>(L);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
-    double acc[1] = {0.0};
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col(g, tile_col(tile, p, L));
-        T zc[M], az[M], uc[M], pc[M], qc[M];
+        T zc[M], az[M], pc[M], qc[M];
         ld<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
         stencil<T, M, V>(g, c, p.l, L, p.k0, z, zc, vert, az);
-        ld<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
-        ld<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
-        ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+        if (FIRST) {
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-            uc[i] = uc[i] + alpha * pc[i];
-            pc[i] = zc[i] + beta * pc[i];
-            qc[i] = az[i] + beta * qc[i];
-            acc[0] += double(pc[i]) * double(qc[i]);
+            for (int i = 0; i < M; ++i) {
+                pc[i] = zc[i];
+                qc[i] = az[i];
+                acc[0] += double(pc[i]) * double(qc[i]);
+            }
+            if (zero_u) {
+                T zero[M];
+#pragma unroll
+                for (int i = 0; i < M; ++i) zero[i] = T(0);
+                st<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, zero);
+            }
+        } else {
+            T uc[M];
+            ld<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
+            ld<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
+            ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                uc[i] = uc[i] + alpha * pc[i];
+                pc[i] = zc[i] + beta * pc[i];
+                qc[i] = az[i] + beta * qc[i];
+                acc[0] += double(pc[i]) * double(qc[i]);
+            }
+            st<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
         }
-        st<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
         st<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
         st<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
     }
+}
+
+template <typename T, int M, bool V>
+__global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
+{
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    if (s->flag != kRunning) return;
+    double acc[1] = {0.0};
+    if (s->iter == 0) fused_apply_body<T, M, V, true>(a, s, rhs, blk, acc);
+    else fused_apply_body<T, M, V, false>(a, s, rhs, blk, acc);
     double tot[1];
     if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
-                       &s->ticket, a.red_mode, tot)) {
+                   &s->ticket, a.red_mode, tot)) {
         if (threadIdx.x == 0) finish_apply(s, tot[0]);
     }
 }
 
 // Exit correction u += alpha p (the fused iteration leaves u one step
-// behind r).  Runs once: the last workgroup marks it done.
+// behind r).  Runs once: the last workgroup (or the finalize launch) marks
+// it done.
 template <typename T, int M, bool V>
 __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
 {
@@ -454,7 +500,13 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
-    if (!(s->flag == kConverged || s->flag == kMaxIter) || s->fixed) return;
+    // stopped before the first iteration: x = x0 (zero for a zero start, which
+    // nothing has written yet -- also after a breakdown in the first kernel)
+    const bool none = s->iter == 0;
+    const bool stopped = s->flag == kConverged || s->flag == kMaxIter ||
+                         (s->flag == kBreakdown && none);
+    if (!stopped || s->fixed) return;
+    if (none && !s->zero_start) return;
     const int64_t off = rhs * g.n;
     T* u = static_cast<T*>(a.io0) + off;
     const T* pp = static_cast<const T*>(a.io3) + off;
@@ -464,11 +516,17 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col(g, tile_col(tile, p, L));
-        T uc[M], pc[M];
-        ld<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
-        ld<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
+        T uc[M];
+        if (none) {
 #pragma unroll
-        for (int i = 0; i < M; ++i) uc[i] += alpha * pc[i];
+            for (int i = 0; i < M; ++i) uc[i] = T(0);
+        } else {
+            T pc[M];
+            ld<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
+            ld<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
+#pragma unroll
+            for (int i = 0; i < M; ++i) uc[i] += alpha * pc[i];
+        }
         st<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
     }
     if (a.red_mode == 0) {   // mode 1: the finalize launch marks it done
@@ -611,7 +669,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(ColArgs a)
     SolverState* s = a.st + rhs;
     const double* part = a.part + rhs * a.blocks_per_rhs * kRedSlots;
     if (K == Kind::Fixup) {
-        if (threadIdx.x == 0 && (s->flag == kConverged || s->flag == kMaxIter)) s->fixed = 1;
+        if (threadIdx.x == 0 && (s->flag == kConverged || s->flag == kMaxIter ||
+                                 (s->flag == kBreakdown && s->iter == 0)))
+            s->fixed = 1;
         return;
     }
     if (K != Kind::TrueResidual && s->flag != kRunning) return;   // main kernel skipped

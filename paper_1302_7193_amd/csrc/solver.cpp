@@ -45,7 +45,7 @@ struct Layout {
     size_t total = 0;
 };
 
-Layout plan(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
+Layout plan_n(int64_t cells, const pcg_solve_opts& o, int64_t nrhs)
 {
     Layout w;
     size_t off = 0;
@@ -54,7 +54,7 @@ Layout plan(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
         off += al256(bytes);
         return at;
     };
-    const size_t n = (size_t)P->geom.n * (size_t)nrhs;
+    const size_t n = (size_t)cells * (size_t)nrhs;
     if (o.precision == PCG_PREC_MIXED) {
         w.r32 = take(4 * n);
         w.z32 = take(4 * n);
@@ -68,12 +68,17 @@ Layout plan(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
         w.q = take(8 * n);
     }
     // partial-sum slots for any tuning (block caps never exceed kMaxBlocks)
-    const int64_t nb = std::max(kMaxBlocks, blas_blocks(P->geom.n));
+    const int64_t nb = std::max(kMaxBlocks, blas_blocks(cells));
     w.part = take((size_t)nrhs * nb * kRedSlots * sizeof(double));
     w.st = take((size_t)nrhs * sizeof(SolverState));
     w.st_o = take((size_t)nrhs * sizeof(SolverState));
     w.total = off;
     return w;
+}
+
+Layout plan(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
+{
+    return plan_n(P->geom.n, o, nrhs);
 }
 
 std::string hip_msg(hipError_t e, const char* what)
@@ -228,7 +233,8 @@ struct RunInfo {
 };
 
 // Fused Krylov engine for nrhs right-hand sides of precision T.  The states
-// at a.st must hold fresh_state() values; `zero_start` selects x0 = 0.
+// at a.st must hold fresh_state() values with zero_start set as `zero_start`
+// (x0 = 0: x is not read and the first kernel B takes r from b = a.in1).
 template <typename T>
 pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a, int64_t nrhs,
                      bool zero_start, const pcg_solve_opts& o, SolverState* host_states,
@@ -240,8 +246,8 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a,
     K = std::min(K, std::max(1, o.max_iter));
     const bool use_graph = o.graph_chunk != 0 && !profile;
 
-    if (launch<T>(zero_start ? Kind::InitZero : Kind::InitFull, a, nrhs, s, info.launches))
-        return PCG_E_DEVICE;
+    // zero start: the first kernel B reads b itself; otherwise r = b - A x0
+    if (!zero_start && launch<T>(Kind::InitFull, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
 
     // profile: launch i of kind is_a[i] is bracketed by events 2i and 2i+1
     std::vector<char> is_a;
@@ -353,6 +359,7 @@ pcg_status solve_fp64(pcg_problem* P, const double* b, double* x, char* ws, cons
     a.io4 = ws + w.q;
     a.st = reinterpret_cast<SolverState*>(ws + w.st);
     std::vector<SolverState> hs(nrhs, fresh_state(o.rtol, o.atol, o.max_iter, 1.0));
+    for (auto& h : hs) h.zero_start = o.x0_zero != 0;
     if (upload_states(P, a.st, hs.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
     RunInfo info;
     pcg_status st = run_fused<double>(P, PCG_F64, 0, a, nrhs, o.x0_zero != 0, o, hs.data(), info, s);
@@ -563,6 +570,7 @@ pcg_status solve_mixed(pcg_problem* P, const double* b, double* x, char* ws, con
             const int budget = std::max(1, o.max_iter - inner_iters[i]);
             hi[i] = fresh_state(o.inner_rtol, 0.0, budget, 1.0);
             hi[i].flag = done[i] ? kConverged : kRunning;
+            hi[i].zero_start = 1;
         }
         if (upload_states(P, st_in, hi.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
         pcg_solve_opts io = o;
@@ -627,7 +635,10 @@ pcg_status time_tuning(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
     a.st = reinterpret_cast<SolverState*>(ws + w.st);
     const int reps = 4;
     if (ensure_events(P, 2 * reps) != PCG_OK) return PCG_E_DEVICE;
+    // iter = 1: time the general kernels (alpha = beta = 0, p = q = 0 after
+    // the start kernel), not the first-iteration specialisations
     std::vector<SolverState> hs(nrhs, fresh_state(0.0, 0.0, 1 << 30, 1.0));
+    for (auto& h : hs) h.iter = 1;
     int cnt = 0;
     for (int i = -1; i < reps; ++i) {   // rep -1 warms up
         if (upload_states(P, a.st, hs.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
@@ -648,7 +659,7 @@ pcg_status time_tuning(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
     std::vector<SolverState> out(nrhs);
     if (read_states(P, a.st, out.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
     for (int64_t i = 0; i < nrhs; ++i)
-        if (out[i].flag != kRunning || out[i].iter != 1) {
+        if (out[i].flag != kRunning || out[i].iter != 2) {
             set_error("autotune: the synthetic first iteration did not complete (internal)");
             return PCG_E_DEVICE;
         }
@@ -740,6 +751,11 @@ pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
 }
 
 }  // namespace
+
+size_t request_bytes(int64_t n, const pcg_solve_opts& o)
+{
+    return plan_n(n, o, 1).total;
+}
 
 size_t workspace_bytes(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
 {

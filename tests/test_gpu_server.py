@@ -1,0 +1,132 @@
+"""Serving runtime on the GPU, through the C ABI: results identical alone and
+in a concurrent mix of different grids (and identical to a direct solve),
+admission by HBM budget, rejection of requests that can never fit,
+cancellation of queued requests.  Accuracy of every served result is checked
+with the oracle's assembled matrix."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1302_7193_amd as pcg  # noqa: E402
+import synth_inputs as si  # noqa: E402
+
+SHAPES = [(32, 32, 32, 1e2), (48, 40, 64, 1e4), (16, 16, 128, 1e5), (64, 64, 32, 3e3),
+          (24, 20, 100, 1e3), (40, 40, 16, 1e2), (20, 36, 64, 5e4), (32, 32, 32, 1e2)]
+
+
+def requests(precision=pcg.PCG_PREC_MIXED):
+    out = []
+    for rid, (nx, ny, nz, g2) in enumerate(SHAPES):
+        d = pcg.pcg_desc_from_ratio(nx, ny, nz, 1.05, g2, pcg.PCG_BC_DIRICHLET)
+        b = si.rhs_uniform(nx, ny, nz, 1000 + rid)
+        out.append((d, b))
+    return out, pcg.pcg_default_opts(precision=precision)
+
+
+def serve(reqs, opts, max_active, budget=None, one_at_a_time=False):
+    need = max(pcg.pcg_request_bytes(d, opts) for d, _ in reqs)
+    arena = torch.empty(sum(pcg.pcg_request_bytes(d, opts) for d, _ in reqs) + (1 << 20),
+                        dtype=torch.uint8, device="cuda")
+    srv = pcg.Server(arena, budget or arena.numel(), max_active)
+    xs, res = [None] * len(reqs), [None] * len(reqs)
+    try:
+        if one_at_a_time:
+            for i, (d, b) in enumerate(reqs):
+                xs[i] = np.zeros_like(b)
+                t = pcg.pcg_submit(srv, d, b, xs[i], opts)
+                st, res[i] = pcg.pcg_wait(srv, t)
+                assert st == pcg.PCG_OK, res[i]
+        else:
+            tickets = []
+            for i, (d, b) in enumerate(reqs):
+                xs[i] = np.zeros_like(b)
+                tickets.append(pcg.pcg_submit(srv, d, b, xs[i], opts))
+            pending = set(range(len(reqs)))
+            deadline = time.time() + 120
+            while pending and time.time() < deadline:
+                for i in list(pending):
+                    st, r = pcg.pcg_poll(srv, tickets[i])
+                    if st != pcg.PCG_E_AGAIN:
+                        assert st == pcg.PCG_OK, r
+                        res[i] = r
+                        pending.discard(i)
+                time.sleep(0.001)
+            assert not pending
+        stats = pcg.pcg_server_query(srv)
+    finally:
+        srv.close()
+    return xs, res, stats, need
+
+
+@pytest.mark.parametrize("precision", [pcg.PCG_PREC_MIXED, pcg.PCG_PREC_FP64])
+def test_results_identical_alone_and_in_the_mix(precision):
+    reqs, opts = requests(precision)
+    alone, ra, _, _ = serve(reqs, opts, max_active=1, one_at_a_time=True)
+    mixed, rm, stats, _ = serve(reqs, opts, max_active=4)
+    assert stats["completed"] == len(reqs) and stats["peak_bytes_in_use"] > 0
+    for i, (d, b) in enumerate(reqs):
+        np.testing.assert_array_equal(alone[i], mixed[i])
+        assert ra[i]["iterations"] == rm[i]["iterations"]
+        g = oracle.Grid(d.nx, d.ny, d.nz, d.dx, d.dy, d.height, d.grading, d.k_h, d.k_v,
+                        False, False)
+        A = oracle.assemble(g)
+        true = oracle.residual_norm(A, b, mixed[i]) / np.linalg.norm(b)
+        assert true < 1.05e-8, (i, true)
+        assert rm[i]["elapsed_ms"] > 0
+
+
+def test_served_result_equals_direct_solve():
+    reqs, opts = requests()
+    d, b = reqs[1]
+    xs, _, _, _ = serve([reqs[1]], opts, max_active=2)
+    p = pcg.Problem(d)
+    o = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED, x0_zero=1)
+    bt = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(bt)
+    st, r = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
+    assert st == pcg.PCG_OK
+    np.testing.assert_array_equal(x.cpu().numpy(), xs[0])
+
+
+def test_admission_by_budget():
+    reqs, opts = requests()
+    need = max(pcg.pcg_request_bytes(d, opts) for d, _ in reqs)
+    xs, res, stats, _ = serve(reqs, opts, max_active=4, budget=need)
+    assert stats["completed"] == len(reqs)
+    assert stats["peak_bytes_in_use"] <= need        # at most what fits in the budget at once
+
+
+def test_oversize_request_rejected_and_cancel_queued():
+    reqs, opts = requests()
+    arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    small = min(pcg.pcg_request_bytes(d, opts) for d, _ in reqs)
+    srv = pcg.Server(arena, small, max_active=1)
+    try:
+        big = pcg.pcg_desc_from_ratio(256, 256, 64, 1.05, 1e3, pcg.PCG_BC_DIRICHLET)
+        bb = np.zeros(256 * 256 * 64)
+        with pytest.raises(pcg.PCGError) as e:
+            pcg.pcg_submit(srv, big, bb, np.zeros_like(bb), opts)
+        assert e.value.status == pcg.PCG_E_NOMEM
+        # one worker: the second of two requests queues behind the first
+        d0, b0 = min(reqs, key=lambda r: pcg.pcg_request_bytes(r[0], opts))
+        x0, x1 = np.zeros_like(b0), np.zeros_like(b0)
+        t0 = pcg.pcg_submit(srv, d0, b0, x0, opts)
+        t1 = pcg.pcg_submit(srv, d0, b0, x1, opts)
+        c = pcg.pcg_cancel(srv, t1)
+        assert c in (pcg.PCG_OK, pcg.PCG_E_AGAIN)
+        st, r = pcg.pcg_wait(srv, t0)
+        assert st == pcg.PCG_OK
+        st1, _ = pcg.pcg_wait(srv, t1)
+        assert st1 == (pcg.PCG_E_CANCELLED if c == pcg.PCG_OK else pcg.PCG_OK)
+        stats = pcg.pcg_server_query(srv)
+        assert stats["rejected"] == 1 and stats["queued"] == 0 and stats["active"] == 0
+    finally:
+        srv.close()
