@@ -196,8 +196,7 @@ def extras(pcg, si, torch, main):
     # mixed precision vs plain FP64 on 1024 x 1024 x 128
     d3 = pcg.pcg_desc_from_ratio(1024, 1024, 128, 1.05, 1e4, pcg.PCG_BC_DIRICHLET)
     P3 = pcg.Problem(d3)
-    log("generating 1024x1024x128 right-hand side")
-    b3 = torch.from_numpy(si.rhs_smooth_noise(1024, 1024, 128, 2)).cuda()
+    b3 = si.rhs_smooth_noise_torch(1024, 1024, 128, 2)
     x3 = torch.empty_like(b3)
     res3 = {}
     for name, o in (("fp64", pcg.pcg_default_opts(x0_zero=1, true_residual=1)),
@@ -213,6 +212,9 @@ def extras(pcg, si, torch, main):
     out["mixed_1024x1024x128"] = res3
     del P3, b3, x3
 
+    out["batched_256x256x64x64"] = batched(pcg, si, torch)
+    out["serving_512_requests"] = serving(pcg, si, torch)
+
     # plain copy kernel: attainable HBM bandwidth
     a = torch.empty(1 << 29, dtype=torch.float64, device="cuda")   # 4 GiB
     c = torch.empty_like(a)
@@ -220,6 +222,105 @@ def extras(pcg, si, torch, main):
     out["hbm_copy_probe_GBps"] = 2 * a.numel() * 8 / (t_cp * 1e-3) / 1e9
     del a, c
     return out
+
+
+def batched(pcg, si, torch, nrhs=64):
+    """64 right-hand sides (seeds 100..163) on one 256 x 256 x 64 Dirichlet
+    operator (anisotropy 1e3): mixed precision, every kernel launched once for
+    all right-hand sides, launch parameters from the autotuner."""
+    d = pcg.pcg_desc_from_ratio(256, 256, 64, 1.05, 1e3, pcg.PCG_BC_DIRICHLET)
+    P = pcg.Problem(d)
+    n = P.n
+    B = torch.empty(nrhs * n, dtype=torch.float64, device="cuda")
+    for s_ in range(nrhs):
+        si.rhs_uniform_torch(256, 256, 64, 100 + s_, out=B[s_ * n:(s_ + 1) * n])
+    X = torch.empty_like(B)
+    t32 = pcg.pcg_autotune(P, pcg.PCG_F32, nrhs).as_dict()
+    t64 = pcg.pcg_autotune(P, pcg.PCG_F64, nrhs).as_dict()
+    out = {"nrhs": nrhs, "unknowns_per_rhs": n, "tuning_fp32": t32, "tuning_fp64": t64}
+    for name, o in (("mixed", pcg.pcg_default_opts(x0_zero=1, precision=pcg.PCG_PREC_MIXED)),
+                    ("fp64", pcg.pcg_default_opts(x0_zero=1, true_residual=1))):
+        ws = pcg.workspace(P, o, nrhs)
+        pcg.pcg_solve_batched(P, nrhs, B, X, ws, o)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st, res = pcg.pcg_solve_batched(P, nrhs, B, X, ws, o)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        its = [r["iterations"] for r in res]
+        out[name] = dict(ms_per_batched_solve=ms, status=pcg.STATUS_NAMES[st],
+                         all_ok=all(r["status"] == 0 for r in res),
+                         iterations_mean=sum(its) / nrhs, iterations_max=max(its),
+                         outer_max=max(r["outer_iterations"] for r in res),
+                         max_rel_res_true=max(r["rel_res_true"] for r in res),
+                         rhs_unknowns_iter_per_s=n * sum(its) / (ms * 1e-3),
+                         algorithmic_GBps=(44 if name == "mixed" else 88) * n * sum(its) / (ms * 1e-3) / 1e9)
+        del ws
+        log("batched %s: %.2f ms, %.1f it/rhs" % (name, ms, sum(its) / nrhs))
+    out["mixed_speedup_over_fp64"] = out["fp64"]["ms_per_batched_solve"] / out["mixed"]["ms_per_batched_solve"]
+    return out
+
+
+def serving(pcg, si, torch, n_requests=512, max_active=4):
+    """Poisson arrivals (mean 200/s, seed 5) of mixed-precision solves with
+    n x n x n_z grids, n in {64,128,256,512}, n_z in {32,64,128}, anisotropy
+    log-uniform in [1e2,1e5], U[-1,1) right-hand sides (seed 1000 + id),
+    device-resident; admitted by a 200 GB HBM budget.  The trace is replayed
+    once to warm the per-shape state, then timed."""
+    import numpy as np
+    trace = si.serving_trace(n_requests, 200.0, seed=5)
+    opts = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED)
+    descs, bs, xs = [], [], []
+    for r in trace:
+        descs.append(pcg.pcg_desc_from_ratio(r["nx"], r["ny"], r["nz"], 1.05, r["gamma2"],
+                                             pcg.PCG_BC_DIRICHLET))
+        bs.append(si.rhs_uniform_torch(r["nx"], r["ny"], r["nz"], r["seed"]))
+        xs.append(torch.empty_like(bs[-1]))
+    need = max(pcg.pcg_request_bytes(d, opts) for d in descs)
+    arena = torch.empty(max_active * need + (64 << 20), dtype=torch.uint8, device="cuda")
+    srv = pcg.Server(arena, 200 * 10**9, max_active)
+    torch.cuda.synchronize()
+
+    def replay():
+        t0 = time.perf_counter()
+        tickets, pending, lat, done_at, stats = [None] * n_requests, set(), [0.0] * n_requests, 0.0, []
+        nxt = 0
+        while nxt < n_requests or pending:
+            now = time.perf_counter() - t0
+            while nxt < n_requests and trace[nxt]["arrival"] <= now:
+                tickets[nxt] = pcg.pcg_submit_device(srv, descs[nxt], bs[nxt], xs[nxt], opts)
+                pending.add(nxt)
+                nxt += 1
+            for i in list(pending):
+                st, r = pcg.pcg_poll(srv, tickets[i])
+                if st != pcg.PCG_E_AGAIN:
+                    pending.discard(i)
+                    lat[i] = r["elapsed_ms"]
+                    stats.append((st, r["rel_res_true"], r["iterations"]))
+                    done_at = time.perf_counter() - t0
+            time.sleep(0.0002)
+        return lat, done_at, stats
+
+    log("serving: warm-up replay")
+    replay()
+    log("serving: timed replay")
+    lat, span, stats = replay()
+    q = pcg.pcg_server_query(srv)
+    srv.close()
+    lat = np.array(lat)
+    ok = sum(1 for st, _, _ in stats if st == 0)
+    nunk = np.array([d.nx * d.ny * d.nz for d in descs], dtype=np.float64)
+    return dict(requests=n_requests, completed_ok=ok, solves_per_s=n_requests / span,
+                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                mean_ms=float(lat.mean()), max_ms=float(lat.max()),
+                max_rel_res_true=float(max(r for _, r, _ in stats)),
+                mean_inner_iterations=float(np.mean([it for _, _, it in stats])),
+                trace_span_s=trace[-1]["arrival"], makespan_s=span,
+                mean_unknowns=float(nunk.mean()), max_active=max_active,
+                peak_bytes_in_use=q["peak_bytes_in_use"], budget_bytes=200 * 10**9,
+                input="device-resident right-hand sides (pcg_submit_device)")
 
 
 def cpu_baseline(n_iter=2):

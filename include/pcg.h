@@ -254,6 +254,16 @@ pcg_status pcg_server_create(const pcg_server_opts *opts, void *arena, size_t ar
 pcg_status pcg_submit(pcg_server *s, const pcg_problem_desc *desc, const pcg_solve_opts *opts,
                       const double *b_host, double *x_host, uint64_t *ticket);
 
+/* As pcg_submit with b and x in device memory (n FP64 values each, 16-byte
+ * aligned, caller-owned, valid until the ticket is finished): nothing is
+ * copied and only the workspace (pcg_workspace_bytes) is taken from the
+ * arena and counted against the budget.  The solve is ordered after the
+ * work queued on `stream` (the producer of b) at the time of the call; x is
+ * final when pcg_poll/pcg_wait reports the ticket finished. */
+pcg_status pcg_submit_device(pcg_server *s, const pcg_problem_desc *desc,
+                             const pcg_solve_opts *opts, const double *b_dev, double *x_dev,
+                             void *stream, uint64_t *ticket);
+
 /* PCG_E_AGAIN while queued or running; otherwise the solve's status with
  * *out filled (elapsed_ms = submission to completion) and the ticket
  * released; PCG_E_CANCELLED for a cancelled request. */

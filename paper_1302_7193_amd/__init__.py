@@ -115,6 +115,9 @@ _sig = {
                                ctypes.POINTER(_P)]),
     "pcg_submit": (_S, [_P, ctypes.POINTER(pcg_problem_desc), ctypes.POINTER(pcg_solve_opts),
                         _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "pcg_submit_device": (_S, [_P, ctypes.POINTER(pcg_problem_desc),
+                               ctypes.POINTER(pcg_solve_opts), _P, _P, _P,
+                               ctypes.POINTER(ctypes.c_uint64)]),
     "pcg_poll": (_S, [_P, ctypes.c_uint64, ctypes.POINTER(pcg_result)]),
     "pcg_wait": (_S, [_P, ctypes.c_uint64, ctypes.POINTER(pcg_result)]),
     "pcg_cancel": (_S, [_P, ctypes.c_uint64]),
@@ -376,6 +379,20 @@ def pcg_submit(s: Server, desc: pcg_problem_desc, b_host, x_host,
                            _host_vec(b_host, n, "b_host"), _host_vec(x_host, n, "x_host"),
                            ctypes.byref(t)), "pcg_submit")
     s._keep[t.value] = (b_host, x_host)
+    return t.value
+
+
+def pcg_submit_device(s: Server, desc: pcg_problem_desc, b: torch.Tensor, x: torch.Tensor,
+                      opts: pcg_solve_opts | None = None, stream=None) -> int:
+    """Device-resident request; ordered after the work queued so far on
+    `stream` (default: the current torch stream, which produced b)."""
+    n = desc.nx * desc.ny * desc.nz
+    t = ctypes.c_uint64()
+    _check(_lib.pcg_submit_device(s.handle, ctypes.byref(desc),
+                                  ctypes.byref(opts) if opts else None,
+                                  _vec(b, n, torch.float64, "b"), _vec(x, n, torch.float64, "x"),
+                                  _stream(stream), ctypes.byref(t)), "pcg_submit_device")
+    s._keep[t.value] = (b, x)
     return t.value
 
 

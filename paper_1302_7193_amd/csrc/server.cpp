@@ -52,8 +52,10 @@ struct Request {
     uint64_t ticket = 0;
     pcg_problem_desc desc{};
     pcg_solve_opts opts{};
-    const double* b_host = nullptr;
+    const double* b_host = nullptr;   // or device pointers when device_io
     double* x_host = nullptr;
+    bool device_io = false;
+    hipEvent_t ready = nullptr;       // device_io: b and x are ready once this fires
     size_t need = 0;
     size_t offset = 0;
     ReqState state = ReqState::Queued;
@@ -126,6 +128,10 @@ struct pcg_server {
             }
             pcg_result res{};
             pcg_status st = have_stream ? run(*req, problems, stream, &res) : PCG_E_DEVICE;
+            if (req->ready) {
+                (void)hipEventDestroy(req->ready);
+                req->ready = nullptr;
+            }
             {
                 std::lock_guard<std::mutex> lk(mu);
                 arena.release(req->offset);
@@ -159,6 +165,18 @@ struct pcg_server {
         pcg_problem* P = it->second;
         const size_t n = (size_t)P->geom.n;
         char* base = arena_base + r.offset;
+        if (r.device_io) {   // b and x live in the caller's device memory
+            if (r.ready && hipStreamWaitEvent(s, r.ready, 0) != hipSuccess) {
+                pcg::set_error("pcg server: waiting for the producer stream failed");
+                return PCG_E_DEVICE;
+            }
+            pcg_status st = pcg::solve(P, r.b_host, r.x_host, base, r.need, r.opts, 1, res, s);
+            if (hipStreamSynchronize(s) != hipSuccess) {
+                pcg::set_error("pcg server: stream synchronisation failed");
+                return PCG_E_DEVICE;
+            }
+            return st;
+        }
         double* b = reinterpret_cast<double*>(base);
         double* x = reinterpret_cast<double*>(base + al256(8 * n));
         char* ws = base + 2 * al256(8 * n);
@@ -233,11 +251,17 @@ pcg_status pcg_server_create(const pcg_server_opts* opts, void* arena, size_t ar
     return PCG_OK;
 }
 
-pcg_status pcg_submit(pcg_server* S, const pcg_problem_desc* desc, const pcg_solve_opts* opts,
-                      const double* b_host, double* x_host, uint64_t* ticket)
+static pcg_status submit(pcg_server* S, const pcg_problem_desc* desc, const pcg_solve_opts* opts,
+                         const double* b, double* x, bool device_io, hipStream_t producer,
+                         uint64_t* ticket)
 {
-    if (!S || !desc || !b_host || !x_host || !ticket) {
+    if (!S || !desc || !b || !x || !ticket) {
         pcg::set_error("pcg_submit: NULL argument");
+        return PCG_E_INVALID;
+    }
+    if (device_io && (((reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(x)) & 15u) ||
+                      static_cast<const void*>(b) == static_cast<const void*>(x))) {
+        pcg::set_error("pcg_submit_device: b and x must be distinct 16-byte aligned device arrays");
         return PCG_E_INVALID;
     }
     const std::string err = pcg::validate(*desc);
@@ -255,11 +279,26 @@ pcg_status pcg_submit(pcg_server* S, const pcg_problem_desc* desc, const pcg_sol
         pcg::set_error("pcg_submit: served solves run the fused iteration with max_iter >= 1");
         return PCG_E_INVALID;
     }
-    r->b_host = b_host;
-    r->x_host = x_host;
+    r->b_host = b;
+    r->x_host = x;
+    r->device_io = device_io;
     r->need = pcg_request_bytes(desc, &r->opts);
+    if (device_io) {   // only the workspace lives in the arena
+        const int64_t n = (int64_t)desc->nx * desc->ny * desc->nz;
+        r->need = pcg::request_bytes(n, r->opts);
+        // order the solve after the work already queued on the producer stream
+        if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(r->ready, producer) != hipSuccess) {
+            if (r->ready) (void)hipEventDestroy(r->ready);
+            r->ready = nullptr;
+            pcg::set_error("pcg_submit_device: could not record the producer stream");
+            return PCG_E_DEVICE;
+        }
+    }
     std::lock_guard<std::mutex> lk(S->mu);
     if (r->need > S->opts.hbm_budget_bytes || r->need > S->arena.size()) {
+        if (r->ready) (void)hipEventDestroy(r->ready);
+        r->ready = nullptr;
         ++S->n_rejected;
         std::ostringstream m;
         m << "pcg_submit: request needs " << r->need << " bytes; budget " << S->opts.hbm_budget_bytes
@@ -275,6 +314,19 @@ pcg_status pcg_submit(pcg_server* S, const pcg_problem_desc* desc, const pcg_sol
     *ticket = r->ticket;
     S->cv_admit.notify_one();
     return PCG_OK;
+}
+
+pcg_status pcg_submit(pcg_server* S, const pcg_problem_desc* desc, const pcg_solve_opts* opts,
+                      const double* b_host, double* x_host, uint64_t* ticket)
+{
+    return submit(S, desc, opts, b_host, x_host, false, nullptr, ticket);
+}
+
+pcg_status pcg_submit_device(pcg_server* S, const pcg_problem_desc* desc,
+                             const pcg_solve_opts* opts, const double* b_dev, double* x_dev,
+                             void* stream, uint64_t* ticket)
+{
+    return submit(S, desc, opts, b_dev, x_dev, true, static_cast<hipStream_t>(stream), ticket);
 }
 
 static pcg_status finish_ticket(pcg_server* S, std::unordered_map<uint64_t, std::shared_ptr<Request>>::iterator it,
@@ -344,6 +396,10 @@ pcg_status pcg_cancel(pcg_server* S, uint64_t ticket)
             break;
         }
     r->state = ReqState::Cancelled;
+    if (r->ready) {
+        (void)hipEventDestroy(r->ready);
+        r->ready = nullptr;
+    }
     ++S->n_cancelled;
     S->cv_admit.notify_all();   // the head may have changed
     S->cv_done.notify_all();
@@ -372,6 +428,10 @@ void pcg_server_destroy(pcg_server* S)
         std::lock_guard<std::mutex> lk(S->mu);
         for (auto& r : S->queue) {
             r->state = ReqState::Cancelled;
+            if (r->ready) {
+                (void)hipEventDestroy(r->ready);
+                r->ready = nullptr;
+            }
             ++S->n_cancelled;
         }
         S->queue.clear();

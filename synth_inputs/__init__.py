@@ -83,6 +83,58 @@ def rhs_smooth_noise(nx: int, ny: int, nz: int, seed: int, noise: float = 0.01) 
     return out
 
 
+# ---- the same streams generated on a torch device (large workloads) ----
+# int64 arithmetic wraps modulo 2^64 on the device; logical right shifts are
+# an arithmetic shift followed by a mask.  Element-for-element equal to the
+# numpy functions above (tested).
+
+def _i64(v: int) -> int:
+    v &= 0xFFFFFFFFFFFFFFFF
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def _srl(z, k: int):
+    import torch
+    return torch.bitwise_and(torch.bitwise_right_shift(z, k), (1 << (64 - k)) - 1)
+
+
+def uniform_pm1_torch(seed: int, count: int, start: int = 0, device="cuda", out=None):
+    """U[-1, 1) values for logical indices start .. start+count-1 as a float64
+    tensor on `device` (optionally written into `out`)."""
+    import torch
+    if out is None:
+        out = torch.empty(count, dtype=torch.float64, device=device)
+    g, m1, m2 = _i64(int(GOLDEN)), _i64(int(M1)), _i64(int(M2))
+    sd = _i64(seed)
+    chunk = 1 << 24
+    for s in range(0, count, chunk):
+        e = min(count, s + chunk)
+        z = torch.arange(start + s + 1, start + e + 1, dtype=torch.int64, device=out.device)
+        z.mul_(g).add_(sd)
+        z = torch.bitwise_xor(z, _srl(z, 30)).mul_(m1)
+        z = torch.bitwise_xor(z, _srl(z, 27)).mul_(m2)
+        z = torch.bitwise_xor(z, _srl(z, 31))
+        u = _srl(z, 11).to(torch.float64)
+        out[s:e] = u.mul_(2.0 / 9007199254740992.0).sub_(1.0)
+    return out
+
+
+def rhs_uniform_torch(nx, ny, nz, seed, device="cuda", out=None):
+    return uniform_pm1_torch(seed, nx * ny * nz, 0, device, out)
+
+
+def rhs_smooth_noise_torch(nx, ny, nz, seed, noise=0.01, device="cuda"):
+    import torch
+    out = uniform_pm1_torch(seed, nx * ny * nz, 0, device)
+    out.mul_(noise)
+    ar = lambda m: torch.sin(torch.pi * (torch.arange(m, dtype=torch.float64, device=out.device) + 0.5) / m)
+    sx, sy, sz = ar(nx), ar(ny), ar(nz)
+    o3 = out.view(nx, ny, nz)
+    for i in range(nx):
+        o3[i].add_(sx[i] * sy[:, None] * sz[None, :])
+    return out
+
+
 def rhs_batch(nx: int, ny: int, nz: int, seeds) -> np.ndarray:
     """Stack of U[-1, 1) right-hand sides, one row per seed."""
     return np.stack([rhs_uniform(nx, ny, nz, s) for s in seeds])

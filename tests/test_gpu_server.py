@@ -130,3 +130,34 @@ def test_oversize_request_rejected_and_cancel_queued():
         assert stats["rejected"] == 1 and stats["queued"] == 0 and stats["active"] == 0
     finally:
         srv.close()
+
+
+def test_device_resident_requests_equal_host_requests():
+    reqs, opts = requests()
+    host, _, _, _ = serve(reqs[:4], opts, max_active=3)
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    srv = pcg.Server(arena, arena.numel(), 3)
+    try:
+        outs, tickets = [], []
+        for d, b in reqs[:4]:
+            bt = torch.from_numpy(b).cuda()
+            xt = torch.full_like(bt, float("nan"))
+            outs.append(xt)
+            tickets.append(pcg.pcg_submit_device(srv, d, bt, xt, opts))
+        for t in tickets:
+            st, r = pcg.pcg_wait(srv, t)
+            assert st == pcg.PCG_OK
+        for i in range(4):
+            np.testing.assert_array_equal(outs[i].cpu().numpy(), host[i])
+    finally:
+        srv.close()
+
+
+def test_device_generator_matches_host_generator():
+    for seed, n, start in ((1, 1 << 20, 0), (1000 + 17, 33333, 777), (2**40 + 3, 4096, 1 << 33)):
+        a = si.uniform_pm1(seed, n, start)
+        b = si.uniform_pm1_torch(seed, n, start, device="cuda").cpu().numpy()
+        np.testing.assert_array_equal(a, b)
+    a = si.rhs_smooth_noise(17, 9, 33, 2)
+    b = si.rhs_smooth_noise_torch(17, 9, 33, 2).cpu().numpy()
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)

@@ -367,3 +367,11 @@ def test_generator_ranges_and_independence_of_chunks():
     assert u.min() >= -1 and u.max() < 1 and abs(u.mean()) < 0.02
     tail = si.uniform_pm1(0, 100, start=5000)
     np.testing.assert_array_equal(tail, u[5000:5100])
+
+
+def test_torch_generator_equals_numpy_generator_on_cpu():
+    torch = pytest.importorskip("torch")
+    for seed, n, start in ((0, 5000, 0), (1234567, 3000, 10**6), (2**63 + 9, 100, 7)):
+        a = si.uniform_pm1(seed, n, start)
+        b = si.uniform_pm1_torch(seed, n, start, device="cpu").numpy()
+        np.testing.assert_array_equal(a, b)
