@@ -136,10 +136,29 @@ __device__ __forceinline__ void ld_tab(const T* __restrict__ tab, int comp, int 
 //       + d_k [ sum_{T'} alpha_{T,T'} x_{T',k} - alpha_T x_k ],   s = a - b - c.
 // xc: this lane's levels of x (zero beyond n_z); x: the whole vector for the
 // horizontal neighbours.
+// The vertical coefficients of this lane's levels (the same for every column
+// a lane visits, so loaded once per kernel).
+template <typename T, int M>
+struct VertCoef {
+    T s[M], b[M], c[M], d[M];
+};
+
+template <typename T, int M, bool V>
+__device__ __forceinline__ VertCoef<T, M> load_vert(const Geom& g, const T* __restrict__ vert,
+                                                    int k0)
+{
+    VertCoef<T, M> v;
+    ld_tab<T, M, V>(vert, 0, g.nzp, k0, g.nz, v.s);
+    ld_tab<T, M, V>(vert, 1, g.nzp, k0, g.nz, v.b);
+    ld_tab<T, M, V>(vert, 2, g.nzp, k0, g.nz, v.c);
+    ld_tab<T, M, V>(vert, 3, g.nzp, k0, g.nz, v.d);
+    return v;
+}
+
 template <typename T, int M, bool V>
 __device__ __forceinline__ void stencil(const Geom& g, const Col& c, int l, int L, int k0,
                                         const T* __restrict__ x, const T (&xc)[M],
-                                        const T* __restrict__ vert, T (&y)[M])
+                                        const VertCoef<T, M>& vc, T (&y)[M])
 {
     T below = __shfl_up(xc[M - 1], 1, L);
     T above = __shfl_down(xc[0], 1, L);
@@ -152,34 +171,50 @@ __device__ __forceinline__ void stencil(const Geom& g, const Col& c, int l, int 
     ld<T, M, V>(x, c.jm, c.ok && c.jm >= 0, k0, g.nz, xjm);
     ld<T, M, V>(x, c.jp, c.ok && c.jp >= 0, k0, g.nz, xjp);
 
-    T s[M], bb[M], cc[M], d[M];
-    ld_tab<T, M, V>(vert, 0, g.nzp, k0, g.nz, s);
-    ld_tab<T, M, V>(vert, 1, g.nzp, k0, g.nz, bb);
-    ld_tab<T, M, V>(vert, 2, g.nzp, k0, g.nz, cc);
-    ld_tab<T, M, V>(vert, 3, g.nzp, k0, g.nz, d);
-
     const T area = T(g.area), ax = T(g.ax), ay = T(g.ay), at = T(c.alpha_t);
 #pragma unroll
     for (int t = 0; t < M; ++t) {
         const T lo = t == 0 ? below : xc[t - 1];
         const T hi = t == M - 1 ? above : xc[t + 1];
-        const T vertical = area * (s[t] * xc[t] + bb[t] * hi + cc[t] * lo);
-        const T horizontal = d[t] * (ax * (xim[t] + xip[t]) + ay * (xjm[t] + xjp[t]) - at * xc[t]);
+        const T vertical = area * (vc.s[t] * xc[t] + vc.b[t] * hi + vc.c[t] * lo);
+        const T horizontal =
+            vc.d[t] * (ax * (xim[t] + xip[t]) + ay * (xjm[t] + xjp[t]) - at * xc[t]);
         y[t] = vertical + horizontal;
     }
 }
 
 // z = M^{-1} r on one column segment (see the file comment).  r: this
 // lane's levels; on return z holds the solution on them.
+// LU factors of one column class on this lane's levels.
+template <typename T, int M>
+struct LuCoef {
+    T l[M], inv_d[M], phi[M];
+};
+
+template <typename T, int M, bool V>
+__device__ __forceinline__ LuCoef<T, M> load_lu(const Geom& g, const T* __restrict__ lu, int cls,
+                                                int k0)
+{
+    LuCoef<T, M> f;
+    const T* tab = lu + (int64_t)cls * 3 * g.nzp;
+    ld_tab<T, M, V>(tab, 0, g.nzp, k0, g.nz, f.l);
+    ld_tab<T, M, V>(tab, 1, g.nzp, k0, g.nz, f.inv_d);
+    ld_tab<T, M, V>(tab, 2, g.nzp, k0, g.nz, f.phi);
+    return f;
+}
+
+// f0: the class-0 factors (interior / periodic columns), loaded once per
+// kernel; columns of another class load theirs.
 template <typename T, int M, bool V>
 __device__ __forceinline__ void line_solve(const Geom& g, const Col& c, int l, int L, int k0,
-                                           const T* __restrict__ lu, const T (&r)[M], T (&z)[M])
+                                           const T* __restrict__ lu, const LuCoef<T, M>& f0,
+                                           const T (&r)[M], T (&z)[M])
 {
-    const T* tab = lu + (int64_t)c.cls * 3 * g.nzp;
-    T lf[M], inv_d[M], phi[M];
-    ld_tab<T, M, V>(tab, 0, g.nzp, k0, g.nz, lf);
-    ld_tab<T, M, V>(tab, 1, g.nzp, k0, g.nz, inv_d);
-    ld_tab<T, M, V>(tab, 2, g.nzp, k0, g.nz, phi);
+    LuCoef<T, M> f = f0;
+    if (c.cls != 0) f = load_lu<T, M, V>(g, lu, c.cls, k0);
+    const T (&lf)[M] = f.l;
+    const T (&inv_d)[M] = f.inv_d;
+    const T (&phi)[M] = f.phi;
 
     // forward substitution, local part: w = Q + P * w_in
     T P = T(1), Q = T(0);
@@ -273,13 +308,14 @@ __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
     T* y = static_cast<T*>(a.io0) + rhs * g.n;
     const T* vert = static_cast<const T*>(a.vert);
     const Lane p = lane_pos<M>(L);
+    const VertCoef<T, M> vc = load_vert<T, M, V>(g, vert, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col(g, tile_col(tile, p, L));
         T xc[M], yc[M];
         ld<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
-        stencil<T, M, V>(g, c, p.l, L, p.k0, x, xc, vert, yc);
+        stencil<T, M, V>(g, c, p.l, L, p.k0, x, xc, vc, yc);
         st<T, M, V>(y, c.idx, c.ok, p.k0, g.nz, yc);
     }
 }
@@ -296,13 +332,14 @@ __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
     T* z = static_cast<T*>(a.io0) + rhs * g.n;
     const T* lu = static_cast<const T*>(a.lu);
     const Lane p = lane_pos<M>(L);
+    const LuCoef<T, M> f0 = load_lu<T, M, V>(g, lu, 0, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col(g, tile_col(tile, p, L));
         T rc[M], zc[M];
         ld<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
-        line_solve<T, M, V>(g, c, p.l, L, p.k0, lu, rc, zc);
+        line_solve<T, M, V>(g, c, p.l, L, p.k0, lu, f0, rc, zc);
         st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
     }
 }
@@ -324,6 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
     const T* vert = static_cast<const T*>(a.vert);
     const bool in_place = a.in1 == a.io1;   // b already stored in r
     const Lane p = lane_pos<M>(L);
+    const VertCoef<T, M> vc = load_vert<T, M, V>(g, vert, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     T zero[M];
@@ -342,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
             T bc[M], rc[M], xc[M], ax[M];
             ld<T, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
             ld<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
-            stencil<T, M, V>(g, c, p.l, L, p.k0, x, xc, vert, ax);
+            stencil<T, M, V>(g, c, p.l, L, p.k0, x, xc, vc, ax);
 #pragma unroll
             for (int i = 0; i < M; ++i) rc[i] = bc[i] - ax[i];
             st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
@@ -375,6 +413,7 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
     const T* lu = static_cast<const T*>(a.lu);
     const T alpha = T(s->alpha);
     const Lane p = lane_pos<M>(L);
+    const LuCoef<T, M> f0 = load_lu<T, M, V>(g, lu, 0, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
@@ -390,7 +429,7 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[0] += double(rc[i]) * double(rc[i]);
         if (!FIRST || store_r) st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
-        line_solve<T, M, V>(g, c, p.l, L, p.k0, lu, rc, zc);
+        line_solve<T, M, V>(g, c, p.l, L, p.k0, lu, f0, rc, zc);
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[1] += double(rc[i]) * double(zc[i]);
         st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
@@ -433,13 +472,14 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
     const T alpha = T(s->alpha), beta = T(s->beta);
     const bool zero_u = FIRST && s->zero_start;
     const Lane p = lane_pos<M>(L);
+    const VertCoef<T, M> vc = load_vert<T, M, V>(g, vert, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col(g, tile_col(tile, p, L));
         T zc[M], az[M], pc[M], qc[M];
         ld<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
-        stencil<T, M, V>(g, c, p.l, L, p.k0, z, zc, vert, az);
+        stencil<T, M, V>(g, c, p.l, L, p.k0, z, zc, vc, az);
         if (FIRST) {
 #pragma unroll
             for (int i = 0; i < M; ++i) {
@@ -551,6 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
     const double* b = static_cast<const double*>(a.in1) + rhs * g.n;
     const double* vert = static_cast<const double*>(a.vert);
     const Lane p = lane_pos<M>(L);
+    const VertCoef<double, M> vc = load_vert<double, M, V>(g, vert, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     double acc[1] = {0.0};
@@ -559,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
         double xc[M], ax[M], bc[M];
         ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
         ld<double, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
-        stencil<double, M, V>(g, c, p.l, L, p.k0, x, xc, vert, ax);
+        stencil<double, M, V>(g, c, p.l, L, p.k0, x, xc, vc, ax);
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             const double d = bc[i] - ax[i];
@@ -591,6 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
     const double* vert = static_cast<const double*>(a.vert);
     const double scale = s->aux;
     const Lane p = lane_pos<M>(L);
+    const VertCoef<double, M> vc = load_vert<double, M, V>(g, vert, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     double acc[1] = {0.0};
@@ -604,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
             for (int i = 0; i < M; ++i) ax[i] = 0.0;
         } else {
             ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
-            stencil<double, M, V>(g, c, p.l, L, p.k0, x, xc, vert, ax);
+            stencil<double, M, V>(g, c, p.l, L, p.k0, x, xc, vc, ax);
         }
 #pragma unroll
         for (int i = 0; i < M; ++i) {
