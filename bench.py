@@ -357,39 +357,100 @@ def copy_probe(gib=1, reps=5):
                       "reps": reps}))
 
 
-def summarize_rocprof(directory, kernel_filter="k_fused|k_init|k_fixup|copy|elementwise"):
-    """Condense rocprofv3 CSV output (kernel stats and/or counter collection)
-    found under `directory` into a few lines of text."""
+def _csv_rows(directory, suffix):
     import csv
     import glob
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True)):
+        with open(path) as f:
+            yield path, list(csv.DictReader(f))
+
+
+def _working(values, frac=0.1):
+    """Dispatches that did work: an early-exit launch (the solve had already
+    stopped) takes a few microseconds and moves almost nothing."""
+    top = max(values) if values else 0.0
+    return [v for v in values if v >= frac * top]
+
+
+def summarize_rocprof(directory, kernel_filter="k_fused|k_init|k_fixup|k_finalize|copy|elementwise"):
+    """Condense rocprofv3 CSV output under `directory` into a few lines:
+    the per-kernel stats table, per-dispatch durations from the kernel trace
+    (all dispatches and the ones that did work), and counter means."""
     import re
     lines = []
-    for path in sorted(glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)):
+    for path, rows in _csv_rows(directory, "kernel_stats.csv"):
         lines.append("# kernel stats: %s" % os.path.relpath(path, directory))
         lines.append("name | calls | total_ms | avg_us | min_us | max_us | pct")
-        with open(path) as f:
-            for row in csv.DictReader(f):
-                lines.append("%s | %s | %.3f | %.2f | %.2f | %.2f | %s" % (
-                    row["Name"], row["Calls"], float(row["TotalDurationNs"]) / 1e6,
-                    float(row["AverageNs"]) / 1e3, float(row["MinNs"]) / 1e3,
-                    float(row["MaxNs"]) / 1e3, row.get("Percentage", "")))
-    for path in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"),
-                                 recursive=True)):
-        agg = {}
-        with open(path) as f:
-            for row in csv.DictReader(f):
-                name = row["Kernel_Name"]
-                if not re.search(kernel_filter, name):
-                    continue
-                key = (name, row["Counter_Name"], row.get("Grid_Size", ""))
-                v = agg.setdefault(key, [0, 0.0])
-                v[0] += 1
-                v[1] += float(row["Counter_Value"])
+        for row in rows:
+            lines.append("%s | %s | %.3f | %.2f | %.2f | %.2f | %s" % (
+                row["Name"], row["Calls"], float(row["TotalDurationNs"]) / 1e6,
+                float(row["AverageNs"]) / 1e3, float(row["MinNs"]) / 1e3,
+                float(row["MaxNs"]) / 1e3, row.get("Percentage", "")))
+    for path, rows in _csv_rows(directory, "kernel_trace.csv"):
+        per = {}
+        for row in rows:
+            name = row["Kernel_Name"]
+            if re.search(kernel_filter, name):
+                per.setdefault(name, []).append(
+                    (float(row["End_Timestamp"]) - float(row["Start_Timestamp"])) / 1e3)
+        lines.append("# kernel trace: %s" % os.path.relpath(path, directory))
+        lines.append("name | dispatches | avg_us | working_dispatches | working_avg_us")
+        for name, d in sorted(per.items()):
+            w = _working(d)
+            lines.append("%s | %d | %.2f | %d | %.2f" % (name, len(d), sum(d) / len(d), len(w),
+                                                        sum(w) / len(w)))
+    for path, rows in _csv_rows(directory, "counter_collection.csv"):
+        per = {}
+        for row in rows:
+            name = row["Kernel_Name"]
+            if re.search(kernel_filter, name):
+                per.setdefault((name, row["Counter_Name"]), []).append(float(row["Counter_Value"]))
         lines.append("# counters: %s" % os.path.relpath(path, directory))
-        lines.append("kernel | counter | grid | dispatches | mean_per_dispatch")
-        for (name, cn, grid), (c, tot) in sorted(agg.items()):
-            lines.append("%s | %s | %s | %d | %.1f" % (name, cn, grid, c, tot / c))
+        lines.append("kernel | counter | dispatches | mean | working_dispatches | working_mean")
+        for (name, cn), v in sorted(per.items()):
+            w = _working(v)
+            lines.append("%s | %s | %d | %.1f | %d | %.1f" % (name, cn, len(v), sum(v) / len(v),
+                                                              len(w), sum(w) / len(w)))
     print("\n".join(lines))
+
+
+def traffic_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, kernel, command):
+    """HBM bytes per working dispatch of `kernel` from FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch), each scaled by the same counter's reading for a plain
+    1 GiB device copy (bench.py --copy-probe)."""
+    import re
+
+    def means(directory, counter, pattern):
+        vals = []
+        for _, rows in _csv_rows(directory, "counter_collection.csv"):
+            vals += [float(r["Counter_Value"]) for r in rows
+                     if r["Counter_Name"] == counter and re.search(pattern, r["Kernel_Name"])]
+        w = _working(vals)
+        return sum(w) / len(w), len(w)
+
+    gib_kib = float(1 << 20)
+    cf, _ = means(cfetch_dir, "FETCH_SIZE", "copyBuffer")
+    cw, _ = means(cwrite_dir, "WRITE_SIZE", "copyBuffer")
+    ff, fw = gib_kib / cf, gib_kib / cw
+    sym = re.escape(KERNEL_SYMBOL[kernel])
+    f, nf = means(fetch_dir, "FETCH_SIZE", sym)
+    w, nw = means(write_dir, "WRITE_SIZE", sym)
+    out = [
+        "# HBM traffic of %s on 512x512x128 (FP64, default tuning), per dispatch" % KERNEL_SYMBOL[kernel],
+        "# commands: %s" % command,
+        "kernel = %s" % KERNEL_SYMBOL[kernel],
+        "kernel_source_sha256_16 = %s" % kernel_source_hash(),
+        "copy_probe_fetch_kib_per_gib = %.1f" % cf,
+        "copy_probe_write_kib_per_gib = %.1f" % cw,
+        "fetch_scale = %.4f" % ff,
+        "write_scale = %.4f" % fw,
+        "fetch_kib_per_dispatch = %.1f  (mean over %d working dispatches)" % (f, nf),
+        "write_kib_per_dispatch = %.1f  (mean over %d working dispatches)" % (w, nw),
+        "hbm_fetch_bytes_per_launch = %.0f" % (f * ff * 1024),
+        "hbm_write_bytes_per_launch = %.0f" % (w * fw * 1024),
+        "hbm_bytes_per_launch = %.0f" % ((f * ff + w * fw) * 1024),
+    ]
+    print("\n".join(out))
 
 
 def main():
@@ -404,9 +465,19 @@ def main():
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="print a text summary of rocprofv3 CSV output under DIR and exit")
+    ap.add_argument("--traffic-summary", nargs=5,
+                    metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="print the HBM traffic summary of a fused kernel (fused_apply or "
+                         "fused_prec) from rocprofv3 counter runs and exit")
+    ap.add_argument("--traffic-command", default="",
+                    help="the profiling commands, recorded in the traffic summary")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(args.summarize_rocprof)
+        return
+    if args.traffic_summary:
+        k, fd, wd, cfd, cwd = args.traffic_summary
+        traffic_summary(fd, wd, cfd, cwd, k, args.traffic_command)
         return
     if args.copy_probe:
         copy_probe()
@@ -436,6 +507,8 @@ def main():
                        total_ms=m["ms"][k], symbol=KERNEL_SYMBOL[k])
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     traffic = measured_traffic(dom, "512x512x128")
+    for k in kern:
+        kern[k]["traffic"] = measured_traffic(k, "512x512x128")
     line = {
         "metric": METRIC,
         "value": value,

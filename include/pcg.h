@@ -178,8 +178,10 @@ pcg_status pcg_solve_batched(pcg_problem *p, int32_t nrhs, const double *b, doub
  *                     line solve combines the L pieces with a log2(L)-step
  *                     in-wave scan (the sub-structuring of Sec. 6.1).
  *                     Power of two, 1 <= L <= 64, 16*L >= n_z.
- *   block_cap         workgroups per right-hand side (>= 1, <= 16384);
- *                     each walks a contiguous range of column tiles.
+ *   block_cap         workgroups per right-hand side (>= 1, <= 65536; default
+ *                     16384); each walks a contiguous range of column tiles.
+ *                     Workspace sizes depend on it: query pcg_workspace_bytes
+ *                     after changing the tuning.
  *   reduction         0: the last workgroup of each reduction totals the
  *                     partial sums and performs the scalar step inside the
  *                     kernel (device-scope fences in every workgroup);

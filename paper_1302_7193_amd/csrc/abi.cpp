@@ -189,7 +189,7 @@ pcg_status pcg_problem_create(const pcg_problem_desc* desc, pcg_problem** out)
     build_tables(*desc, P->geom, P->vert64, P->lu64);
     for (int d = 0; d < 2; ++d) {
         P->tune[d].shape = default_shape(desc->nz, d);
-        P->tune[d].block_cap = 2048;
+        P->tune[d].block_cap = kDefaultCap;
         P->tune[d].red_mode = 1;
     }
     const size_t nv = P->vert64.size(), nl = P->lu64.size();
@@ -231,7 +231,6 @@ void pcg_problem_destroy(pcg_problem* P)
     (void)hipSetDevice(P->device);
     for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : P->events) (void)hipEventDestroy(e);
-    if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
     if (P->pinned_states) (void)hipHostFree(P->pinned_states);
     if (P->dev_tables) (void)hipFree(P->dev_tables);
     if (cur >= 0) (void)hipSetDevice(cur);
@@ -374,7 +373,7 @@ pcg_status pcg_set_tuning(pcg_problem* P, int32_t dtype, const pcg_tuning* t)
         return PCG_E_INVALID;
     }
     if (t->block_cap < 1 || t->block_cap > kMaxBlocks || (t->reduction != 0 && t->reduction != 1)) {
-        set_error("pcg_set_tuning: block_cap must be in [1, 16384] and reduction 0 or 1");
+        set_error("pcg_set_tuning: block_cap must be in [1, 65536] and reduction 0 or 1");
         return PCG_E_INVALID;
     }
     sh.M = 1;

@@ -96,12 +96,12 @@ __global__ __launch_bounds__(kBlock) void k_blas(BlasArgs a)
 
 // Mode-1 reductions of the BLAS-1 kernels (one workgroup).
 template <Blas OP>
-__global__ __launch_bounds__(kBlock) void k_blas_finalize(BlasArgs a)
+__global__ __launch_bounds__(kFinalThreads) void k_blas_finalize(BlasArgs a)
 {
     SolverState* s = a.st;
     if (s->flag != kRunning) return;
     double tot[2];
-    sum_partials<2, false>(a.part, a.blocks, tot);
+    sum_partials<2, false, kFinalThreads>(a.part, a.blocks, tot);
     if (threadIdx.x == 0) blas_finish<OP>(s, tot);
 }
 
@@ -116,7 +116,7 @@ hipError_t launch_blas(Blas op, const BlasArgs& a, hipStream_t s)
 #define PCG_BLAS_CASE(X)                                                                \
     case Blas::X:                                                                       \
         hipLaunchKernelGGL((k_blas<Blas::X>), grid, block, 0, s, a);                    \
-        if (fin) hipLaunchKernelGGL((k_blas_finalize<Blas::X>), dim3(1), block, 0, s, a); \
+        if (fin) hipLaunchKernelGGL((k_blas_finalize<Blas::X>), dim3(1), dim3(kFinalThreads), 0, s, a); \
         break;
         PCG_BLAS_CASE(DotPQ)
         PCG_BLAS_CASE(DotRZ)

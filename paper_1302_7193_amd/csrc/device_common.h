@@ -47,24 +47,67 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (&out)[NV])
     __syncthreads();
 }
 
-// Fixed-order total of the nblk published partial sums (every thread gets
-// it).  COHERENT: read with device-scope atomic loads (partials written by
-// other workgroups of the running kernel).
-template <int NV, bool COHERENT>
+// Fixed-order total of the nblk published partial sums, computed as if by
+// kFinalThreads virtual threads: virtual thread v adds slots v, v + 1024, ...
+// in order, virtual wavefronts add their 64 lanes by shuffles, and the 16
+// wavefront sums are added in order.  A workgroup of BS threads plays
+// 1024 / BS virtual threads per thread, so the finalize launch (1024
+// threads) and the in-kernel mode (256 threads) produce identical bits.
+// Every thread gets the totals.  COHERENT: device-scope atomic loads
+// (partials written by other workgroups of the running kernel).
+constexpr int kFinalThreads = 1024;
+
+template <int NV, bool COHERENT, int BS>
 __device__ __forceinline__ void sum_partials(const double* part, int64_t nblk, double (&tot)[NV])
 {
-    double acc[NV];
+    constexpr int R = kFinalThreads / BS;
+    constexpr int kWavesV = kFinalThreads / kWave;
+    __shared__ double sm[kWavesV][NV];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    double acc[R][NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int64_t b = threadIdx.x; b < nblk; b += kBlock) {
+    for (int r = 0; r < R; ++r) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
+        for (int i = 0; i < NV; ++i) acc[r][i] = 0.0;
+        const int64_t v = threadIdx.x + (int64_t)r * BS;
+        auto load = [&](int64_t b, int i) {
             const double* q = &part[b * kRedSlots + i];
-            acc[i] += COHERENT ? __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                               : *q;
+            return COHERENT ? __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *q;
+        };
+        int64_t b = v;
+        // eight loads in flight, added in slot order
+        for (; b + 7 * kFinalThreads < nblk; b += 8 * kFinalThreads) {
+            double t[8][NV];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int i = 0; i < NV; ++i) t[u][i] = load(b + (int64_t)u * kFinalThreads, i);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int i = 0; i < NV; ++i) acc[r][i] += t[u][i];
         }
+        for (; b < nblk; b += kFinalThreads) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[r][i] += load(b, i);
+        }
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[r][i] = wave_sum(acc[r][i]);
     }
-    block_sum<NV>(acc, tot);
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) sm[wave + r * (BS / kWave)][i] = acc[r][i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double sum = 0.0;
+        for (int w = 0; w < kWavesV; ++w) sum += sm[w][i];
+        tot[i] = sum;
+    }
+    __syncthreads();
 }
 
 // Publish this workgroup's sums of v in slot blk of part.
@@ -101,7 +144,7 @@ __device__ __forceinline__ bool publish(double (&v)[NV], double* part, int64_t b
     __syncthreads();
     if (!is_last) return false;
     __threadfence();
-    sum_partials<NV, true>(part, nblk, tot);
+    sum_partials<NV, true, kBlock>(part, nblk, tot);
     if (threadIdx.x == 0) *ticket = 0u;
     return true;
 }

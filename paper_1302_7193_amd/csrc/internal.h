@@ -17,8 +17,9 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlock = 256;        // threads per workgroup of the column kernels
 constexpr int kMaxNz = 1024;       // columns up to 64 lanes x 16 levels
 constexpr int kClasses = 9;        // column classes: Dirichlet faces in x (0..2) x in y (0..2)
-constexpr int kRedSlots = 4;       // doubles per workgroup in the partial-sum buffer
-constexpr int64_t kMaxBlocks = 16384;   // workgroups per right-hand side (partial-sum slots)
+constexpr int kRedSlots = 2;       // doubles per workgroup in the partial-sum buffer
+constexpr int64_t kMaxBlocks = 65536;   // largest workgroup cap per right-hand side
+constexpr int64_t kDefaultCap = 16384;  // default workgroup cap per right-hand side
 
 // Solver flags kept in device memory.
 enum : int32_t {
@@ -83,7 +84,7 @@ struct Shape {
 // Tunable launch parameters of one precision (see pcg_tuning).
 struct Tuning {
     Shape shape;
-    int64_t block_cap = 2048;   // workgroups per right-hand side
+    int64_t block_cap = kDefaultCap;   // workgroups per right-hand side
     int red_mode = 1;           // reduction mode (ColArgs::red_mode)
 };
 
@@ -125,13 +126,24 @@ struct ColArgs {
     int x0_zero;        // refinement kernels: x is zero (not read)
 };
 
-// Host launchers (kernels.hip): T = double or float.  launch_column issues
-// the kernel and, for mode-1 reductions, its finalize launch;
-// launch_column_main / launch_column_finalize issue them separately.
+// Host launchers (kernels.hip): T = double or float.  column_launches
+// returns the kernel (and, for mode-1 reductions, its finalize kernel) with
+// launch dimensions, for direct launches or graph nodes; launch_column
+// issues both; launch_column_main / launch_column_finalize issue them
+// separately.
+struct KernelLaunch {
+    const void* func;
+    dim3 grid;
+    dim3 block;
+};
+template <typename T>
+int column_launches(Kind kind, const ColArgs& a, int64_t batch, KernelLaunch out[2]);
+hipError_t issue(const KernelLaunch& k, const ColArgs& a, hipStream_t s);
 template <typename T>
 hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s);
 template <typename T>
 hipError_t launch_column_main(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s);
+template <typename T>
 hipError_t launch_column_finalize(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s);
 
 // Unfused BLAS-1 style kernels with device-resident scalars (blas.hip).

@@ -705,7 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
 // Mode-1 reductions: one workgroup per right-hand side totals the published
 // partial sums in the same order as mode 0 and performs the scalar step.
 template <Kind K>
-__global__ __launch_bounds__(kBlock) void k_finalize(ColArgs a)
+__global__ __launch_bounds__(kFinalThreads) void k_finalize(ColArgs a)
 {
     const int64_t rhs = blockIdx.x;
     SolverState* s = a.st + rhs;
@@ -719,11 +719,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(ColArgs a)
     if (K != Kind::TrueResidual && s->flag != kRunning) return;   // main kernel skipped
     if (K == Kind::FusedPrec) {
         double tot[2];
-        sum_partials<2, false>(part, a.blocks_per_rhs, tot);
+        sum_partials<2, false, kFinalThreads>(part, a.blocks_per_rhs, tot);
         if (threadIdx.x == 0) finish_prec(s, tot[0], tot[1]);
     } else {
         double tot[1];
-        sum_partials<1, false>(part, a.blocks_per_rhs, tot);
+        sum_partials<1, false, kFinalThreads>(part, a.blocks_per_rhs, tot);
         if (threadIdx.x == 0) {
             if (K == Kind::FusedApply) finish_apply(s, tot[0]);
             else if (K == Kind::TrueResidual) s->aux = sqrt(tot[0]);
@@ -741,95 +741,125 @@ bool has_finalize(Kind k)
            k == Kind::TrueResidual || k == Kind::Residual64;
 }
 
-hipError_t launch_finalize(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+const void* finalize_func(Kind kind)
 {
-    const dim3 grid((unsigned)batch), block(kBlock);
     switch (kind) {
-    case Kind::FusedPrec: hipLaunchKernelGGL((k_finalize<Kind::FusedPrec>), grid, block, 0, s, a); break;
-    case Kind::FusedApply: hipLaunchKernelGGL((k_finalize<Kind::FusedApply>), grid, block, 0, s, a); break;
-    case Kind::Fixup: hipLaunchKernelGGL((k_finalize<Kind::Fixup>), grid, block, 0, s, a); break;
-    case Kind::TrueResidual: hipLaunchKernelGGL((k_finalize<Kind::TrueResidual>), grid, block, 0, s, a); break;
-    case Kind::Residual64: hipLaunchKernelGGL((k_finalize<Kind::Residual64>), grid, block, 0, s, a); break;
-    default: return hipSuccess;
+    case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_finalize<Kind::FusedPrec>);
+    case Kind::FusedApply: return reinterpret_cast<const void*>(&k_finalize<Kind::FusedApply>);
+    case Kind::Fixup: return reinterpret_cast<const void*>(&k_finalize<Kind::Fixup>);
+    case Kind::TrueResidual: return reinterpret_cast<const void*>(&k_finalize<Kind::TrueResidual>);
+    case Kind::Residual64: return reinterpret_cast<const void*>(&k_finalize<Kind::Residual64>);
+    default: return nullptr;
     }
-    return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- dispatch --
-
 template <typename T, int M, bool V>
-hipError_t launch_m(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+const void* main_func_m(Kind kind)
 {
-    const dim3 grid((unsigned)(a.blocks_per_rhs * batch)), block(kBlock);
     switch (kind) {
-    case Kind::Apply: hipLaunchKernelGGL((k_apply<T, M, V>), grid, block, 0, s, a); break;
-    case Kind::Precond: hipLaunchKernelGGL((k_precond<T, M, V>), grid, block, 0, s, a); break;
-    case Kind::InitFull: hipLaunchKernelGGL((k_init<T, M, V, false>), grid, block, 0, s, a); break;
-    case Kind::InitZero: hipLaunchKernelGGL((k_init<T, M, V, true>), grid, block, 0, s, a); break;
-    case Kind::FusedPrec: hipLaunchKernelGGL((k_fused_prec<T, M, V>), grid, block, 0, s, a); break;
-    case Kind::FusedApply: hipLaunchKernelGGL((k_fused_apply<T, M, V>), grid, block, 0, s, a); break;
-    case Kind::Fixup: hipLaunchKernelGGL((k_fixup<T, M, V>), grid, block, 0, s, a); break;
+    case Kind::Apply: return reinterpret_cast<const void*>(&k_apply<T, M, V>);
+    case Kind::Precond: return reinterpret_cast<const void*>(&k_precond<T, M, V>);
+    case Kind::InitFull: return reinterpret_cast<const void*>(&k_init<T, M, V, false>);
+    case Kind::InitZero: return reinterpret_cast<const void*>(&k_init<T, M, V, true>);
+    case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V>);
+    case Kind::FusedApply: return reinterpret_cast<const void*>(&k_fused_apply<T, M, V>);
+    case Kind::Fixup: return reinterpret_cast<const void*>(&k_fixup<T, M, V>);
     case Kind::TrueResidual:
-        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((k_true_residual<M, V>), grid, block, 0, s, a);
-        else return hipErrorInvalidValue;
-        break;
+        if constexpr (sizeof(T) == 8) return reinterpret_cast<const void*>(&k_true_residual<M, V>);
+        return nullptr;
     case Kind::Residual64:
-        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((k_residual64<M, V>), grid, block, 0, s, a);
-        else return hipErrorInvalidValue;
-        break;
+        if constexpr (sizeof(T) == 8) return reinterpret_cast<const void*>(&k_residual64<M, V>);
+        return nullptr;
     case Kind::Update64:
-        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((k_update64<M, V>), grid, block, 0, s, a);
-        else return hipErrorInvalidValue;
-        break;
+        if constexpr (sizeof(T) == 8) return reinterpret_cast<const void*>(&k_update64<M, V>);
+        return nullptr;
     }
-    return hipGetLastError();
+    return nullptr;
 }
 
 template <typename T, int M>
-hipError_t launch_v(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+const void* main_func_v(Kind kind, const ColArgs& a)
 {
     // vector path: whole chunks valid and 16-byte aligned rows and chunks
     const bool vec = (a.g.nz % M == 0) && ((M * sizeof(T)) % 16 == 0) &&
                      ((a.g.nz * sizeof(T)) % 16 == 0);
-    if (vec) return launch_m<T, M, true>(kind, a, batch, s);
-    return launch_m<T, M, false>(kind, a, batch, s);
+    return vec ? main_func_m<T, M, true>(kind) : main_func_m<T, M, false>(kind);
 }
 
-}  // namespace
-
 template <typename T>
-hipError_t launch_column_main(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+const void* main_func(Kind kind, const ColArgs& a)
 {
     const int M = a.L > 0 ? (a.g.nz + a.L - 1) / a.L : 0;
     int Mp = 1;
     while (Mp < M) Mp <<= 1;
     switch (Mp) {
-    case 1: return launch_v<T, 1>(kind, a, batch, s);
-    case 2: return launch_v<T, 2>(kind, a, batch, s);
-    case 4: return launch_v<T, 4>(kind, a, batch, s);
-    case 8: return launch_v<T, 8>(kind, a, batch, s);
-    case 16: return launch_v<T, 16>(kind, a, batch, s);
-    default: return hipErrorInvalidValue;
+    case 1: return main_func_v<T, 1>(kind, a);
+    case 2: return main_func_v<T, 2>(kind, a);
+    case 4: return main_func_v<T, 4>(kind, a);
+    case 8: return main_func_v<T, 8>(kind, a);
+    case 16: return main_func_v<T, 16>(kind, a);
+    default: return nullptr;
     }
 }
 
+}  // namespace
+
+template <typename T>
+int column_launches(Kind kind, const ColArgs& a, int64_t batch, KernelLaunch out[2])
+{
+    out[0].func = main_func<T>(kind, a);
+    if (!out[0].func) return 0;
+    out[0].grid = dim3((unsigned)(a.blocks_per_rhs * batch));
+    out[0].block = dim3(kBlock);
+    if (a.red_mode == 0 || !has_finalize(kind)) return 1;
+    out[1].func = finalize_func(kind);
+    out[1].grid = dim3((unsigned)batch);
+    out[1].block = dim3(kFinalThreads);
+    return 2;
+}
+
+hipError_t issue(const KernelLaunch& k, const ColArgs& a, hipStream_t s)
+{
+    void* args[] = {const_cast<ColArgs*>(&a)};
+    return hipLaunchKernel(k.func, k.grid, k.block, args, 0, s);
+}
+
+template <typename T>
+hipError_t launch_column_main(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
+{
+    KernelLaunch k[2];
+    if (column_launches<T>(kind, a, batch, k) < 1) return hipErrorInvalidValue;
+    return issue(k[0], a, s);
+}
+
+template <typename T>
 hipError_t launch_column_finalize(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
 {
-    if (a.red_mode == 0 || !has_finalize(kind)) return hipSuccess;
-    return launch_finalize(kind, a, batch, s);
+    KernelLaunch k[2];
+    if (column_launches<T>(kind, a, batch, k) < 2) return hipSuccess;
+    return issue(k[1], a, s);
 }
 
 template <typename T>
 hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
 {
-    hipError_t e = launch_column_main<T>(kind, a, batch, s);
-    if (e != hipSuccess) return e;
-    return launch_column_finalize(kind, a, batch, s);
+    KernelLaunch k[2];
+    const int n = column_launches<T>(kind, a, batch, k);
+    if (n < 1) return hipErrorInvalidValue;
+    for (int i = 0; i < n; ++i) {
+        const hipError_t e = issue(k[i], a, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
+template int column_launches<double>(Kind, const ColArgs&, int64_t, KernelLaunch*);
+template int column_launches<float>(Kind, const ColArgs&, int64_t, KernelLaunch*);
 template hipError_t launch_column<double>(Kind, const ColArgs&, int64_t, hipStream_t);
 template hipError_t launch_column<float>(Kind, const ColArgs&, int64_t, hipStream_t);
 template hipError_t launch_column_main<double>(Kind, const ColArgs&, int64_t, hipStream_t);
 template hipError_t launch_column_main<float>(Kind, const ColArgs&, int64_t, hipStream_t);
+template hipError_t launch_column_finalize<double>(Kind, const ColArgs&, int64_t, hipStream_t);
+template hipError_t launch_column_finalize<float>(Kind, const ColArgs&, int64_t, hipStream_t);
 
 }  // namespace pcg

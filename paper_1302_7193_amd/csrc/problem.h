@@ -10,7 +10,7 @@
 
 namespace pcg {
 
-// Key of a captured iteration chunk: every pointer and size baked into it.
+// Key of a graph of iteration chunks: every pointer and size baked into it.
 struct GraphKey {
     int dtype;
     int kind;             // 0: fused iteration chunk, 1: unfused iteration chunk
@@ -46,7 +46,6 @@ struct pcg_problem {
     int last_iters[2] = {0, 0};            // adaptive chunk length per precision
     pcg::SolverState* pinned_states = nullptr;  // host-pinned staging of solver states
     int64_t pinned_cap = 0;
-    hipStream_t capture_stream = nullptr;
     std::map<pcg::GraphKey, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> events;
 };

@@ -6,7 +6,8 @@
 // in arrival order whenever a worker is idle and the request's device bytes
 // (b, x and its solve workspace) fit both the HBM budget and the
 // caller-provided device arena.  An admitted request is copied in, solved by
-// the fused iteration (HIP-graph chunks), copied out and its arena block is
+// the fused iteration (HIP-graph chunks, built without stream capture so the
+// workers never interfere), copied out and its arena block is
 // released, which may admit the next request.  Requests of different shapes
 // overlap on the device through the worker streams.  Each request's kernels,
 // launch shapes and reduction orders depend only on its own descriptor and
@@ -21,6 +22,7 @@
 #include <new>
 #include <mutex>
 #include <sstream>
+#include <string>
 #include <thread>
 #include <tuple>
 #include <unordered_map>
@@ -41,6 +43,7 @@ std::string validate(const pcg_problem_desc& d);
 extern "C" pcg_status pcg_problem_create(const pcg_problem_desc* desc, pcg_problem** out);
 extern "C" void pcg_problem_destroy(pcg_problem* p);
 extern "C" void pcg_default_opts(pcg_solve_opts* o);
+extern "C" size_t pcg_last_error(char* buf, size_t n);
 
 namespace {
 
@@ -61,6 +64,7 @@ struct Request {
     ReqState state = ReqState::Queued;
     pcg_result result{};
     pcg_status status = PCG_E_AGAIN;
+    std::string error;                // worker's message for a failed solve
     Clock::time_point t_submit;
 };
 
@@ -128,6 +132,12 @@ struct pcg_server {
             }
             pcg_result res{};
             pcg_status st = have_stream ? run(*req, problems, stream, &res) : PCG_E_DEVICE;
+            std::string err;
+            if (st != PCG_OK && st != PCG_E_NOCONV && st != PCG_E_BREAKDOWN) {
+                char buf[512];
+                pcg_last_error(buf, sizeof(buf));   // this worker thread's message
+                err = have_stream ? buf : "pcg server: could not create a worker stream";
+            }
             if (req->ready) {
                 (void)hipEventDestroy(req->ready);
                 req->ready = nullptr;
@@ -141,6 +151,7 @@ struct pcg_server {
                     std::chrono::duration<double, std::milli>(Clock::now() - req->t_submit).count();
                 req->result = res;
                 req->status = st;
+                req->error = err;
                 req->state = ReqState::Done;
                 ++n_completed;
             }
@@ -339,6 +350,7 @@ static pcg_status finish_ticket(pcg_server* S, std::unordered_map<uint64_t, std:
     }
     if (out) *out = r->result;
     const pcg_status st = r->status;
+    if (!r->error.empty()) pcg::set_error(r->error);   // report in the polling thread
     S->tickets.erase(it);
     return st;
 }

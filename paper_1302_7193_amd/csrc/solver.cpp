@@ -6,8 +6,8 @@
 // returns at once when the flag of its right-hand side is set, so a chunk
 // that overshoots the exit costs only empty launches.  With an adaptive
 // chunk (K = the previous solve's iteration count) a repeated solve issues
-// exactly the launches it needs.  Chunks are captured once as HIP graphs
-// and replayed.
+// exactly the launches it needs.  Chunks are built once as HIP graphs
+// (explicit kernel nodes) and replayed.
 //
 // Mixed precision: FP64 residual r = b - A x (scaled to FP32), an FP32 inner
 // solve of A d = r to a relative tolerance, FP64 update x += d / scale,
@@ -45,7 +45,9 @@ struct Layout {
     size_t total = 0;
 };
 
-Layout plan_n(int64_t cells, const pcg_solve_opts& o, int64_t nrhs)
+// Workspace layout.  `slots`: partial-sum slots per right-hand side (the
+// largest workgroup count any kernel of the solve may use).
+Layout plan_n(int64_t cells, const pcg_solve_opts& o, int64_t nrhs, int64_t slots)
 {
     Layout w;
     size_t off = 0;
@@ -67,8 +69,7 @@ Layout plan_n(int64_t cells, const pcg_solve_opts& o, int64_t nrhs)
         w.p = take(8 * n);
         w.q = take(8 * n);
     }
-    // partial-sum slots for any tuning (block caps never exceed kMaxBlocks)
-    const int64_t nb = std::max(kMaxBlocks, blas_blocks(cells));
+    const int64_t nb = std::max(slots, blas_blocks(cells));
     w.part = take((size_t)nrhs * nb * kRedSlots * sizeof(double));
     w.st = take((size_t)nrhs * sizeof(SolverState));
     w.st_o = take((size_t)nrhs * sizeof(SolverState));
@@ -76,9 +77,12 @@ Layout plan_n(int64_t cells, const pcg_solve_opts& o, int64_t nrhs)
     return w;
 }
 
+// With the problem's current tunings (a workspace sized before a tuning
+// change may be too small afterwards; pcg_solve then reports PCG_E_NOMEM).
 Layout plan(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
 {
-    return plan_n(P->geom.n, o, nrhs);
+    return plan_n(P->geom.n, o, nrhs,
+                  std::max(blocks_per_rhs(P, PCG_F64), blocks_per_rhs(P, PCG_F32)));
 }
 
 std::string hip_msg(hipError_t e, const char* what)
@@ -184,6 +188,9 @@ pcg_status issue_chunk(const ColArgs& a, int64_t nrhs, int K, hipStream_t s, int
     return launch<T>(Kind::Fixup, a, nrhs, s, count);
 }
 
+// The chunk as an explicitly built HIP graph (kernel nodes in sequence).  No
+// stream capture is involved, so building is independent of what other host
+// threads do with their streams.
 template <typename T>
 pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, int64_t nrhs, int K,
                        hipGraphExec_t* out)
@@ -203,22 +210,47 @@ pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, int64_t nrhs
         *out = it->second;
         return PCG_OK;
     }
-    if (!P->capture_stream)
-        PCG_HIP(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking),
-                "hipStreamCreateWithFlags");
-    PCG_HIP(hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeThreadLocal),
-            "hipStreamBeginCapture");
-    int dummy = 0;
-    pcg_status st = issue_chunk<T>(a, nrhs, K, P->capture_stream, dummy);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(P->capture_stream, &graph);
-    if (st != PCG_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return st;
+    std::vector<KernelLaunch> seq;
+    auto add = [&](Kind k) -> bool {
+        KernelLaunch l[2];
+        const int n = column_launches<T>(k, a, nrhs, l);
+        for (int i = 0; i < n; ++i) seq.push_back(l[i]);
+        return n > 0;
+    };
+    for (int i = 0; i < K; ++i)
+        if (!add(Kind::FusedApply) || !add(Kind::FusedPrec)) {
+            set_error("graph: no kernel for this shape (internal)");
+            return PCG_E_DEVICE;
+        }
+    if (!add(Kind::Fixup)) {
+        set_error("graph: no kernel for this shape (internal)");
+        return PCG_E_DEVICE;
     }
-    PCG_HIP(e, "hipStreamEndCapture");
+    hipGraph_t graph = nullptr;
+    PCG_HIP(hipGraphCreate(&graph, 0), "hipGraphCreate");
+    ColArgs args = a;   // node parameters are copied when the node is added
+    void* params[] = {&args};
+    hipGraphNode_t prev = nullptr;
+    for (const KernelLaunch& l : seq) {
+        hipKernelNodeParams np{};
+        np.func = const_cast<void*>(l.func);
+        np.gridDim = l.grid;
+        np.blockDim = l.block;
+        np.sharedMemBytes = 0;
+        np.kernelParams = params;
+        np.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        const hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr,
+                                                   prev ? 1 : 0, &np);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            set_error(hip_msg(e, "hipGraphAddKernelNode"));
+            return PCG_E_DEVICE;
+        }
+        prev = node;
+    }
     hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     PCG_HIP(e, "hipGraphInstantiate");
     P->graphs[key] = exec;
@@ -257,7 +289,7 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a,
         PCG_HIP(hipEventRecord(P->events[2 * i], s), "hipEventRecord");
         PCG_HIP(launch_column_main<T>(k, a, nrhs, s), "kernel launch");
         PCG_HIP(hipEventRecord(P->events[2 * i + 1], s), "hipEventRecord");
-        PCG_HIP(launch_column_finalize(k, a, nrhs, s), "finalize launch");
+        PCG_HIP(launch_column_finalize<T>(k, a, nrhs, s), "finalize launch");
         ++info.launches;
         is_a.push_back(kind_a);
         return PCG_OK;
@@ -638,7 +670,10 @@ pcg_status time_tuning(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
     // iter = 1: time the general kernels (alpha = beta = 0, p = q = 0 after
     // the start kernel), not the first-iteration specialisations
     std::vector<SolverState> hs(nrhs, fresh_state(0.0, 0.0, 1 << 30, 1.0));
-    for (auto& h : hs) h.iter = 1;
+    for (auto& h : hs) {
+        h.iter = 1;
+        h.r0norm = 1.0;   // the exit test divides by it
+    }
     int cnt = 0;
     for (int i = -1; i < reps; ++i) {   // rep -1 warms up
         if (upload_states(P, a.st, hs.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
@@ -685,7 +720,7 @@ pcg_status autotune(pcg_problem* P, int dtype, int64_t nrhs, hipStream_t s, Tuni
     pcg_solve_opts o;
     pcg_default_opts(&o);
     o.precision = dtype == PCG_F64 ? PCG_PREC_FP64 : PCG_PREC_MIXED;
-    const Layout w = plan(P, o, nrhs);
+    const Layout w = plan_n(P->geom.n, o, nrhs, kMaxBlocks);   // any candidate fits
     const size_t ubytes = al256((size_t)P->geom.n * nrhs * (dtype == PCG_F64 ? 8 : 4));
     DeviceBuffer buf;
     hipError_t e = hipMalloc(&buf.p, w.total + ubytes);
@@ -721,7 +756,7 @@ pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
         sh.M = 1;
         while (sh.M * L < nz) sh.M <<= 1;
         if (sh.M * L >= 2 * nz && L > 1 && sh.M > 1) continue;   // lanes idle: skip
-        for (int64_t total = 512; total <= 16384; total <<= 1) {
+        for (int64_t total = 512; total <= kMaxBlocks; total <<= 1) {
             const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(kMaxBlocks, total / nrhs));
             for (int mode = 0; mode < 2; ++mode) {
                 Tuning t;
@@ -752,9 +787,10 @@ pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
 
 }  // namespace
 
+// Workspace of one served request (default tunings, whatever the shape).
 size_t request_bytes(int64_t n, const pcg_solve_opts& o)
 {
-    return plan_n(n, o, 1).total;
+    return plan_n(n, o, 1, kDefaultCap).total;
 }
 
 size_t workspace_bytes(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)

@@ -408,7 +408,7 @@ def test_fp64_solve_parity_under_tunings(L, cap, mode):
 def test_set_tuning_rejects_bad_values():
     p = pcg.Problem(GRIDS["7x6x1024-tall"]())
     for bad in (dict(lanes_per_column=32), dict(lanes_per_column=3), dict(block_cap=0),
-                dict(block_cap=20000), dict(reduction=2)):
+                dict(block_cap=70000), dict(reduction=2)):
         with pytest.raises(pcg.PCGError):
             pcg.pcg_set_tuning(p, pcg.PCG_F64, **bad)
     t = pcg.pcg_get_tuning(p, pcg.PCG_F64)
