@@ -197,10 +197,23 @@ typedef struct {
 pcg_status pcg_get_tuning(const pcg_problem *p, int32_t dtype, pcg_tuning *out);
 pcg_status pcg_set_tuning(pcg_problem *p, int32_t dtype, const pcg_tuning *t);
 
+/* Tuning cache: launch parameters keyed by (GPU architecture, n_x, n_y,
+ * n_z, dtype, nrhs).  Loaded on first use from tuning_cache.txt next to
+ * libpcg.so, or from the file named by the PCG_TUNING_CACHE environment
+ * variable (empty: none).  A solve of nrhs right-hand sides uses the entry
+ * for its shape unless the problem's tuning was set explicitly
+ * (pcg_set_tuning, pcg_autotune); pcg_get_tuning reports the tuning a
+ * one-right-hand-side solve would use.  pcg_autotune adds its result to the
+ * in-memory table; pcg_tuning_cache_save writes the table (path NULL: the
+ * default file); pcg_tuning_cache_load merges a file into it. */
+pcg_status pcg_tuning_cache_load(const char *path);
+pcg_status pcg_tuning_cache_save(const char *path);
+
 /* Autotuner: times fused iterations (kernels A and B over nrhs right-hand
  * sides, on synthetic vectors) for every supported lanes_per_column, a
  * ladder of block caps and both reduction modes, keeps the fastest for
- * (p, dtype) and returns it in best (may be NULL).  A set-up utility: it
+ * (p, dtype), records it in the tuning cache for (shape, dtype, nrhs) and
+ * returns it in best (may be NULL).  A set-up utility: it
  * allocates (and frees) its own device scratch of about 5 vectors of
  * nrhs*n values of dtype.  Blocks. */
 pcg_status pcg_autotune(pcg_problem *p, int32_t dtype, int32_t nrhs, void *stream,

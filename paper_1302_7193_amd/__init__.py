@@ -109,6 +109,8 @@ _sig = {
     "pcg_get_tuning": (_S, [_P, ctypes.c_int32, ctypes.POINTER(pcg_tuning)]),
     "pcg_set_tuning": (_S, [_P, ctypes.c_int32, ctypes.POINTER(pcg_tuning)]),
     "pcg_autotune": (_S, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(pcg_tuning)]),
+    "pcg_tuning_cache_load": (_S, [ctypes.c_char_p]),
+    "pcg_tuning_cache_save": (_S, [ctypes.c_char_p]),
     "pcg_request_bytes": (ctypes.c_size_t, [ctypes.POINTER(pcg_problem_desc),
                                             ctypes.POINTER(pcg_solve_opts)]),
     "pcg_server_create": (_S, [ctypes.POINTER(pcg_server_opts), _P, ctypes.c_size_t,
@@ -306,6 +308,14 @@ def pcg_autotune(p: Problem, dtype: int, nrhs: int = 1, stream=None) -> pcg_tuni
     _check(_lib.pcg_autotune(p.handle, dtype, nrhs, _stream(stream), ctypes.byref(t)),
            "pcg_autotune")
     return t
+
+
+def pcg_tuning_cache_load(path: str | None = None) -> None:
+    _check(_lib.pcg_tuning_cache_load(path.encode() if path else None), "pcg_tuning_cache_load")
+
+
+def pcg_tuning_cache_save(path: str | None = None) -> None:
+    _check(_lib.pcg_tuning_cache_save(path.encode() if path else None), "pcg_tuning_cache_save")
 
 
 def solve(desc: pcg_problem_desc, b: torch.Tensor, x0: torch.Tensor | None = None, **opts):

@@ -186,6 +186,14 @@ pcg_status pcg_problem_create(const pcg_problem_desc* desc, pcg_problem** out)
     }
     P->desc = *desc;
     P->device = dev;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            std::string a = prop.gcnArchName;
+            P->arch = a.substr(0, a.find(':'));
+        }
+        if (P->arch.empty()) P->arch = "unknown";
+    }
     build_tables(*desc, P->geom, P->vert64, P->lu64);
     for (int d = 0; d < 2; ++d) {
         P->tune[d].shape = default_shape(desc->nz, d);
@@ -258,9 +266,11 @@ pcg_status pcg_apply(pcg_problem* P, int32_t dtype, const void* x, void* y, void
     }
     if (check_aligned({x, y}, "pcg_apply") != PCG_OK) return PCG_E_INVALID;
     return on_device(P->device, [&]() -> pcg_status {
+        TuneScope ts(P, 1);
         ColArgs a{};
         a.g = P->geom;
         a.L = P->tune[dtype].shape.L;
+        a.red_mode = P->tune[dtype].red_mode;
         a.blocks_per_rhs = blocks_per_rhs(P, dtype);
         a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
         a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
@@ -285,9 +295,11 @@ pcg_status pcg_precond(pcg_problem* P, int32_t dtype, const void* r, void* z, vo
     }
     if (check_aligned({r, z}, "pcg_precond") != PCG_OK) return PCG_E_INVALID;
     return on_device(P->device, [&]() -> pcg_status {
+        TuneScope ts(P, 1);
         ColArgs a{};
         a.g = P->geom;
         a.L = P->tune[dtype].shape.L;
+        a.red_mode = P->tune[dtype].red_mode;
         a.blocks_per_rhs = blocks_per_rhs(P, dtype);
         a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
         a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
@@ -353,9 +365,10 @@ pcg_status pcg_get_tuning(const pcg_problem* P, int32_t dtype, pcg_tuning* out)
         set_error("pcg_get_tuning: NULL argument or bad dtype");
         return PCG_E_INVALID;
     }
-    out->lanes_per_column = P->tune[dtype].shape.L;
-    out->block_cap = (int32_t)P->tune[dtype].block_cap;
-    out->reduction = P->tune[dtype].red_mode;
+    const Tuning t = effective_tuning(P, dtype, 1);
+    out->lanes_per_column = t.shape.L;
+    out->block_cap = (int32_t)t.block_cap;
+    out->reduction = t.red_mode;
     return PCG_OK;
 }
 
@@ -381,6 +394,7 @@ pcg_status pcg_set_tuning(pcg_problem* P, int32_t dtype, const pcg_tuning* t)
     P->tune[dtype].shape = sh;
     P->tune[dtype].block_cap = t->block_cap;
     P->tune[dtype].red_mode = t->reduction;
+    P->tune_explicit[dtype] = true;
     return PCG_OK;
 }
 
@@ -391,12 +405,20 @@ pcg_status pcg_autotune(pcg_problem* P, int32_t dtype, int32_t nrhs, void* strea
         set_error("pcg_autotune: NULL problem, bad dtype or nrhs < 1");
         return PCG_E_INVALID;
     }
+    Tuning t;
     pcg_status st = on_device(P->device, [&]() -> pcg_status {
-        Tuning t;
         return autotune(P, dtype, nrhs, static_cast<hipStream_t>(stream), &t);
     });
-    if (st == PCG_OK && best) return pcg_get_tuning(P, dtype, best);
-    return st;
+    if (st != PCG_OK) return st;
+    P->tune[dtype] = t;
+    P->tune_explicit[dtype] = true;
+    tuning_store(P, dtype, nrhs, t);
+    if (best) {
+        best->lanes_per_column = t.shape.L;
+        best->block_cap = (int32_t)t.block_cap;
+        best->reduction = t.red_mode;
+    }
+    return PCG_OK;
 }
 
 size_t pcg_csr_bytes(const pcg_problem* P, int32_t dtype)

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <map>
+#include <string>
 #include <mutex>
 #include <tuple>
 #include <vector>
@@ -32,6 +33,17 @@ struct GraphKey {
 
 }  // namespace pcg
 
+struct pcg_problem;
+
+namespace pcg {
+
+// Tuning cache (tuning_cache.cpp).
+bool tuning_lookup(const pcg_problem* P, int dtype, int64_t nrhs, Tuning* out);
+void tuning_store(const pcg_problem* P, int dtype, int64_t nrhs, const Tuning& t);
+Tuning effective_tuning(const pcg_problem* P, int dtype, int64_t nrhs);
+
+}  // namespace pcg
+
 struct pcg_problem {
     pcg_problem_desc desc{};
     pcg::Geom geom{};
@@ -42,10 +54,38 @@ struct pcg_problem {
     const double* d_lu64 = nullptr;
     const float* d_vert32 = nullptr;
     const float* d_lu32 = nullptr;
+    std::string arch;                      // e.g. "gfx950" (tuning-cache key)
     pcg::Tuning tune[2];                   // launch parameters per dtype
+    bool tune_explicit[2] = {false, false};  // set by pcg_set_tuning / pcg_autotune
     int last_iters[2] = {0, 0};            // adaptive chunk length per precision
     pcg::SolverState* pinned_states = nullptr;  // host-pinned staging of solver states
     int64_t pinned_cap = 0;
     std::map<pcg::GraphKey, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> events;
 };
+
+namespace pcg {
+
+// For the duration of one call, the problem's tunings are the effective ones
+// for nrhs right-hand sides (explicit setting, else the tuning cache, else
+// the defaults).
+class TuneScope {
+public:
+    TuneScope(pcg_problem* P, int64_t nrhs) : P_(P)
+    {
+        for (int d = 0; d < 2; ++d) {
+            saved_[d] = P->tune[d];
+            P->tune[d] = effective_tuning(P, d, nrhs);
+        }
+    }
+    ~TuneScope()
+    {
+        for (int d = 0; d < 2; ++d) P_->tune[d] = saved_[d];
+    }
+
+private:
+    pcg_problem* P_;
+    Tuning saved_[2];
+};
+
+}  // namespace pcg

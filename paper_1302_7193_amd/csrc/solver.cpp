@@ -787,20 +787,23 @@ pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
 
 }  // namespace
 
-// Workspace of one served request (default tunings, whatever the shape).
+// Workspace of one served request, enough for any tuning of its shape.
 size_t request_bytes(int64_t n, const pcg_solve_opts& o)
 {
-    return plan_n(n, o, 1, kDefaultCap).total;
+    return plan_n(n, o, 1, kMaxBlocks).total;
 }
 
-size_t workspace_bytes(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
+size_t workspace_bytes(const pcg_problem* Pc, const pcg_solve_opts& o, int64_t nrhs)
 {
+    pcg_problem* P = const_cast<pcg_problem*>(Pc);
+    TuneScope ts(P, nrhs);
     return plan(P, o, nrhs).total;
 }
 
 pcg_status solve(pcg_problem* P, const double* b, double* x, void* workspace, size_t ws_bytes,
                  const pcg_solve_opts& o, int64_t nrhs, pcg_result* res, hipStream_t s)
 {
+    TuneScope ts(P, nrhs);
     const Layout w = plan(P, o, nrhs);
     if (ws_bytes < w.total) {
         std::ostringstream m;

@@ -96,3 +96,26 @@ def test_workspace_and_csr_sizes_are_host_computable():
     assert pcg._lib.pcg_workspace_bytes(None, None, 1) == 0
     assert pcg._lib.pcg_apply(None, 0, None, None, None) == pcg.PCG_E_INVALID
     assert "NULL" in pcg.pcg_last_error()
+
+
+def test_tuning_cache_file_round_trip(lib, tmp_path):
+    """The tuning cache parses its text format (skipping comments and
+    malformed or unsupported entries) and writes back what it holds."""
+    src = tmp_path / "in.txt"
+    src.write_text("# comment line\n"
+                   "gfx950 97 89 61 0 1 16 2048 1   # trailing comment\n"
+                   "gfx950 97 89 61 1 64 32 65536 0\n"
+                   "gfx950 97 89 61 0 1 48 2048 1\n"          # L not a power of two
+                   "gfx950 97 89 61 0 1 16 0 1\n"             # block cap below 1
+                   "gfx950 97 89 61 2 1 16 2048 1\n"          # unknown dtype
+                   "gfx950 97 89\n")                          # truncated
+    lib.pcg_tuning_cache_load.argtypes = [ctypes.c_char_p]
+    lib.pcg_tuning_cache_save.argtypes = [ctypes.c_char_p]
+    assert lib.pcg_tuning_cache_load(str(src).encode()) == 0
+    assert lib.pcg_tuning_cache_load(str(tmp_path / "missing.txt").encode()) != 0
+    out = tmp_path / "out.txt"
+    assert lib.pcg_tuning_cache_save(str(out).encode()) == 0
+    rows = [ln.split() for ln in out.read_text().splitlines() if ln and not ln.startswith("#")]
+    mine = sorted(r for r in rows if r[1:4] == ["97", "89", "61"])
+    assert mine == [["gfx950", "97", "89", "61", "0", "1", "16", "2048", "1"],
+                    ["gfx950", "97", "89", "61", "1", "64", "32", "65536", "0"]]

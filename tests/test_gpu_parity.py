@@ -450,3 +450,34 @@ def test_mixed_precision_zero_start_ignores_x():
     st, r = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
     assert st == pcg.PCG_OK
     assert oracle.residual_norm(A, b, x.cpu().numpy()) / np.linalg.norm(b) < 1.05e-8
+
+
+def test_tuning_cache_entry_applies_unless_set_explicitly(tmp_path):
+    """A cache entry for a shape changes the launch parameters of new problems
+    of that shape (solve bitwise equal to the same tuning set explicitly);
+    an explicit setting wins over the cache."""
+    d = make_desc(23, 19, 61, 1e4)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    f = tmp_path / "cache.txt"
+    f.write_text(f"{arch} 23 19 61 0 1 8 3 0\n")
+    pcg.pcg_tuning_cache_load(str(f))
+    b = cuda(si.rhs_uniform(d.nx, d.ny, d.nz, 44))
+    o = pcg.pcg_default_opts()
+
+    def run(p):
+        x = torch.zeros_like(b)
+        st, r = pcg.pcg_solve(p, b, x, pcg.workspace(p, o), o)
+        assert st == pcg.PCG_OK
+        return x.cpu(), r["iterations"]
+
+    cached = pcg.Problem(d)
+    t = pcg.pcg_get_tuning(cached, pcg.PCG_F64)
+    assert (t.lanes_per_column, t.block_cap, t.reduction) == (8, 3, 0)
+    explicit = pcg.Problem(d)
+    pcg.pcg_set_tuning(explicit, pcg.PCG_F64, lanes_per_column=8, block_cap=3, reduction=0)
+    xc, ic = run(cached)
+    xe, ie = run(explicit)
+    assert ic == ie and torch.equal(xc, xe)
+    pcg.pcg_set_tuning(cached, pcg.PCG_F64, lanes_per_column=64, block_cap=16384, reduction=1)
+    t = pcg.pcg_get_tuning(cached, pcg.PCG_F64)
+    assert (t.lanes_per_column, t.block_cap, t.reduction) == (64, 16384, 1)
