@@ -11,7 +11,8 @@ paper:
 
 * ``assemble``       Sec. 3.1, eqs. ModelEqnCubedSphere / DiagonalMatrix /
                      TridiagonalMatrix, written as an explicit finite-volume
-                     CSR matrix on a flat graded grid.
+                     CSR matrix on a flat graded grid (uniform or stretched
+                     tensor-product horizontal cells).
 * ``line_blocks``    Sec. 4.1: the preconditioner is A with the couplings
                      between vertical columns dropped.
 * ``line_solve``     Sec. 4.2: one tridiagonal (Thomas) solve per column.
@@ -79,6 +80,12 @@ def _load():
     lib.orc_residual_norm.restype = ctypes.c_double
     lib.orc_row_apply.argtypes = geo + [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
     lib.orc_row_apply.restype = ctypes.c_double
+    geo_w = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double,
+             ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+    lib.orc_assemble_geom.argtypes = geo_w + [_i64p, _i32p, _dp]
+    lib.orc_assemble_geom.restype = ctypes.c_long
+    lib.orc_row_apply_geom.argtypes = geo_w + [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+    lib.orc_row_apply_geom.restype = ctypes.c_double
     _lib = lib
     return lib
 
@@ -95,7 +102,9 @@ def _f64(a):
 class Grid:
     """Flat tensor-product grid: n_x*n_y horizontal cells of size dx*dy, n_z
     levels over height H graded with ratio q (finest at k = 0), diffusion
-    K_h horizontally and K_v vertically, periodic or Dirichlet sides."""
+    K_h horizontally and K_v vertically, periodic or Dirichlet sides.
+    Optional ``xw`` / ``yw`` (tuples of n_x / n_y widths) make the horizontal
+    grid stretched; dx and dy are then unused."""
     nx: int
     ny: int
     nz: int
@@ -107,13 +116,29 @@ class Grid:
     kv: float
     per_x: bool = False
     per_y: bool = False
+    xw: tuple | None = None
+    yw: tuple | None = None
 
     @property
     def n(self) -> int:
         return self.nx * self.ny * self.nz
 
+    @property
+    def stretched(self) -> bool:
+        return self.xw is not None or self.yw is not None
+
+    def widths(self):
+        xw = np.full(self.nx, self.dx) if self.xw is None else _f64(self.xw)
+        yw = np.full(self.ny, self.dy) if self.yw is None else _f64(self.yw)
+        assert xw.shape == (self.nx,) and yw.shape == (self.ny,)
+        return xw, yw
+
     def args(self):
         return (self.nx, self.ny, self.nz, self.dx, self.dy, self.H, self.q,
+                self.kh, self.kv, int(self.per_x), int(self.per_y))
+
+    def args_w(self, xw, yw):
+        return (self.nx, self.ny, self.nz, _d(xw), _d(yw), self.H, self.q,
                 self.kh, self.kv, int(self.per_x), int(self.per_y))
 
 
@@ -159,8 +184,13 @@ def assemble(g: Grid) -> CSR:
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     col = np.zeros(7 * n, dtype=np.int32)
     val = np.zeros(7 * n, dtype=np.float64)
-    nnz = _load().orc_assemble(*g.args(), row_ptr.ctypes.data_as(_i64p),
-                               col.ctypes.data_as(_i32p), _d(val))
+    if g.stretched:
+        xw, yw = g.widths()
+        nnz = _load().orc_assemble_geom(*g.args_w(xw, yw), row_ptr.ctypes.data_as(_i64p),
+                                        col.ctypes.data_as(_i32p), _d(val))
+    else:
+        nnz = _load().orc_assemble(*g.args(), row_ptr.ctypes.data_as(_i64p),
+                                   col.ctypes.data_as(_i32p), _d(val))
     return CSR(n, row_ptr, col[:nnz].copy(), val[:nnz].copy())
 
 
@@ -212,6 +242,9 @@ def residual_norm(A: CSR, b, x) -> float:
 def row_apply(g: Grid, i: int, j: int, k: int, x) -> float:
     """(A x) at cell (i, j, k) without assembling A (for sampled checks on
     grids too large to assemble)."""
+    if g.stretched:
+        xw, yw = g.widths()
+        return _load().orc_row_apply_geom(*g.args_w(xw, yw), i, j, k, _d(_f64(x)))
     return _load().orc_row_apply(*g.args(), i, j, k, _d(_f64(x)))
 
 

@@ -79,41 +79,46 @@ static long cell_index(int i, int j, int k, int ny, int nz)
 /* The entries of row c = (i,j,k) of A.  Writes up to 7 (column, value)
  * pairs, the diagonal first, and returns their number.
  *
- * Cell volume V = dx*dy*dz[k]:
+ * Horizontal cell widths dxs[0..nx-1] and dys[0..ny-1] (a tensor-product
+ * grid, uniform or stretched; Sec. 3.1 allows any horizontal geometry, only
+ * |T| and the face weights alpha_{T,T'} change).  Cell volume
+ * V = dxs[i]*dys[j]*dz[k]:
  *   A_cc += V                                  (zero-order term)
  *   for every face f of the cell, transmissibility
  *     t_f = diffusion coefficient * face area / distance between centres:
  *     interior or periodic neighbour n:  A_cc += t_f,  A_cn -= t_f
  *     Dirichlet face (ghost value -u):   A_cc += diffusion * area / (half cell)
- * A neighbour that appears twice (periodic direction of length 1 or 2) is
- * stored twice. */
-static int build_row(int nx, int ny, int nz, double dx, double dy, const double *dz,
-                     double k_h, double k_v, int per_x, int per_y,
+ * The distance between the centres of horizontal neighbours is the mean of
+ * their widths (across the periodic seam too).  A neighbour that appears
+ * twice (periodic direction of length 1 or 2) is stored twice. */
+static int build_row(int nx, int ny, int nz, const double *dxs, const double *dys,
+                     const double *dz, double k_h, double k_v, int per_x, int per_y,
                      int i, int j, int k, int32_t *col, double *val)
 {
     long c = cell_index(i, j, k, ny, nz);
+    double dx = dxs[i], dy = dys[j];
     double diag = dx * dy * dz[k];
     int pos = 1;
-    /* faces normal to x: area dy*dz[k], centre distance dx */
+    /* faces normal to x: area dy*dz[k] */
     for (int s = -1; s <= 1; s += 2) {
         int ii = i + s;
         if (ii < 0 || ii >= nx) {
             if (!per_x) { diag += k_h * dy * dz[k] / (0.5 * dx); continue; }
             ii = (ii + nx) % nx;
         }
-        double t = k_h * dy * dz[k] / dx;
+        double t = k_h * dy * dz[k] / (0.5 * (dx + dxs[ii]));
         diag += t;
         col[pos] = (int32_t)cell_index(ii, j, k, ny, nz);
         val[pos++] = -t;
     }
-    /* faces normal to y: area dx*dz[k], centre distance dy */
+    /* faces normal to y: area dx*dz[k] */
     for (int s = -1; s <= 1; s += 2) {
         int jj = j + s;
         if (jj < 0 || jj >= ny) {
             if (!per_y) { diag += k_h * dx * dz[k] / (0.5 * dy); continue; }
             jj = (jj + ny) % ny;
         }
-        double t = k_h * dx * dz[k] / dy;
+        double t = k_h * dx * dz[k] / (0.5 * (dy + dys[jj]));
         diag += t;
         col[pos] = (int32_t)cell_index(i, jj, k, ny, nz);
         val[pos++] = -t;
@@ -140,11 +145,12 @@ static int build_row(int nx, int ny, int nz, double dx, double dy, const double 
     return pos;
 }
 
-/* Assemble A in CSR.  row_ptr has n+1 entries; col/val have room for 7n.
- * Returns the number of stored entries. */
-long orc_assemble(int nx, int ny, int nz, double dx, double dy, double H, double q,
-                  double k_h, double k_v, int per_x, int per_y,
-                  int64_t *row_ptr, int32_t *col, double *val)
+/* Assemble A in CSR on a grid with horizontal widths dxs[nx], dys[ny].
+ * row_ptr has n+1 entries; col/val have room for 7n.  Returns the number of
+ * stored entries. */
+long orc_assemble_geom(int nx, int ny, int nz, const double *dxs, const double *dys,
+                       double H, double q, double k_h, double k_v, int per_x, int per_y,
+                       int64_t *row_ptr, int32_t *col, double *val)
 {
     double *dz = (double *)malloc(sizeof(double) * (size_t)nz);
     orc_vertical_spacing(nz, H, q, dz);
@@ -153,11 +159,31 @@ long orc_assemble(int nx, int ny, int nz, double dx, double dy, double H, double
     for (int i = 0; i < nx; ++i)
         for (int j = 0; j < ny; ++j)
             for (int k = 0; k < nz; ++k) {
-                pos += build_row(nx, ny, nz, dx, dy, dz, k_h, k_v, per_x, per_y,
+                pos += build_row(nx, ny, nz, dxs, dys, dz, k_h, k_v, per_x, per_y,
                                  i, j, k, col + pos, val + pos);
                 row_ptr[cell_index(i, j, k, ny, nz) + 1] = pos;
             }
     free(dz);
+    return pos;
+}
+
+static double *constant_widths(int n, double w)
+{
+    double *a = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int i = 0; i < n; ++i) a[i] = w;
+    return a;
+}
+
+/* Assemble A on the uniform grid of cell size dx * dy. */
+long orc_assemble(int nx, int ny, int nz, double dx, double dy, double H, double q,
+                  double k_h, double k_v, int per_x, int per_y,
+                  int64_t *row_ptr, int32_t *col, double *val)
+{
+    double *dxs = constant_widths(nx, dx), *dys = constant_widths(ny, dy);
+    long pos = orc_assemble_geom(nx, ny, nz, dxs, dys, H, q, k_h, k_v, per_x, per_y,
+                                 row_ptr, col, val);
+    free(dxs);
+    free(dys);
     return pos;
 }
 
@@ -319,18 +345,32 @@ double orc_residual_norm(long n, const int64_t *row_ptr, const int32_t *col,
     return sqrt(s);
 }
 
-/* Row (i,j,k) of A x, for sampled checks on grids too large to assemble. */
-double orc_row_apply(int nx, int ny, int nz, double dx, double dy, double H, double q,
-                     double k_h, double k_v, int per_x, int per_y,
-                     int i, int j, int k, const double *x)
+/* Row (i,j,k) of A x, for sampled checks on grids too large to assemble
+ * (horizontal widths dxs[nx], dys[ny]). */
+double orc_row_apply_geom(int nx, int ny, int nz, const double *dxs, const double *dys,
+                          double H, double q, double k_h, double k_v, int per_x, int per_y,
+                          int i, int j, int k, const double *x)
 {
     int32_t col[7];
     double val[7];
     double *dz = (double *)malloc(sizeof(double) * (size_t)nz);
     orc_vertical_spacing(nz, H, q, dz);
-    int cnt = build_row(nx, ny, nz, dx, dy, dz, k_h, k_v, per_x, per_y, i, j, k, col, val);
+    int cnt = build_row(nx, ny, nz, dxs, dys, dz, k_h, k_v, per_x, per_y, i, j, k, col, val);
     double s = 0.0;
     for (int e = 0; e < cnt; ++e) s += val[e] * x[col[e]];
     free(dz);
+    return s;
+}
+
+/* The same on the uniform grid of cell size dx * dy. */
+double orc_row_apply(int nx, int ny, int nz, double dx, double dy, double H, double q,
+                     double k_h, double k_v, int per_x, int per_y,
+                     int i, int j, int k, const double *x)
+{
+    double *dxs = constant_widths(nx, dx), *dys = constant_widths(ny, dy);
+    double s = orc_row_apply_geom(nx, ny, nz, dxs, dys, H, q, k_h, k_v, per_x, per_y,
+                                  i, j, k, x);
+    free(dxs);
+    free(dys);
     return s;
 }

@@ -135,6 +135,31 @@ def rhs_smooth_noise_torch(nx, ny, nz, seed, noise=0.01, device="cuda"):
     return out
 
 
+def widths_sine(n: int, amp: float = 0.5, length: float = 1.0) -> np.ndarray:
+    """Smoothly stretched horizontal cell widths: w_i proportional to
+    1 + amp*sin(2*pi*(i + 1/2)/n), scaled so they sum to ``length``.  The
+    ratio of the largest to the smallest width is about (1+amp)/(1-amp), and
+    the variation is periodic, so the same widths suit periodic sides."""
+    w = 1.0 + amp * np.sin(2.0 * np.pi * (np.arange(n) + 0.5) / n)
+    return w * (length / w.sum())
+
+
+def widths_graded(n: int, ratio: float = 1.05, length: float = 1.0) -> np.ndarray:
+    """Cell widths refined towards both ends (walls): w_i proportional to
+    ratio**min(i, n-1-i), scaled to sum to ``length``."""
+    i = np.arange(n)
+    w = ratio ** np.minimum(i, n - 1 - i).astype(np.float64)
+    return w * (length / w.sum())
+
+
+def widths_random(n: int, seed: int, lo: float = 0.5, hi: float = 1.5,
+                  length: float = 1.0) -> np.ndarray:
+    """Independent widths drawn uniformly from [lo, hi) (stream ``seed``),
+    scaled to sum to ``length``; neighbouring cells differ arbitrarily."""
+    w = lo + (hi - lo) * uniform01(seed, 0, n)
+    return w * (length / w.sum())
+
+
 def rhs_batch(nx: int, ny: int, nz: int, seeds) -> np.ndarray:
     """Stack of U[-1, 1) right-hand sides, one row per seed."""
     return np.stack([rhs_uniform(nx, ny, nz, s) for s in seeds])
