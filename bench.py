@@ -44,8 +44,19 @@ def solve_kernel_bytes(kernel, iterations, n):
     if kernel == "fused_apply":
         return n * (BYTES["fused_apply_first"] + BYTES["fused_apply"] * (iterations - 1))
     return n * (BYTES["fused_prec_first"] + BYTES["fused_prec"] * iterations)
-KERNEL_SYMBOL = {"fused_apply": "k_fused_apply<double, 4, true>",
-                 "fused_prec": "k_fused_prec<double, 4, true>"}
+KERNEL_PATTERN = {"fused_apply": r"k_fused_apply<double, \d+, (true|false), false>",
+                  "fused_prec": r"k_fused_prec<double, \d+, (true|false), false>"}
+
+
+def kernel_symbol(kernel, lanes_per_column, nz, elem=8, stretched=False):
+    """Template instance of a fused kernel that runs for this launch shape:
+    M levels per lane, 16-byte vector path when whole chunks are aligned."""
+    m = 1
+    while m * lanes_per_column < nz:
+        m *= 2
+    vec = nz % m == 0 and (m * elem) % 16 == 0 and (nz * elem) % 16 == 0
+    t = "double" if elem == 8 else "float"
+    return "k_%s<%s, %d, %s, %s>" % (kernel, t, m, str(vec).lower(), str(stretched).lower())
 
 
 def log(*a):
@@ -60,9 +71,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload_tag: str):
+def measured_traffic(kernel: str, workload_tag: str, symbol: str):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if
-    they were taken on the current kernel source (else None)."""
+    they were taken on the current kernel source and launch shape (else
+    None)."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload_tag))
     if not os.path.exists(path):
         return None
@@ -72,7 +84,7 @@ def measured_traffic(kernel: str, workload_tag: str):
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("kernel") != symbol:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -88,6 +100,7 @@ def run_main(pcg, si, torch, steps, warmup):
     b = torch.from_numpy(si.rhs_uniform(nx, ny, nz, 1)).cuda()
     x = torch.empty_like(b)
     opts = pcg.pcg_default_opts(rtol=1e-8, profile=1, x0_zero=1, graph_chunk=-1)
+    tuning = pcg.pcg_get_tuning(P, pcg.PCG_F64).as_dict()
     ws = pcg.workspace(P, opts)
     for _ in range(warmup):
         st, r = pcg.pcg_solve(P, b, x, ws, opts)
@@ -108,8 +121,8 @@ def run_main(pcg, si, torch, steps, warmup):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     assert st == pcg.PCG_OK, r
-    return dict(P=P, b=b, x=x, n=n, steps=steps, iters=iters, elapsed=elapsed, ms=ms, cnt=cnt,
-                launches=launches, last=r)
+    return dict(P=P, b=b, x=x, n=n, nz=nz, steps=steps, iters=iters, elapsed=elapsed, ms=ms,
+                cnt=cnt, launches=launches, last=r, tuning=tuning)
 
 
 def cuda_time(torch, fn, reps):
@@ -212,6 +225,7 @@ def extras(pcg, si, torch, main):
     out["mixed_1024x1024x128"] = res3
     del P3, b3, x3
 
+    out["stretched_512x512x128_fp64"] = stretched(pcg, si, torch, out["fused_fp64_graph"])
     out["batched_256x256x64x64"] = batched(pcg, si, torch)
     out["serving_512_requests"] = serving(pcg, si, torch)
 
@@ -221,6 +235,37 @@ def extras(pcg, si, torch, main):
     t_cp = cuda_time(torch, lambda: c.copy_(a), 10)
     out["hbm_copy_probe_GBps"] = 2 * a.numel() * 8 / (t_cp * 1e-3) / 1e9
     del a, c
+    return out
+
+
+def stretched(pcg, si, torch, uniform):
+    """The main workload's operator on a stretched horizontal grid (widths
+    proportional to 1 + a sin(2 pi (i + 1/2) / n), a = 0.5 in x and 0.25 in
+    y, so neighbouring columns differ and the widest cell is 3x the
+    narrowest): |T| and alpha_{T,T'} rebuilt per column from the widths and
+    every column block factorised in the kernel.  FP64 fused solve, and the
+    operator and preconditioner alone."""
+    nx, ny, nz = 512, 512, 128
+    d = pcg.pcg_desc_from_ratio(nx, ny, nz, 1.05, 1e5, pcg.PCG_BC_PERIODIC)
+    P = pcg.Problem(d, si.widths_sine(nx, 0.5), si.widths_sine(ny, 0.25))
+    n = P.n
+    b = torch.from_numpy(si.rhs_uniform(nx, ny, nz, 1)).cuda()
+    x = torch.empty_like(b)
+    o = pcg.pcg_default_opts(x0_zero=1, graph_chunk=-1, true_residual=1)
+    ws = pcg.workspace(P, o)
+    ms, its, st, r = timed_solves(pcg, torch, P, b, x, ws, o, 10)
+    y = torch.empty_like(b)
+    t_mf = cuda_time(torch, lambda: pcg.pcg_apply(P, pcg.PCG_F64, b, y), 30)
+    t_pc = cuda_time(torch, lambda: pcg.pcg_precond(P, pcg.PCG_F64, b, y), 30)
+    out = dict(ms_per_solve=ms, iterations=its, status=pcg.STATUS_NAMES[st],
+               rel_res_true=r["rel_res_true"], unknowns_iter_per_s=n * its / (ms * 1e-3),
+               algorithmic_GBps=BYTES["iteration"] * n * its / (ms * 1e-3) / 1e9,
+               time_per_iteration_over_uniform=(ms / its) / (uniform["ms_per_solve"] /
+                                                             uniform["iterations"]),
+               apply_us=t_mf * 1e3, apply_GBps=BYTES["apply"] * n / (t_mf * 1e-3) / 1e9,
+               precond_us=t_pc * 1e3, precond_GBps=BYTES["precond"] * n / (t_pc * 1e-3) / 1e9,
+               tuning=pcg.pcg_get_tuning(P, pcg.PCG_F64).as_dict())
+    log("stretched 512x512x128: %.3f ms/solve, %.1f it" % (ms, its))
     return out
 
 
@@ -432,13 +477,19 @@ def traffic_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, kernel, comman
     cf, _ = means(cfetch_dir, "FETCH_SIZE", "copyBuffer")
     cw, _ = means(cwrite_dir, "WRITE_SIZE", "copyBuffer")
     ff, fw = gib_kib / cf, gib_kib / cw
-    sym = re.escape(KERNEL_SYMBOL[kernel])
+    sym = KERNEL_PATTERN[kernel]
+    names = set()
+    for _, rows in _csv_rows(fetch_dir, "counter_collection.csv"):
+        names |= {re.search(sym, r["Kernel_Name"]).group(0) for r in rows
+                  if re.search(sym, r["Kernel_Name"])}
+    if len(names) != 1:
+        raise SystemExit("expected one instance of %s in the counters, found %s" % (kernel, names))
     f, nf = means(fetch_dir, "FETCH_SIZE", sym)
     w, nw = means(write_dir, "WRITE_SIZE", sym)
     out = [
-        "# HBM traffic of %s on 512x512x128 (FP64, default tuning), per dispatch" % KERNEL_SYMBOL[kernel],
+        "# HBM traffic of %s on 512x512x128 (FP64, tuning in use), per dispatch" % kernel,
         "# commands: %s" % command,
-        "kernel = %s" % KERNEL_SYMBOL[kernel],
+        "kernel = %s" % names.pop(),
         "kernel_source_sha256_16 = %s" % kernel_source_hash(),
         "copy_probe_fetch_kib_per_gib = %.1f" % cf,
         "copy_probe_write_kib_per_gib = %.1f" % cw,
@@ -484,7 +535,8 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
-              "(each GPU would solve its own column blocks; see DESIGN.md)", file=sys.stderr)
+              "(sharded, each GPU would own a block of whole columns and exchange one "
+              "ring of neighbour columns per iteration)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -504,11 +556,12 @@ def main():
         achieved = per_launch / (avg * 1e-3) / 1e9
         kern[k] = dict(avg_ms=avg, launches=m["cnt"][k], achieved_GBps=achieved,
                        algorithmic_bytes_per_launch=per_launch,
-                       total_ms=m["ms"][k], symbol=KERNEL_SYMBOL[k])
+                       total_ms=m["ms"][k],
+                       symbol=kernel_symbol(k, m["tuning"]["lanes_per_column"], m["nz"]))
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    traffic = measured_traffic(dom, "512x512x128")
     for k in kern:
-        kern[k]["traffic"] = measured_traffic(k, "512x512x128")
+        kern[k]["traffic"] = measured_traffic(k, "512x512x128", kern[k]["symbol"])
+    traffic = kern[dom]["traffic"]
     line = {
         "metric": METRIC,
         "value": value,
@@ -526,7 +579,7 @@ def main():
                                "U[-1,1) seed 1, FP64 fused PCG to rel. residual 1e-8",
                    "nx": 512, "ny": 512, "nz": 128, "unknowns": n,
                    "iterations_per_solve": iters / args.steps},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom],
+        "roofline": {"bound": "hbm", "kernel": kern[dom]["symbol"],
                      "achieved": kern[dom]["achieved_GBps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": kern[dom]["achieved_GBps"] / PEAK_HBM_GBPS,
                      "traffic": traffic,

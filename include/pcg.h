@@ -132,6 +132,20 @@ pcg_status pcg_desc_from_ratio(int32_t nx, int32_t ny, int32_t nz, double gradin
  * at most nine column classes (number of Dirichlet side faces).  Allocates
  * a few KiB of device memory owned by the handle. */
 pcg_status pcg_problem_create(const pcg_problem_desc *desc, pcg_problem **out);
+
+/* The same operator on a stretched tensor-product horizontal grid: cell
+ * (i, j) is x_widths[i] by y_widths[j] (host arrays of n_x and n_y positive
+ * finite values, copied; desc->dx and desc->dy are not used).  The
+ * horizontal geometry enters the method only through |T| and the face
+ * weights alpha_{T,T'} (Sec. 3.1, eqs. DiagonalMatrix / TridiagonalMatrix;
+ * Sec. 4.2), which the kernels rebuild per column from these widths: the
+ * distance between neighbouring centres is the mean of their widths (half a
+ * width at a Dirichlet wall, the first and last cells across a periodic
+ * seam).  Every column block now differs, so the line solve factorises it in
+ * the kernel instead of using per-class factors.  Errors as
+ * pcg_problem_create, and PCG_E_INVALID for a NULL or non-positive width. */
+pcg_status pcg_problem_create_stretched(const pcg_problem_desc *desc, const double *x_widths,
+                                        const double *y_widths, pcg_problem **out);
 void pcg_problem_destroy(pcg_problem *p);
 
 /* Bytes of device workspace pcg_solve needs for these options
@@ -197,8 +211,8 @@ typedef struct {
 pcg_status pcg_get_tuning(const pcg_problem *p, int32_t dtype, pcg_tuning *out);
 pcg_status pcg_set_tuning(pcg_problem *p, int32_t dtype, const pcg_tuning *t);
 
-/* Tuning cache: launch parameters keyed by (GPU architecture, n_x, n_y,
- * n_z, dtype, nrhs).  Loaded on first use from tuning_cache.txt next to
+/* Tuning cache: launch parameters keyed by (GPU architecture, uniform or
+ * stretched horizontal grid, n_x, n_y, n_z, dtype, nrhs).  Loaded on first use from tuning_cache.txt next to
  * libpcg.so, or from the file named by the PCG_TUNING_CACHE environment
  * variable (empty: none).  A solve of nrhs right-hand sides uses the entry
  * for its shape unless the problem's tuning was set explicitly

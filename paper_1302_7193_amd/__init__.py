@@ -94,6 +94,9 @@ _sig = {
                                  ctypes.c_double, ctypes.c_int32,
                                  ctypes.POINTER(pcg_problem_desc)]),
     "pcg_problem_create": (_S, [ctypes.POINTER(pcg_problem_desc), ctypes.POINTER(_P)]),
+    "pcg_problem_create_stretched": (_S, [ctypes.POINTER(pcg_problem_desc),
+                                          ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_P)]),
     "pcg_problem_destroy": (None, [_P]),
     "pcg_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(pcg_solve_opts), ctypes.c_int32]),
     "pcg_apply": (_S, [_P, ctypes.c_int32, _P, _P, _P]),
@@ -197,13 +200,29 @@ def pcg_desc_from_ratio(nx, ny, nz, grading, gamma2, bc=PCG_BC_DIRICHLET) -> pcg
 
 
 class Problem:
-    """Owning handle of a pcg_problem (destroyed with the object)."""
+    """Owning handle of a pcg_problem (destroyed with the object).  With
+    ``x_widths`` / ``y_widths`` (n_x and n_y cell widths) the horizontal grid
+    is stretched (pcg_problem_create_stretched)."""
 
-    def __init__(self, desc: pcg_problem_desc):
+    def __init__(self, desc: pcg_problem_desc, x_widths=None, y_widths=None):
         self.desc = desc
         self.n = desc.nx * desc.ny * desc.nz
         h = _P()
-        _check(_lib.pcg_problem_create(ctypes.byref(desc), ctypes.byref(h)), "pcg_problem_create")
+        if x_widths is None and y_widths is None:
+            _check(_lib.pcg_problem_create(ctypes.byref(desc), ctypes.byref(h)),
+                   "pcg_problem_create")
+        else:
+            import numpy as np
+            xw = np.ascontiguousarray(np.full(desc.nx, desc.dx) if x_widths is None else x_widths,
+                                      dtype=np.float64)
+            yw = np.ascontiguousarray(np.full(desc.ny, desc.dy) if y_widths is None else y_widths,
+                                      dtype=np.float64)
+            if xw.shape != (desc.nx,) or yw.shape != (desc.ny,):
+                raise ValueError("x_widths / y_widths must hold n_x / n_y values")
+            dp = ctypes.POINTER(ctypes.c_double)
+            _check(_lib.pcg_problem_create_stretched(ctypes.byref(desc), xw.ctypes.data_as(dp),
+                                                     yw.ctypes.data_as(dp), ctypes.byref(h)),
+                   "pcg_problem_create_stretched")
         self.handle = h
 
     def __del__(self):
@@ -215,6 +234,10 @@ class Problem:
 
 def pcg_problem_create(desc: pcg_problem_desc) -> Problem:
     return Problem(desc)
+
+
+def pcg_problem_create_stretched(desc: pcg_problem_desc, x_widths, y_widths) -> Problem:
+    return Problem(desc, x_widths, y_widths)
 
 
 def pcg_problem_destroy(p: Problem) -> None:

@@ -13,6 +13,8 @@
 namespace pcg {
 
 std::string validate(const pcg_problem_desc& d);
+std::string stretched_geometry(const pcg_problem_desc& d, const double* xw, const double* yw,
+                               std::vector<double>& hgeo);
 void build_tables(const pcg_problem_desc& d, Geom& g, std::vector<double>& vert,
                   std::vector<double>& lu);
 size_t workspace_bytes(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs);
@@ -162,14 +164,17 @@ pcg_status pcg_desc_from_ratio(int32_t nx, int32_t ny, int32_t nz, double gradin
     return PCG_OK;
 }
 
-pcg_status pcg_problem_create(const pcg_problem_desc* desc, pcg_problem** out)
+static pcg_status create_problem(const pcg_problem_desc* desc, const double* xw, const double* yw,
+                                 pcg_problem** out)
 {
     if (!desc || !out) {
         set_error("desc/out is NULL");
         return PCG_E_INVALID;
     }
     *out = nullptr;
-    const std::string err = validate(*desc);
+    std::string err = validate(*desc);
+    std::vector<double> hgeo;
+    if (err.empty() && xw) err = stretched_geometry(*desc, xw, yw, hgeo);
     if (!err.empty()) {
         set_error(err);
         return PCG_E_INVALID;
@@ -195,26 +200,30 @@ pcg_status pcg_problem_create(const pcg_problem_desc* desc, pcg_problem** out)
         if (P->arch.empty()) P->arch = "unknown";
     }
     build_tables(*desc, P->geom, P->vert64, P->lu64);
+    P->hgeo = std::move(hgeo);
     for (int d = 0; d < 2; ++d) {
         P->tune[d].shape = default_shape(desc->nz, d);
         P->tune[d].block_cap = kDefaultCap;
         P->tune[d].red_mode = 1;
     }
-    const size_t nv = P->vert64.size(), nl = P->lu64.size();
-    const size_t b64v = al256(8 * nv), b64l = al256(8 * nl), b32v = al256(4 * nv), b32l = al256(4 * nl);
-    hipError_t e = hipMalloc(&P->dev_tables, b64v + b64l + b32v + b32l);
+    const size_t nv = P->vert64.size(), nl = P->lu64.size(), ng = P->hgeo.size();
+    const size_t b64v = al256(8 * nv), b64l = al256(8 * nl), b32v = al256(4 * nv),
+                 b32l = al256(4 * nl), bg = al256(8 * ng);
+    const size_t total = b64v + b64l + b32v + b32l + bg;
+    hipError_t e = hipMalloc(&P->dev_tables, total);
     if (e != hipSuccess) {
         set_error(hip_msg(e, "hipMalloc(tables)"));
         delete P;
         return PCG_E_NOMEM;
     }
-    std::vector<char> host(b64v + b64l + b32v + b32l, 0);
+    std::vector<char> host(total, 0);
     std::memcpy(host.data(), P->vert64.data(), 8 * nv);
     std::memcpy(host.data() + b64v, P->lu64.data(), 8 * nl);
     float* v32 = reinterpret_cast<float*>(host.data() + b64v + b64l);
     float* l32 = reinterpret_cast<float*>(host.data() + b64v + b64l + b32v);
     for (size_t i = 0; i < nv; ++i) v32[i] = (float)P->vert64[i];
     for (size_t i = 0; i < nl; ++i) l32[i] = (float)P->lu64[i];
+    if (ng) std::memcpy(host.data() + b64v + b64l + b32v + b32l, P->hgeo.data(), 8 * ng);
     e = hipMemcpy(P->dev_tables, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         set_error(hip_msg(e, "hipMemcpy(tables)"));
@@ -227,8 +236,25 @@ pcg_status pcg_problem_create(const pcg_problem_desc* desc, pcg_problem** out)
     P->d_lu64 = reinterpret_cast<const double*>(base + b64v);
     P->d_vert32 = reinterpret_cast<const float*>(base + b64v + b64l);
     P->d_lu32 = reinterpret_cast<const float*>(base + b64v + b64l + b32v);
+    if (ng) P->d_hgeo = reinterpret_cast<const double*>(base + b64v + b64l + b32v + b32l);
     *out = P;
     return PCG_OK;
+}
+
+pcg_status pcg_problem_create(const pcg_problem_desc* desc, pcg_problem** out)
+{
+    return create_problem(desc, nullptr, nullptr, out);
+}
+
+pcg_status pcg_problem_create_stretched(const pcg_problem_desc* desc, const double* x_widths,
+                                        const double* y_widths, pcg_problem** out)
+{
+    if (!x_widths || !y_widths) {
+        if (out) *out = nullptr;
+        set_error("pcg_problem_create_stretched: width arrays must not be NULL");
+        return PCG_E_INVALID;
+    }
+    return create_problem(desc, x_widths, y_widths, out);
 }
 
 void pcg_problem_destroy(pcg_problem* P)
@@ -272,8 +298,7 @@ pcg_status pcg_apply(pcg_problem* P, int32_t dtype, const void* x, void* y, void
         a.L = P->tune[dtype].shape.L;
         a.red_mode = P->tune[dtype].red_mode;
         a.blocks_per_rhs = blocks_per_rhs(P, dtype);
-        a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
-        a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
+        set_tables(a, P, dtype);
         a.in0 = x;
         a.io0 = y;
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -301,8 +326,7 @@ pcg_status pcg_precond(pcg_problem* P, int32_t dtype, const void* r, void* z, vo
         a.L = P->tune[dtype].shape.L;
         a.red_mode = P->tune[dtype].red_mode;
         a.blocks_per_rhs = blocks_per_rhs(P, dtype);
-        a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
-        a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
+        set_tables(a, P, dtype);
         a.in0 = r;
         a.io0 = z;
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -439,7 +463,8 @@ pcg_status pcg_csr_build(pcg_problem* P, int32_t dtype, void* buf, size_t bytes,
         return PCG_E_NOMEM;
     }
     return on_device(P->device, [&]() -> pcg_status {
-        hipError_t e = csr_build(P->geom, P->d_vert64, dtype, buf, static_cast<hipStream_t>(stream));
+        hipError_t e = csr_build(P->geom, P->d_vert64, P->d_hgeo, dtype, buf,
+                                 static_cast<hipStream_t>(stream));
         if (e != hipSuccess) {
             set_error(hip_msg(e, "pcg_csr_build launch"));
             return PCG_E_DEVICE;

@@ -27,7 +27,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_csr_build(Geom g, const double* __restrict__ vert,
-                                                      T* val, int32_t* col, int32_t* rowp)
+                                                      const double* __restrict__ hgeo, T* val,
+                                                      int32_t* col, int32_t* rowp)
 {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (r > g.n) return;
@@ -41,7 +42,20 @@ __global__ __launch_bounds__(kBlock) void k_csr_build(Geom g, const double* __re
     if (i < g.nx - 1) ip = c + g.ny; else if (g.per_x) ip = c - (int64_t)(g.nx - 1) * g.ny; else { ip = -1; ++cx; }
     if (j > 0) jm = c - 1; else if (g.per_y) jm = c + (g.ny - 1); else { jm = -1; ++cy; }
     if (j < g.ny - 1) jp = c + 1; else if (g.per_y) jp = c - (g.ny - 1); else { jp = -1; ++cy; }
-    const double alpha_t = (2 + cx) * g.ax + (2 + cy) * g.ay;
+    // |T| and the face weights alpha_{T,T'}: uniform, or from the per-index
+    // widths and reciprocal centre distances of a stretched grid
+    double area = g.area, wxm = g.ax, wxp = g.ax, wym = g.ay, wyp = g.ay;
+    double alpha_t = (2 + cx) * g.ax + (2 + cy) * g.ay;
+    if (hgeo) {
+        const double* hx = hgeo;
+        const double* hy = hgeo + 3 * (int64_t)g.nx;
+        area = hx[i] * hy[j];
+        wxm = hy[j] * hx[g.nx + i];
+        wxp = hy[j] * hx[2 * g.nx + i];
+        wym = hx[i] * hy[g.ny + j];
+        wyp = hx[i] * hy[2 * g.ny + j];
+        alpha_t = (wxm + wxp) + (wym + wyp);
+    }
     const double s = vert[k], b = vert[g.nzp + k], cc = vert[2 * g.nzp + k], d = vert[3 * g.nzp + k];
     int64_t e = row_offset(g, i, j, k);
     rowp[r] = (int32_t)e;
@@ -50,13 +64,13 @@ __global__ __launch_bounds__(kBlock) void k_csr_build(Geom g, const double* __re
         col[e] = (int32_t)column;
         ++e;
     };
-    if (im >= 0) put(im * g.nz + k, d * g.ax);
-    if (jm >= 0) put(jm * g.nz + k, d * g.ay);
-    if (k > 0) put(r - 1, g.area * cc);
-    put(r, g.area * s - alpha_t * d);
-    if (k < g.nz - 1) put(r + 1, g.area * b);
-    if (jp >= 0) put(jp * g.nz + k, d * g.ay);
-    if (ip >= 0) put(ip * g.nz + k, d * g.ax);
+    if (im >= 0) put(im * g.nz + k, d * wxm);
+    if (jm >= 0) put(jm * g.nz + k, d * wym);
+    if (k > 0) put(r - 1, area * cc);
+    put(r, area * s - alpha_t * d);
+    if (k < g.nz - 1) put(r + 1, area * b);
+    if (jp >= 0) put(jp * g.nz + k, d * wyp);
+    if (ip >= 0) put(ip * g.nz + k, d * wxp);
 }
 
 template <typename T>
@@ -94,17 +108,18 @@ size_t csr_bytes(const Geom& g, int dtype)
     return align256(vs * nnz) + align256(4 * nnz) + align256(4 * ((size_t)g.n + 1));
 }
 
-hipError_t csr_build(const Geom& g, const double* vert64, int dtype, void* buf, hipStream_t s)
+hipError_t csr_build(const Geom& g, const double* vert64, const double* hgeo, int dtype, void* buf,
+                     hipStream_t s)
 {
     const dim3 grid((unsigned)((g.n + 1 + kBlock - 1) / kBlock)), block(kBlock);
     if (dtype == PCG_F64) {
         double* v; int32_t *c, *r;
         sections<double>(g, buf, v, c, r);
-        hipLaunchKernelGGL((k_csr_build<double>), grid, block, 0, s, g, vert64, v, c, r);
+        hipLaunchKernelGGL((k_csr_build<double>), grid, block, 0, s, g, vert64, hgeo, v, c, r);
     } else {
         float* v; int32_t *c, *r;
         sections<float>(g, buf, v, c, r);
-        hipLaunchKernelGGL((k_csr_build<float>), grid, block, 0, s, g, vert64, v, c, r);
+        hipLaunchKernelGGL((k_csr_build<float>), grid, block, 0, s, g, vert64, hgeo, v, c, r);
     }
     return hipGetLastError();
 }

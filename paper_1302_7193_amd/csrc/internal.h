@@ -63,7 +63,13 @@ struct Geom {
 };
 
 // Column tables in device memory, for one precision T:
-//   vert[4][nzp]     s_k = a_k - b_k - c_k, b_k, c_k, d_k (eq. TridiagonalMatrix)
+//   vert[9][nzp]     s_k = a_k - b_k - c_k, b_k, c_k, d_k (eq. TridiagonalMatrix),
+//                    then, for factorising stretched-grid column blocks in the
+//                    kernel with every quantity scaled by s_k (well inside the
+//                    FP32 range however fine the vertical grid):
+//                    e_k = -d_k / s_k, pi_k = c_k b_{k-1} / (s_k s_{k-1}),
+//                    cs_k = c_k / s_{k-1}, bs_k = b_k / s_k, is_k = 1 / s_k
+//                    (pi_0 = cs_0 = 0, bs_{n_z-1} = 0)
 //   lu[9][3][nzp]    per column class: l_k, 1/D_k, phi_k of the LU factors of
 //                    the column block A_T (zero beyond n_z)
 template <typename T>
@@ -124,6 +130,8 @@ struct ColArgs {
     double* part;       // [batch][blocks_per_rhs][kRedSlots]
     int red_mode;       // 0: last workgroup finishes reductions; 1: finalize launch
     int x0_zero;        // refinement kernels: x is zero (not read)
+    const double* hgeo; // stretched grids: per-index widths and face weights
+                        // [w_x m_x p_x](n_x) [w_y m_y p_y](n_y); null when uniform
 };
 
 // Host launchers (kernels.hip): T = double or float.  column_launches
@@ -174,7 +182,8 @@ hipError_t launch_blas(Blas op, const BlasArgs& a, hipStream_t s);
 
 // CSR comparator (csr.hip).
 size_t csr_bytes(const Geom& g, int dtype);
-hipError_t csr_build(const Geom& g, const double* vert64, int dtype, void* buf, hipStream_t s);
+hipError_t csr_build(const Geom& g, const double* vert64, const double* hgeo, int dtype, void* buf,
+                     hipStream_t s);
 hipError_t csr_apply(const Geom& g, int dtype, const void* buf, const void* x, void* y,
                      hipStream_t s);
 

@@ -19,6 +19,16 @@
 // column system into L pieces plus an L-sized interface problem (Sec. 6.1).
 // L = 1 is the sequential Thomas algorithm of Sec. 4.2.
 //
+// Stretched horizontal grids (G = true).  |T| and the face weights
+// alpha_{T,T'} come from per-index widths, so every column block differs
+// and is factorised in the kernel (as the paper's Thomas sweep recomputes
+// its coefficients per column): the scaled pivots delta_k obey the continued
+// fraction delta_k = g_k - pi_k / delta_{k-1}, a Moebius map of delta_{k-1}.
+// Each lane composes the maps of its levels as a 2x2 matrix, the segment
+// scans those matrices across lanes (rescaled by powers of two), and each
+// lane then runs the recurrence over its own levels from the pivot entering
+// them.
+//
 // Reductions.  Every workgroup writes its partial sums to a fixed slot; the
 // last workgroup to finish (atomic ticket) adds the slots in a fixed order and
 // performs the scalar step of Alg. InterleavedPCG on the device, so results
@@ -34,13 +44,16 @@ struct Col {
     int64_t im, ip, jm, jp;  // neighbour columns, -1 across a Dirichlet face
     int cls;                 // column class: 3 * (#Dirichlet x faces) + #Dirichlet y faces
     double alpha_t;          // alpha_T = sum of alpha_{T,T'}, Dirichlet faces twice
+    double area;             // stretched grids: |T| and the face weights alpha_{T,T'}
+    double wxm, wxp, wym, wyp;
     bool ok;
 };
 
 // Per-column geometry, recomputed from (i, j) (Sec. 4.2: |T| and
 // alpha_{T,T'} are evaluated once per column).  Dirichlet faces use the
 // half-cell distance, i.e. they add 2*alpha_{T,T'} to alpha_T.
-__device__ __forceinline__ Col make_col(const Geom& g, int64_t c)
+template <bool G = false>
+__device__ __forceinline__ Col make_col(const Geom& g, int64_t c, const double* hgeo = nullptr)
 {
     Col o;
     o.ok = c < g.nh;
@@ -61,7 +74,21 @@ __device__ __forceinline__ Col make_col(const Geom& g, int64_t c)
     else if (g.per_y) o.jp = cc - (g.ny - 1);
     else { o.jp = -1; ++cy; }
     o.cls = 3 * cx + cy;
-    o.alpha_t = (2 + cx) * g.ax + (2 + cy) * g.ay;
+    if constexpr (G) {
+        // widths w and reciprocal centre distances m (lower), p (upper) per
+        // index; a Dirichlet wall's m or p is 2/w and its neighbour is absent
+        const double* hx = hgeo;
+        const double* hy = hgeo + 3 * (int64_t)g.nx;
+        const double wi = hx[i], wj = hy[j];
+        o.area = wi * wj;
+        o.wxm = wj * hx[g.nx + i];
+        o.wxp = wj * hx[2 * g.nx + i];
+        o.wym = wi * hy[g.ny + j];
+        o.wyp = wi * hy[2 * g.ny + j];
+        o.alpha_t = (o.wxm + o.wxp) + (o.wym + o.wyp);
+    } else {
+        o.alpha_t = (2 + cx) * g.ax + (2 + cy) * g.ay;
+    }
     return o;
 }
 
@@ -155,7 +182,7 @@ __device__ __forceinline__ VertCoef<T, M> load_vert(const Geom& g, const T* __re
     return v;
 }
 
-template <typename T, int M, bool V>
+template <typename T, int M, bool V, bool G = false>
 __device__ __forceinline__ void stencil(const Geom& g, const Col& c, int l, int L, int k0,
                                         const T* __restrict__ x, const T (&xc)[M],
                                         const VertCoef<T, M>& vc, T (&y)[M])
@@ -171,15 +198,30 @@ __device__ __forceinline__ void stencil(const Geom& g, const Col& c, int l, int 
     ld<T, M, V>(x, c.jm, c.ok && c.jm >= 0, k0, g.nz, xjm);
     ld<T, M, V>(x, c.jp, c.ok && c.jp >= 0, k0, g.nz, xjp);
 
-    const T area = T(g.area), ax = T(g.ax), ay = T(g.ay), at = T(c.alpha_t);
+    const T at = T(c.alpha_t);
+    if constexpr (G) {
+        const T area = T(c.area), wxm = T(c.wxm), wxp = T(c.wxp), wym = T(c.wym),
+                wyp = T(c.wyp);
 #pragma unroll
-    for (int t = 0; t < M; ++t) {
-        const T lo = t == 0 ? below : xc[t - 1];
-        const T hi = t == M - 1 ? above : xc[t + 1];
-        const T vertical = area * (vc.s[t] * xc[t] + vc.b[t] * hi + vc.c[t] * lo);
-        const T horizontal =
-            vc.d[t] * (ax * (xim[t] + xip[t]) + ay * (xjm[t] + xjp[t]) - at * xc[t]);
-        y[t] = vertical + horizontal;
+        for (int t = 0; t < M; ++t) {
+            const T lo = t == 0 ? below : xc[t - 1];
+            const T hi = t == M - 1 ? above : xc[t + 1];
+            const T vertical = area * (vc.s[t] * xc[t] + vc.b[t] * hi + vc.c[t] * lo);
+            const T horizontal = vc.d[t] * ((wxm * xim[t] + wxp * xip[t]) +
+                                            (wym * xjm[t] + wyp * xjp[t]) - at * xc[t]);
+            y[t] = vertical + horizontal;
+        }
+    } else {
+        const T area = T(g.area), ax = T(g.ax), ay = T(g.ay);
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            const T lo = t == 0 ? below : xc[t - 1];
+            const T hi = t == M - 1 ? above : xc[t + 1];
+            const T vertical = area * (vc.s[t] * xc[t] + vc.b[t] * hi + vc.c[t] * lo);
+            const T horizontal =
+                vc.d[t] * (ax * (xim[t] + xip[t]) + ay * (xjm[t] + xjp[t]) - at * xc[t]);
+            y[t] = vertical + horizontal;
+        }
     }
 }
 
@@ -203,15 +245,132 @@ __device__ __forceinline__ LuCoef<T, M> load_lu(const Geom& g, const T* __restri
     return f;
 }
 
-// f0: the class-0 factors (interior / periodic columns), loaded once per
-// kernel; columns of another class load theirs.
-template <typename T, int M, bool V>
+// Coefficients of the line solve loaded once per kernel: on uniform grids
+// the class-0 factors (interior / periodic columns; columns of another class
+// load theirs), on stretched grids the scaled level vectors from which
+// every column's factors are computed.
+template <typename T, int M, bool G>
+struct SolveCoef {
+    LuCoef<T, M> f0;
+};
+template <typename T, int M>
+struct SolveCoef<T, M, true> {
+    T e[M], pi[M], cs[M], bs[M], is[M];
+};
+
+template <typename T, int M, bool V, bool G>
+__device__ __forceinline__ SolveCoef<T, M, G> load_solve(const Geom& g, const ColArgs& a, int k0)
+{
+    SolveCoef<T, M, G> sc;
+    if constexpr (G) {
+        const T* vert = static_cast<const T*>(a.vert);
+        ld_tab<T, M, V>(vert, 4, g.nzp, k0, g.nz, sc.e);
+        ld_tab<T, M, V>(vert, 5, g.nzp, k0, g.nz, sc.pi);
+        ld_tab<T, M, V>(vert, 6, g.nzp, k0, g.nz, sc.cs);
+        ld_tab<T, M, V>(vert, 7, g.nzp, k0, g.nz, sc.bs);
+        ld_tab<T, M, V>(vert, 8, g.nzp, k0, g.nz, sc.is);
+    } else {
+        sc.f0 = load_lu<T, M, V>(g, static_cast<const T*>(a.lu), 0, k0);
+    }
+    return sc;
+}
+
+// Rescale a 2x2 matrix by a power of two so its largest entry lies in
+// [1/2, 1) (exact; the matrix acts projectively).
+template <typename T>
+__device__ __forceinline__ void rescale(T& e00, T& e01, T& e10, T& e11)
+{
+    const T m = fmax(fmax(fabs(e00), fabs(e01)), fmax(fabs(e10), fabs(e11)));
+    int ex;
+    (void)frexp(m, &ex);
+    e00 = ldexp(e00, -ex);
+    e01 = ldexp(e01, -ex);
+    e10 = ldexp(e10, -ex);
+    e11 = ldexp(e11, -ex);
+}
+
+// LU factors of one stretched-grid column on this lane's levels.  Scaled by
+// 1/|T| the block is tridiag(c, s - (alpha_T/|T|) d, b); its pivots are
+// D_k = s_k delta_k with delta_k = g_k - pi_k / delta_{k-1} (delta_{-1}
+// infinite), g_k = 1 + (alpha_T/|T|) e_k.  In homogeneous coordinates (n, m)
+// with delta = n/m one level is the matrix [[g_k, -pi_k], [1, 0]].  Then
+// l_k = c_k / D_{k-1} = cs_k / delta_{k-1}, 1/(|T| D_k) = is_k / (|T| delta_k)
+// and phi_k = b_k / D_k = bs_k / delta_k; levels beyond n_z get zero factors.
+// The factorisation runs in FP64 for either precision: composing many
+// levels of a strongly coupled column cancels digits (the pivot map is close
+// to one with a double fixed point), and FP64 keeps the rounded factors as
+// accurate as the host-computed ones of the uniform path.
+template <typename T, int M>
+__device__ __forceinline__ void gen_factors(const Col& c, int l, int L, int k0, int nz,
+                                            const SolveCoef<T, M, true>& sc, LuCoef<T, M>& f)
+{
+    const double at = c.alpha_t / c.area;
+    const double inv_area = 1.0 / c.area;
+    double gk[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) gk[t] = 1.0 + at * double(sc.e[t]);
+    // this lane's levels, composed (later levels on the left)
+    double e00 = 1.0, e01 = 0.0, e10 = 0.0, e11 = 1.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        if (k0 + t < nz) {
+            const double pi = double(sc.pi[t]);
+            const double n00 = gk[t] * e00 - pi * e10;
+            const double n01 = gk[t] * e01 - pi * e11;
+            e10 = e00;
+            e11 = e01;
+            e00 = n00;
+            e01 = n01;
+            rescale(e00, e01, e10, e11);
+        }
+    }
+    // inclusive scan across the segment: lane l ends with the product over
+    // lanes l, l-1, ..., 0
+    for (int d = 1; d < L; d <<= 1) {
+        const double f00 = __shfl_up(e00, d, L), f01 = __shfl_up(e01, d, L);
+        const double f10 = __shfl_up(e10, d, L), f11 = __shfl_up(e11, d, L);
+        if (l >= d) {
+            const double n00 = e00 * f00 + e01 * f10, n01 = e00 * f01 + e01 * f11;
+            const double n10 = e10 * f00 + e11 * f10, n11 = e10 * f01 + e11 * f11;
+            e00 = n00;
+            e01 = n01;
+            e10 = n10;
+            e11 = n11;
+            rescale(e00, e01, e10, e11);
+        }
+    }
+    // pivot entering this lane: the lanes below applied to delta_{-1} = (1, 0)
+    const double b00 = __shfl_up(e00, 1, L), b10 = __shfl_up(e10, 1, L);
+    double inv_prev = l == 0 ? 0.0 : b10 / b00;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        const int k = k0 + t;
+        if (k < nz) {
+            const double inv = 1.0 / (gk[t] - double(sc.pi[t]) * inv_prev);
+            f.l[t] = T(double(sc.cs[t]) * inv_prev);
+            f.inv_d[t] = T((double(sc.is[t]) * inv) * inv_area);
+            f.phi[t] = T(double(sc.bs[t]) * inv);
+            inv_prev = inv;
+        } else {
+            f.l[t] = T(0);
+            f.inv_d[t] = T(0);
+            f.phi[t] = T(0);
+        }
+    }
+}
+
+template <typename T, int M, bool V, bool G>
 __device__ __forceinline__ void line_solve(const Geom& g, const Col& c, int l, int L, int k0,
-                                           const T* __restrict__ lu, const LuCoef<T, M>& f0,
+                                           const T* __restrict__ lu, const SolveCoef<T, M, G>& sc,
                                            const T (&r)[M], T (&z)[M])
 {
-    LuCoef<T, M> f = f0;
-    if (c.cls != 0) f = load_lu<T, M, V>(g, lu, c.cls, k0);
+    LuCoef<T, M> f;
+    if constexpr (G) {
+        gen_factors<T, M>(c, l, L, k0, g.nz, sc, f);
+    } else {
+        f = sc.f0;
+        if (c.cls != 0) f = load_lu<T, M, V>(g, lu, c.cls, k0);
+    }
     const T (&lf)[M] = f.l;
     const T (&inv_d)[M] = f.inv_d;
     const T (&phi)[M] = f.phi;
@@ -296,7 +455,7 @@ __device__ __forceinline__ int64_t tile_col(int64_t tile, const Lane& p, int L)
 
 // ---------------------------------------------------------------- kernels --
 
-template <typename T, int M, bool V>
+template <typename T, int M, bool V, bool G>
 __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
 {
     const Geom& g = a.g;
@@ -312,15 +471,15 @@ __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col(g, tile_col(tile, p, L));
+        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
         T xc[M], yc[M];
         ld<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
-        stencil<T, M, V>(g, c, p.l, L, p.k0, x, xc, vc, yc);
+        stencil<T, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, yc);
         st<T, M, V>(y, c.idx, c.ok, p.k0, g.nz, yc);
     }
 }
 
-template <typename T, int M, bool V>
+template <typename T, int M, bool V, bool G>
 __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
 {
     const Geom& g = a.g;
@@ -332,20 +491,20 @@ __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
     T* z = static_cast<T*>(a.io0) + rhs * g.n;
     const T* lu = static_cast<const T*>(a.lu);
     const Lane p = lane_pos<M>(L);
-    const LuCoef<T, M> f0 = load_lu<T, M, V>(g, lu, 0, p.k0);
+    const SolveCoef<T, M, G> sc = load_solve<T, M, V, G>(g, a, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col(g, tile_col(tile, p, L));
+        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
         T rc[M], zc[M];
         ld<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
-        line_solve<T, M, V>(g, c, p.l, L, p.k0, lu, f0, rc, zc);
+        line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, rc, zc);
         st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
     }
 }
 
 // r = b - A x; ZERO: x = 0, r = b (nothing to copy when b is r), p = q = 0.
-template <typename T, int M, bool V, bool ZERO>
+template <typename T, int M, bool V, bool ZERO, bool G>
 __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
 {
     const Geom& g = a.g;
@@ -368,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
 #pragma unroll
     for (int i = 0; i < M; ++i) zero[i] = T(0);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col(g, tile_col(tile, p, L));
+        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
         if (ZERO) {
             st<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, zero);
             if (!in_place) {
@@ -380,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
             T bc[M], rc[M], xc[M], ax[M];
             ld<T, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
             ld<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
-            stencil<T, M, V>(g, c, p.l, L, p.k0, x, xc, vc, ax);
+            stencil<T, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, ax);
 #pragma unroll
             for (int i = 0; i < M; ++i) rc[i] = bc[i] - ax[i];
             st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
@@ -397,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
 // FIRST (no iteration done yet): alpha = 0 and q is unset, so q is not read;
 // with a zero start r is taken from b (no start-up kernel), and not stored
 // when b is r itself.
-template <typename T, int M, bool V, bool FIRST>
+template <typename T, int M, bool V, bool FIRST, bool G>
 __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s, int64_t rhs,
                                                 int64_t blk, double (&acc)[2])
 {
@@ -413,11 +572,11 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
     const T* lu = static_cast<const T*>(a.lu);
     const T alpha = T(s->alpha);
     const Lane p = lane_pos<M>(L);
-    const LuCoef<T, M> f0 = load_lu<T, M, V>(g, lu, 0, p.k0);
+    const SolveCoef<T, M, G> sc = load_solve<T, M, V, G>(g, a, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col(g, tile_col(tile, p, L));
+        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
         T rc[M], zc[M];
         ld<T, M, V>(src, c.idx, c.ok, p.k0, g.nz, rc);
         if (!FIRST) {
@@ -429,14 +588,14 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[0] += double(rc[i]) * double(rc[i]);
         if (!FIRST || store_r) st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
-        line_solve<T, M, V>(g, c, p.l, L, p.k0, lu, f0, rc, zc);
+        line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, rc, zc);
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[1] += double(rc[i]) * double(zc[i]);
         st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
     }
 }
 
-template <typename T, int M, bool V>
+template <typename T, int M, bool V, bool G>
 __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
 {
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
@@ -444,8 +603,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[2] = {0.0, 0.0};
-    if (s->iter == 0) fused_prec_body<T, M, V, true>(a, s, rhs, blk, acc);
-    else fused_prec_body<T, M, V, false>(a, s, rhs, blk, acc);
+    if (s->iter == 0) fused_prec_body<T, M, V, true, G>(a, s, rhs, blk, acc);
+    else fused_prec_body<T, M, V, false, G>(a, s, rhs, blk, acc);
     double tot[2];
     if (publish<2>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
                    &s->ticket, a.red_mode, tot)) {
@@ -457,7 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
 // q = A z + beta q; sigma = <p,q> (FP64); scalar step: alpha.
 // FIRST: alpha = 0 and p = q = 0, so p = z, q = A z, and u keeps x0 (written
 // as zero for a zero start); u, p and q are not read.
-template <typename T, int M, bool V, bool FIRST>
+template <typename T, int M, bool V, bool FIRST, bool G>
 __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* s, int64_t rhs,
                                                  int64_t blk, double (&acc)[1])
 {
@@ -476,10 +635,10 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col(g, tile_col(tile, p, L));
+        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
         T zc[M], az[M], pc[M], qc[M];
         ld<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
-        stencil<T, M, V>(g, c, p.l, L, p.k0, z, zc, vc, az);
+        stencil<T, M, V, G>(g, c, p.l, L, p.k0, z, zc, vc, az);
         if (FIRST) {
 #pragma unroll
             for (int i = 0; i < M; ++i) {
@@ -512,7 +671,7 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
     }
 }
 
-template <typename T, int M, bool V>
+template <typename T, int M, bool V, bool G>
 __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
 {
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
@@ -520,8 +679,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[1] = {0.0};
-    if (s->iter == 0) fused_apply_body<T, M, V, true>(a, s, rhs, blk, acc);
-    else fused_apply_body<T, M, V, false>(a, s, rhs, blk, acc);
+    if (s->iter == 0) fused_apply_body<T, M, V, true, G>(a, s, rhs, blk, acc);
+    else fused_apply_body<T, M, V, false, G>(a, s, rhs, blk, acc);
     double tot[1];
     if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
                    &s->ticket, a.red_mode, tot)) {
@@ -579,7 +738,7 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
 }
 
 // FP64 true residual: ||b - A x|| into state.aux (T = double only).
-template <int M, bool V>
+template <int M, bool V, bool G>
 __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
 {
     const Geom& g = a.g;
@@ -596,11 +755,11 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     double acc[1] = {0.0};
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col(g, tile_col(tile, p, L));
+        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
         double xc[M], ax[M], bc[M];
         ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
         ld<double, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
-        stencil<double, M, V>(g, c, p.l, L, p.k0, x, xc, vc, ax);
+        stencil<double, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, ax);
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             const double d = bc[i] - ax[i];
@@ -617,7 +776,7 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
 // Refinement residual: r64 = b - A x in FP64 (r64 = b when a.x0_zero),
 // ||r64|| into state.rnorm (state.r0norm on the first call), FP32 copy
 // r32 = r64 * scale.
-template <int M, bool V>
+template <int M, bool V, bool G>
 __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
 {
     const Geom& g = a.g;
@@ -637,7 +796,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     double acc[1] = {0.0};
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col(g, tile_col(tile, p, L));
+        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
         double xc[M], ax[M], bc[M];
         float rc[M];
         ld<double, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
@@ -646,7 +805,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
             for (int i = 0; i < M; ++i) ax[i] = 0.0;
         } else {
             ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
-            stencil<double, M, V>(g, c, p.l, L, p.k0, x, xc, vc, ax);
+            stencil<double, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, ax);
         }
 #pragma unroll
         for (int i = 0; i < M; ++i) {
@@ -753,22 +912,23 @@ const void* finalize_func(Kind kind)
     }
 }
 
-template <typename T, int M, bool V>
+template <typename T, int M, bool V, bool G>
 const void* main_func_m(Kind kind)
 {
     switch (kind) {
-    case Kind::Apply: return reinterpret_cast<const void*>(&k_apply<T, M, V>);
-    case Kind::Precond: return reinterpret_cast<const void*>(&k_precond<T, M, V>);
-    case Kind::InitFull: return reinterpret_cast<const void*>(&k_init<T, M, V, false>);
-    case Kind::InitZero: return reinterpret_cast<const void*>(&k_init<T, M, V, true>);
-    case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V>);
-    case Kind::FusedApply: return reinterpret_cast<const void*>(&k_fused_apply<T, M, V>);
+    case Kind::Apply: return reinterpret_cast<const void*>(&k_apply<T, M, V, G>);
+    case Kind::Precond: return reinterpret_cast<const void*>(&k_precond<T, M, V, G>);
+    case Kind::InitFull: return reinterpret_cast<const void*>(&k_init<T, M, V, false, G>);
+    case Kind::InitZero: return reinterpret_cast<const void*>(&k_init<T, M, V, true, false>);
+    case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G>);
+    case Kind::FusedApply: return reinterpret_cast<const void*>(&k_fused_apply<T, M, V, G>);
     case Kind::Fixup: return reinterpret_cast<const void*>(&k_fixup<T, M, V>);
     case Kind::TrueResidual:
-        if constexpr (sizeof(T) == 8) return reinterpret_cast<const void*>(&k_true_residual<M, V>);
+        if constexpr (sizeof(T) == 8)
+            return reinterpret_cast<const void*>(&k_true_residual<M, V, G>);
         return nullptr;
     case Kind::Residual64:
-        if constexpr (sizeof(T) == 8) return reinterpret_cast<const void*>(&k_residual64<M, V>);
+        if constexpr (sizeof(T) == 8) return reinterpret_cast<const void*>(&k_residual64<M, V, G>);
         return nullptr;
     case Kind::Update64:
         if constexpr (sizeof(T) == 8) return reinterpret_cast<const void*>(&k_update64<M, V>);
@@ -783,7 +943,8 @@ const void* main_func_v(Kind kind, const ColArgs& a)
     // vector path: whole chunks valid and 16-byte aligned rows and chunks
     const bool vec = (a.g.nz % M == 0) && ((M * sizeof(T)) % 16 == 0) &&
                      ((a.g.nz * sizeof(T)) % 16 == 0);
-    return vec ? main_func_m<T, M, true>(kind) : main_func_m<T, M, false>(kind);
+    if (a.hgeo) return vec ? main_func_m<T, M, true, true>(kind) : main_func_m<T, M, false, true>(kind);
+    return vec ? main_func_m<T, M, true, false>(kind) : main_func_m<T, M, false, false>(kind);
 }
 
 template <typename T>

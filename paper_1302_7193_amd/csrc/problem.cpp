@@ -82,7 +82,7 @@ void build_tables(const pcg_problem_desc& d, Geom& g, std::vector<double>& vert,
 
     const std::vector<double> dz = thicknesses(nz, d.height, d.grading);
     const int nzp = g.nzp;
-    vert.assign(4 * (size_t)nzp, 0.0);
+    vert.assign(9 * (size_t)nzp, 0.0);
     std::vector<double> b(nz), c(nz);
     for (int k = 0; k < nz; ++k) {
         const double a = dz[k];
@@ -94,6 +94,14 @@ void build_tables(const pcg_problem_desc& d, Geom& g, std::vector<double>& vert,
         vert[1 * nzp + k] = b[k];
         vert[2 * nzp + k] = c[k];
         vert[3 * nzp + k] = -d.k_h * dz[k];
+    }
+    for (int k = 0; k < nz; ++k) {
+        const double sk = vert[k];
+        vert[4 * nzp + k] = -vert[3 * nzp + k] / sk;
+        vert[5 * nzp + k] = k > 0 ? (c[k] / sk) * (b[k - 1] / vert[k - 1]) : 0.0;
+        vert[6 * nzp + k] = k > 0 ? c[k] / vert[k - 1] : 0.0;
+        vert[7 * nzp + k] = k < nz - 1 ? b[k] / sk : 0.0;
+        vert[8 * nzp + k] = 1.0 / sk;
     }
 
     // LU factors (no pivoting: every column block is strictly diagonally
@@ -119,6 +127,36 @@ void build_tables(const pcg_problem_desc& d, Geom& g, std::vector<double>& vert,
             dprev = dk;
         }
     }
+}
+
+// Stretched horizontal grids: per index i of a direction with widths w, the
+// width w_i and the reciprocal centre distances to the lower and upper
+// neighbour, m_i and p_i (half a width at a Dirichlet wall, so the face
+// weight alpha_{T,T'} = edge length * m_i counts that face twice; across a
+// periodic seam the distance joins the first and last cells).  Layout
+// [w_x m_x p_x](n_x) [w_y m_y p_y](n_y).
+std::string stretched_geometry(const pcg_problem_desc& d, const double* xw, const double* yw,
+                               std::vector<double>& hgeo)
+{
+    for (int i = 0; i < d.nx; ++i)
+        if (!finite_pos(xw[i])) return "x widths must be positive and finite";
+    for (int j = 0; j < d.ny; ++j)
+        if (!finite_pos(yw[j])) return "y widths must be positive and finite";
+    hgeo.assign(3 * (size_t)d.nx + 3 * (size_t)d.ny, 0.0);
+    auto fill = [](const double* w, int n, bool periodic, double* out) {
+        for (int i = 0; i < n; ++i) {
+            out[i] = w[i];
+            const double lo = i > 0 ? 0.5 * (w[i - 1] + w[i])
+                                    : (periodic ? 0.5 * (w[n - 1] + w[0]) : 0.5 * w[0]);
+            const double hi = i < n - 1 ? 0.5 * (w[i] + w[i + 1])
+                                        : (periodic ? 0.5 * (w[n - 1] + w[0]) : 0.5 * w[n - 1]);
+            out[n + i] = 1.0 / lo;
+            out[2 * n + i] = 1.0 / hi;
+        }
+    };
+    fill(xw, d.nx, d.bc_x == PCG_BC_PERIODIC, hgeo.data());
+    fill(yw, d.ny, d.bc_y == PCG_BC_PERIODIC, hgeo.data() + 3 * (size_t)d.nx);
+    return "";
 }
 
 Shape default_shape(int nz, int dtype)

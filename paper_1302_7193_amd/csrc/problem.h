@@ -49,7 +49,9 @@ struct pcg_problem {
     pcg::Geom geom{};
     int device = 0;
     std::vector<double> vert64, lu64;      // host copies of the tables
-    void* dev_tables = nullptr;            // vert64 | lu64 | vert32 | lu32
+    std::vector<double> hgeo;              // stretched grids: per-index geometry (else empty)
+    void* dev_tables = nullptr;            // vert64 | lu64 | vert32 | lu32 | hgeo
+    const double* d_hgeo = nullptr;        // null for uniform grids
     const double* d_vert64 = nullptr;
     const double* d_lu64 = nullptr;
     const float* d_vert32 = nullptr;
@@ -65,6 +67,14 @@ struct pcg_problem {
 };
 
 namespace pcg {
+
+// Table pointers of one precision in a kernel argument block.
+inline void set_tables(ColArgs& a, const pcg_problem* P, int dtype)
+{
+    a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
+    a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
+    a.hgeo = P->d_hgeo;
+}
 
 // For the duration of one call, the problem's tunings are the effective ones
 // for nrhs right-hand sides (explicit setting, else the tuning cache, else

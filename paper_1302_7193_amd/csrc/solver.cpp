@@ -369,8 +369,7 @@ ColArgs base_args(const pcg_problem* P, int dtype, char* ws, const Layout& w, in
     a.L = P->tune[dtype].shape.L;
     a.red_mode = P->tune[dtype].red_mode;
     a.blocks_per_rhs = bpr;
-    a.vert = dtype == PCG_F64 ? (const void*)P->d_vert64 : (const void*)P->d_vert32;
-    a.lu = dtype == PCG_F64 ? (const void*)P->d_lu64 : (const void*)P->d_lu32;
+    set_tables(a, P, dtype);
     a.part = reinterpret_cast<double*>(ws + w.part);
     return a;
 }

@@ -1,12 +1,15 @@
 // Persistent autotuning results: a process-wide table of launch parameters
-// keyed by (GPU architecture, grid n_x n_y n_z, precision, right-hand sides),
+// keyed by (GPU architecture, horizontal geometry kind, grid n_x n_y n_z,
+// precision, right-hand sides),
 // loaded from a text file next to libpcg.so (or the file named by the
 // PCG_TUNING_CACHE environment variable; an empty value disables it) and
 // extended by pcg_autotune.  A problem uses a table entry for a solve unless
 // its tuning was set explicitly (pcg_set_tuning / pcg_autotune).
 //
 // File format, one entry per line ('#' starts a comment):
-//   arch nx ny nz dtype nrhs lanes_per_column block_cap reduction
+//   arch geom nx ny nz dtype nrhs lanes_per_column block_cap reduction
+// with geom "uniform" or "stretched" (the stretched kernels also factorise
+// the column blocks, so their best launch shape differs).
 #include <dlfcn.h>
 
 #include <cstdio>
@@ -25,7 +28,7 @@ namespace pcg {
 
 namespace {
 
-using Key = std::tuple<std::string, int32_t, int32_t, int32_t, int32_t, int64_t>;
+using Key = std::tuple<std::string, std::string, int32_t, int32_t, int32_t, int32_t, int64_t>;
 
 struct Cache {
     std::mutex mu;
@@ -62,10 +65,11 @@ bool parse_into(const std::string& path, std::map<Key, Tuning>& table)
         const size_t hash = line.find('#');
         if (hash != std::string::npos) line.resize(hash);
         std::istringstream ls(line);
-        std::string arch;
+        std::string arch, geom;
         int32_t nx, ny, nz, dtype, L, mode;
         int64_t nrhs, cap;
-        if (!(ls >> arch >> nx >> ny >> nz >> dtype >> nrhs >> L >> cap >> mode)) continue;
+        if (!(ls >> arch >> geom >> nx >> ny >> nz >> dtype >> nrhs >> L >> cap >> mode)) continue;
+        if (geom != "uniform" && geom != "stretched") continue;
         Shape sh;
         sh.L = L;
         if (dtype < 0 || dtype > 1 || !shape_supported(nz, sh) || cap < 1 || cap > kMaxBlocks ||
@@ -77,7 +81,7 @@ bool parse_into(const std::string& path, std::map<Key, Tuning>& table)
         t.shape = sh;
         t.block_cap = cap;
         t.red_mode = mode;
-        table[Key(arch, nx, ny, nz, dtype, nrhs)] = t;
+        table[Key(arch, geom, nx, ny, nz, dtype, nrhs)] = t;
     }
     return true;
 }
@@ -92,7 +96,8 @@ void ensure_loaded(Cache& c)
 
 Key key_of(const pcg_problem* P, int dtype, int64_t nrhs)
 {
-    return Key(P->arch, P->geom.nx, P->geom.ny, P->geom.nz, dtype, nrhs);
+    return Key(P->arch, P->d_hgeo ? "stretched" : "uniform", P->geom.nx, P->geom.ny, P->geom.nz,
+               dtype, nrhs);
 }
 
 }  // namespace
@@ -155,13 +160,14 @@ pcg_status pcg_tuning_cache_save(const char* path)
         return PCG_E_INVALID;
     }
     out << "# libpcg launch parameters found by pcg_autotune\n"
-        << "# arch nx ny nz dtype nrhs lanes_per_column block_cap reduction\n";
+        << "# arch geom nx ny nz dtype nrhs lanes_per_column block_cap reduction\n";
     for (const auto& kv : c.table) {
         const Key& k = kv.first;
         const Tuning& t = kv.second;
         out << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' '
             << std::get<3>(k) << ' ' << std::get<4>(k) << ' ' << std::get<5>(k) << ' '
-            << t.shape.L << ' ' << t.block_cap << ' ' << t.red_mode << '\n';
+            << std::get<6>(k) << ' ' << t.shape.L << ' ' << t.block_cap << ' ' << t.red_mode
+            << '\n';
     }
     return out ? PCG_OK : PCG_E_INVALID;
 }

@@ -103,12 +103,13 @@ def test_tuning_cache_file_round_trip(lib, tmp_path):
     malformed or unsupported entries) and writes back what it holds."""
     src = tmp_path / "in.txt"
     src.write_text("# comment line\n"
-                   "gfx950 97 89 61 0 1 16 2048 1   # trailing comment\n"
-                   "gfx950 97 89 61 1 64 32 65536 0\n"
-                   "gfx950 97 89 61 0 1 48 2048 1\n"          # L not a power of two
-                   "gfx950 97 89 61 0 1 16 0 1\n"             # block cap below 1
-                   "gfx950 97 89 61 2 1 16 2048 1\n"          # unknown dtype
-                   "gfx950 97 89\n")                          # truncated
+                   "gfx950 uniform 97 89 61 0 1 16 2048 1   # trailing comment\n"
+                   "gfx950 stretched 97 89 61 1 64 32 65536 0\n"
+                   "gfx950 uniform 97 89 61 0 1 48 2048 1\n"      # L not a power of two
+                   "gfx950 uniform 97 89 61 0 1 16 0 1\n"         # block cap below 1
+                   "gfx950 uniform 97 89 61 2 1 16 2048 1\n"      # unknown dtype
+                   "gfx950 curved 97 89 61 0 1 16 2048 1\n"       # unknown geometry
+                   "gfx950 uniform 97 89\n")                      # truncated
     lib.pcg_tuning_cache_load.argtypes = [ctypes.c_char_p]
     lib.pcg_tuning_cache_save.argtypes = [ctypes.c_char_p]
     assert lib.pcg_tuning_cache_load(str(src).encode()) == 0
@@ -116,6 +117,23 @@ def test_tuning_cache_file_round_trip(lib, tmp_path):
     out = tmp_path / "out.txt"
     assert lib.pcg_tuning_cache_save(str(out).encode()) == 0
     rows = [ln.split() for ln in out.read_text().splitlines() if ln and not ln.startswith("#")]
-    mine = sorted(r for r in rows if r[1:4] == ["97", "89", "61"])
-    assert mine == [["gfx950", "97", "89", "61", "0", "1", "16", "2048", "1"],
-                    ["gfx950", "97", "89", "61", "1", "64", "32", "65536", "0"]]
+    mine = sorted(r for r in rows if r[2:5] == ["97", "89", "61"])
+    assert mine == [["gfx950", "stretched", "97", "89", "61", "1", "64", "32", "65536", "0"],
+                    ["gfx950", "uniform", "97", "89", "61", "0", "1", "16", "2048", "1"]]
+
+
+def test_stretched_create_rejects_bad_widths_before_touching_a_device(lib):
+    import paper_1302_7193_amd as pcg
+    d = pcg.pcg_desc_from_ratio(4, 3, 8, 1.05, 1e3, pcg.PCG_BC_DIRICHLET)
+    h = ctypes.c_void_p()
+    dp = ctypes.POINTER(ctypes.c_double)
+    f = lib.pcg_problem_create_stretched
+    f.argtypes = [ctypes.POINTER(pcg.pcg_problem_desc), dp, dp, ctypes.POINTER(ctypes.c_void_p)]
+    good_x, good_y = (ctypes.c_double * 4)(0.25, 0.25, 0.25, 0.25), (ctypes.c_double * 3)(1, 2, 3)
+    for xs, ys in (((0.25, 0.0, 0.25, 0.5), (1, 2, 3)), ((0.25, 0.25, 0.25, 0.25), (1, -2, 3)),
+                   ((0.25, float("nan"), 0.25, 0.5), (1, 2, 3))):
+        xa, ya = (ctypes.c_double * 4)(*xs), (ctypes.c_double * 3)(*ys)
+        assert f(ctypes.byref(d), xa, ya, ctypes.byref(h)) == pcg.PCG_E_INVALID
+        assert not h.value
+    assert f(ctypes.byref(d), None, good_y, ctypes.byref(h)) == pcg.PCG_E_INVALID
+    assert f(ctypes.byref(d), good_x, None, ctypes.byref(h)) == pcg.PCG_E_INVALID

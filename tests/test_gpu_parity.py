@@ -459,7 +459,7 @@ def test_tuning_cache_entry_applies_unless_set_explicitly(tmp_path):
     d = make_desc(23, 19, 61, 1e4)
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     f = tmp_path / "cache.txt"
-    f.write_text(f"{arch} 23 19 61 0 1 8 3 0\n")
+    f.write_text(f"{arch} uniform 23 19 61 0 1 8 3 0\n")
     pcg.pcg_tuning_cache_load(str(f))
     b = cuda(si.rhs_uniform(d.nx, d.ny, d.nz, 44))
     o = pcg.pcg_default_opts()
