@@ -44,19 +44,23 @@ def solve_kernel_bytes(kernel, iterations, n):
     if kernel == "fused_apply":
         return n * (BYTES["fused_apply_first"] + BYTES["fused_apply"] * (iterations - 1))
     return n * (BYTES["fused_prec_first"] + BYTES["fused_prec"] * iterations)
-KERNEL_PATTERN = {"fused_apply": r"k_fused_apply<double, \d+, (true|false), false>",
-                  "fused_prec": r"k_fused_prec<double, \d+, (true|false), false>"}
+KERNEL_PATTERN = {"fused_apply": r"k_fused_apply<double, \d+, (true|false), false, (true|false)>",
+                  "fused_prec": r"k_fused_prec<double, \d+, (true|false), false, (true|false)>"}
+STREAM_BYTES = 64 << 20       # vectors at least this large use nontemporal accesses
 
 
-def kernel_symbol(kernel, lanes_per_column, nz, elem=8, stretched=False):
+def kernel_symbol(kernel, lanes_per_column, n, nz, elem=8, stretched=False, nrhs=1):
     """Template instance of a fused kernel that runs for this launch shape:
-    M levels per lane, 16-byte vector path when whole chunks are aligned."""
+    M levels per lane, 16-byte vector path when whole chunks are aligned,
+    nontemporal accesses for vectors that cannot stay in the caches."""
     m = 1
     while m * lanes_per_column < nz:
         m *= 2
     vec = nz % m == 0 and (m * elem) % 16 == 0 and (nz * elem) % 16 == 0
+    nt = n * nrhs * elem >= STREAM_BYTES and m * elem == 16
     t = "double" if elem == 8 else "float"
-    return "k_%s<%s, %d, %s, %s>" % (kernel, t, m, str(vec).lower(), str(stretched).lower())
+    b = lambda v: str(v).lower()
+    return "k_%s<%s, %d, %s, %s, %s>" % (kernel, t, m, b(vec), b(stretched), b(nt))
 
 
 def log(*a):
@@ -557,7 +561,8 @@ def main():
         kern[k] = dict(avg_ms=avg, launches=m["cnt"][k], achieved_GBps=achieved,
                        algorithmic_bytes_per_launch=per_launch,
                        total_ms=m["ms"][k],
-                       symbol=kernel_symbol(k, m["tuning"]["lanes_per_column"], m["nz"]))
+                       symbol=kernel_symbol(k, m["tuning"]["lanes_per_column_prec" if k == "fused_prec"
+                                                             else "lanes_per_column"], n, m["nz"]))
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     for k in kern:
         kern[k]["traffic"] = measured_traffic(k, "512x512x128", kern[k]["symbol"])

@@ -201,11 +201,17 @@ pcg_status pcg_solve_batched(pcg_problem *p, int32_t nrhs, const double *b, doub
  *                     kernel (device-scope fences in every workgroup);
  *                     1: a separate one-workgroup launch does it.
  * Both reductions add the same numbers in the same order; changing L or
- * block_cap changes the summation order (results stay within rounding). */
+ * block_cap changes the summation order (results stay within rounding).
+ * lanes_per_column_prec / block_cap_prec: L and the block cap of the
+ * line-solve kernels (kernel B of the fused iteration, pcg_precond), which
+ * read and write whole columns independently of the other kernels and
+ * usually prefer fewer lanes per column (shorter scans). */
 typedef struct {
     int32_t lanes_per_column;
     int32_t block_cap;
     int32_t reduction;
+    int32_t lanes_per_column_prec;   /* the same two for the kernels dominated */
+    int32_t block_cap_prec;          /* by the line solve (kernel B, pcg_precond) */
 } pcg_tuning;
 
 pcg_status pcg_get_tuning(const pcg_problem *p, int32_t dtype, pcg_tuning *out);
@@ -225,8 +231,9 @@ pcg_status pcg_tuning_cache_save(const char *path);
 
 /* Autotuner: times fused iterations (kernels A and B over nrhs right-hand
  * sides, on synthetic vectors) for every supported lanes_per_column, a
- * ladder of block caps and both reduction modes, keeps the fastest for
- * (p, dtype), records it in the tuning cache for (shape, dtype, nrhs) and
+ * ladder of block caps and both reduction modes, timing kernel A and kernel
+ * B (each with its reduction) separately, keeps the fastest launch shape of
+ * each and the reduction mode with the fastest pair for (p, dtype), records it in the tuning cache for (shape, dtype, nrhs) and
  * returns it in best (may be NULL).  A set-up utility: it
  * allocates (and frees) its own device scratch of about 5 vectors of
  * nrhs*n values of dtype.  Blocks. */

@@ -53,7 +53,8 @@ class pcg_solve_opts(ctypes.Structure):
 
 class pcg_tuning(ctypes.Structure):
     _fields_ = [("lanes_per_column", ctypes.c_int32), ("block_cap", ctypes.c_int32),
-                ("reduction", ctypes.c_int32)]
+                ("reduction", ctypes.c_int32), ("lanes_per_column_prec", ctypes.c_int32),
+                ("block_cap_prec", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -320,7 +321,13 @@ def pcg_get_tuning(p: Problem, dtype: int) -> pcg_tuning:
 
 
 def pcg_set_tuning(p: Problem, dtype: int, t: pcg_tuning | None = None, **fields) -> None:
+    """Set launch parameters; fields not given keep their current values.  A
+    lanes_per_column or block_cap given without its _prec counterpart sets
+    both (one launch shape for every kernel)."""
     t = t or pcg_get_tuning(p, dtype)
+    for k in ("lanes_per_column", "block_cap"):
+        if k in fields and k + "_prec" not in fields:
+            fields[k + "_prec"] = fields[k]
     for k, v in fields.items():
         setattr(t, k, v)
     _check(_lib.pcg_set_tuning(p.handle, dtype, ctypes.byref(t)), "pcg_set_tuning")

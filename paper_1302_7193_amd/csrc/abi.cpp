@@ -205,6 +205,8 @@ static pcg_status create_problem(const pcg_problem_desc* desc, const double* xw,
         P->tune[d].shape = default_shape(desc->nz, d);
         P->tune[d].block_cap = kDefaultCap;
         P->tune[d].red_mode = 1;
+        P->tune[d].shape_b = P->tune[d].shape;
+        P->tune[d].block_cap_b = kDefaultCap;
     }
     const size_t nv = P->vert64.size(), nl = P->lu64.size(), ng = P->hgeo.size();
     const size_t b64v = al256(8 * nv), b64l = al256(8 * nl), b32v = al256(4 * nv),
@@ -295,9 +297,7 @@ pcg_status pcg_apply(pcg_problem* P, int32_t dtype, const void* x, void* y, void
         TuneScope ts(P, 1);
         ColArgs a{};
         a.g = P->geom;
-        a.L = P->tune[dtype].shape.L;
-        a.red_mode = P->tune[dtype].red_mode;
-        a.blocks_per_rhs = blocks_per_rhs(P, dtype);
+        set_launch(a, P, dtype);
         set_tables(a, P, dtype);
         a.in0 = x;
         a.io0 = y;
@@ -323,9 +323,7 @@ pcg_status pcg_precond(pcg_problem* P, int32_t dtype, const void* r, void* z, vo
         TuneScope ts(P, 1);
         ColArgs a{};
         a.g = P->geom;
-        a.L = P->tune[dtype].shape.L;
-        a.red_mode = P->tune[dtype].red_mode;
-        a.blocks_per_rhs = blocks_per_rhs(P, dtype);
+        set_launch(a, P, dtype);
         set_tables(a, P, dtype);
         a.in0 = r;
         a.io0 = z;
@@ -393,6 +391,8 @@ pcg_status pcg_get_tuning(const pcg_problem* P, int32_t dtype, pcg_tuning* out)
     out->lanes_per_column = t.shape.L;
     out->block_cap = (int32_t)t.block_cap;
     out->reduction = t.red_mode;
+    out->lanes_per_column_prec = t.shape_b.L;
+    out->block_cap_prec = (int32_t)t.block_cap_b;
     return PCG_OK;
 }
 
@@ -402,22 +402,28 @@ pcg_status pcg_set_tuning(pcg_problem* P, int32_t dtype, const pcg_tuning* t)
         set_error("pcg_set_tuning: NULL argument or bad dtype");
         return PCG_E_INVALID;
     }
-    Shape sh;
+    Shape sh, sh_b;
     sh.L = t->lanes_per_column;
-    if (!shape_supported(P->geom.nz, sh)) {
-        set_error("pcg_set_tuning: lanes_per_column must be a power of two in [1, 64] with "
-                  "16 * lanes_per_column >= n_z");
+    sh_b.L = t->lanes_per_column_prec;
+    if (!shape_supported(P->geom.nz, sh) || !shape_supported(P->geom.nz, sh_b)) {
+        set_error("pcg_set_tuning: lanes_per_column and lanes_per_column_prec must be powers "
+                  "of two in [1, 64] with 16 * lanes >= n_z");
         return PCG_E_INVALID;
     }
-    if (t->block_cap < 1 || t->block_cap > kMaxBlocks || (t->reduction != 0 && t->reduction != 1)) {
-        set_error("pcg_set_tuning: block_cap must be in [1, 65536] and reduction 0 or 1");
+    if (t->block_cap < 1 || t->block_cap > kMaxBlocks || t->block_cap_prec < 1 ||
+        t->block_cap_prec > kMaxBlocks || (t->reduction != 0 && t->reduction != 1)) {
+        set_error("pcg_set_tuning: block caps must be in [1, 65536] and reduction 0 or 1");
         return PCG_E_INVALID;
     }
     sh.M = 1;
     while (sh.M * sh.L < P->geom.nz) sh.M <<= 1;
+    sh_b.M = 1;
+    while (sh_b.M * sh_b.L < P->geom.nz) sh_b.M <<= 1;
     P->tune[dtype].shape = sh;
     P->tune[dtype].block_cap = t->block_cap;
     P->tune[dtype].red_mode = t->reduction;
+    P->tune[dtype].shape_b = sh_b;
+    P->tune[dtype].block_cap_b = t->block_cap_prec;
     P->tune_explicit[dtype] = true;
     return PCG_OK;
 }
@@ -441,6 +447,8 @@ pcg_status pcg_autotune(pcg_problem* P, int32_t dtype, int32_t nrhs, void* strea
         best->lanes_per_column = t.shape.L;
         best->block_cap = (int32_t)t.block_cap;
         best->reduction = t.red_mode;
+        best->lanes_per_column_prec = t.shape_b.L;
+        best->block_cap_prec = (int32_t)t.block_cap_b;
     }
     return PCG_OK;
 }

@@ -92,6 +92,8 @@ struct Tuning {
     Shape shape;
     int64_t block_cap = kDefaultCap;   // workgroups per right-hand side
     int red_mode = 1;           // reduction mode (ColArgs::red_mode)
+    Shape shape_b;              // the same two for the line-solve kernels
+    int64_t block_cap_b = kDefaultCap;   // (kernel B, the preconditioner alone)
 };
 
 // ---------------------------------------------------------------- kernels --
@@ -116,6 +118,9 @@ struct ColArgs {
     Geom g;
     int L;
     int64_t blocks_per_rhs;
+    int L_b;                // launch shape of the line-solve kernels (FusedPrec,
+    int64_t bpr_b;          // Precond): column_launches moves it into L and
+                            // blocks_per_rhs for those kinds
     const void* vert;   // Tables<T>::vert
     const void* lu;     // Tables<T>::lu
     const void* in0;    // x (Apply/Init), r (Precond), ...
@@ -143,10 +148,11 @@ struct KernelLaunch {
     const void* func;
     dim3 grid;
     dim3 block;
+    ColArgs args;       // the argument block of this launch
 };
 template <typename T>
 int column_launches(Kind kind, const ColArgs& a, int64_t batch, KernelLaunch out[2]);
-hipError_t issue(const KernelLaunch& k, const ColArgs& a, hipStream_t s);
+hipError_t issue(const KernelLaunch& k, hipStream_t s);
 template <typename T>
 hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s);
 template <typename T>

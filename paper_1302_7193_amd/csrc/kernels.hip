@@ -94,8 +94,23 @@ __device__ __forceinline__ Col make_col(const Geom& g, int64_t c, const double* 
 
 // Load / store the M levels k0..k0+M-1 of column `col`.  V: n_z is a
 // multiple of M and rows are 16-byte aligned, so whole chunks are valid and
-// move as 16-byte vector accesses.
-template <typename T, int M, bool V>
+// move as 16-byte vector accesses.  NT: the access carries the nontemporal
+// hint (vectors streamed once per kernel, larger than the caches).
+template <bool NT, typename T>
+__device__ __forceinline__ T ld1(const T* p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ void st1(T* p, T v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <typename T, int M, bool V, bool NT = false>
 __device__ __forceinline__ void ld(const T* __restrict__ v, int64_t col, bool ok, int k0,
                                    int nz, T (&o)[M])
 {
@@ -103,7 +118,7 @@ __device__ __forceinline__ void ld(const T* __restrict__ v, int64_t col, bool ok
         if (ok && k0 < nz) {
             const T* p = static_cast<const T*>(__builtin_assume_aligned(v + col * nz + k0, 16));
 #pragma unroll
-            for (int t = 0; t < M; ++t) o[t] = p[t];
+            for (int t = 0; t < M; ++t) o[t] = ld1<NT>(p + t);
         } else {
 #pragma unroll
             for (int t = 0; t < M; ++t) o[t] = T(0);
@@ -112,12 +127,12 @@ __device__ __forceinline__ void ld(const T* __restrict__ v, int64_t col, bool ok
 #pragma unroll
         for (int t = 0; t < M; ++t) {
             const int k = k0 + t;
-            o[t] = (ok && k < nz) ? v[col * nz + k] : T(0);
+            o[t] = (ok && k < nz) ? ld1<NT>(v + col * nz + k) : T(0);
         }
     }
 }
 
-template <typename T, int M, bool V>
+template <typename T, int M, bool V, bool NT = false>
 __device__ __forceinline__ void st(T* __restrict__ v, int64_t col, bool ok, int k0, int nz,
                                    const T (&o)[M])
 {
@@ -125,13 +140,13 @@ __device__ __forceinline__ void st(T* __restrict__ v, int64_t col, bool ok, int 
         if (ok && k0 < nz) {
             T* p = static_cast<T*>(__builtin_assume_aligned(v + col * nz + k0, 16));
 #pragma unroll
-            for (int t = 0; t < M; ++t) p[t] = o[t];
+            for (int t = 0; t < M; ++t) st1<NT>(p + t, o[t]);
         }
     } else {
 #pragma unroll
         for (int t = 0; t < M; ++t) {
             const int k = k0 + t;
-            if (ok && k < nz) v[col * nz + k] = o[t];
+            if (ok && k < nz) st1<NT>(v + col * nz + k, o[t]);
         }
     }
 }
@@ -556,7 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
 // FIRST (no iteration done yet): alpha = 0 and q is unset, so q is not read;
 // with a zero start r is taken from b (no start-up kernel), and not stored
 // when b is r itself.
-template <typename T, int M, bool V, bool FIRST, bool G>
+template <typename T, int M, bool V, bool FIRST, bool G, bool NT>
 __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s, int64_t rhs,
                                                 int64_t blk, double (&acc)[2])
 {
@@ -578,24 +593,24 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
         T rc[M], zc[M];
-        ld<T, M, V>(src, c.idx, c.ok, p.k0, g.nz, rc);
+        ld<T, M, V, NT>(src, c.idx, c.ok, p.k0, g.nz, rc);
         if (!FIRST) {
             T qc[M];
-            ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+            ld<T, M, V, NT>(q, c.idx, c.ok, p.k0, g.nz, qc);
 #pragma unroll
             for (int i = 0; i < M; ++i) rc[i] = rc[i] - alpha * qc[i];
         }
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[0] += double(rc[i]) * double(rc[i]);
-        if (!FIRST || store_r) st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+        if (!FIRST || store_r) st<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
         line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, rc, zc);
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[1] += double(rc[i]) * double(zc[i]);
-        st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
+        st<T, M, V, NT>(z, c.idx, c.ok, p.k0, g.nz, zc);
     }
 }
 
-template <typename T, int M, bool V, bool G>
+template <typename T, int M, bool V, bool G, bool NT>
 __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
 {
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
@@ -603,8 +618,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[2] = {0.0, 0.0};
-    if (s->iter == 0) fused_prec_body<T, M, V, true, G>(a, s, rhs, blk, acc);
-    else fused_prec_body<T, M, V, false, G>(a, s, rhs, blk, acc);
+    if (s->iter == 0) fused_prec_body<T, M, V, true, G, NT>(a, s, rhs, blk, acc);
+    else fused_prec_body<T, M, V, false, G, NT>(a, s, rhs, blk, acc);
     double tot[2];
     if (publish<2>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
                    &s->ticket, a.red_mode, tot)) {
@@ -616,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
 // q = A z + beta q; sigma = <p,q> (FP64); scalar step: alpha.
 // FIRST: alpha = 0 and p = q = 0, so p = z, q = A z, and u keeps x0 (written
 // as zero for a zero start); u, p and q are not read.
-template <typename T, int M, bool V, bool FIRST, bool G>
+template <typename T, int M, bool V, bool FIRST, bool G, bool NT>
 __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* s, int64_t rhs,
                                                  int64_t blk, double (&acc)[1])
 {
@@ -650,13 +665,13 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
                 T zero[M];
 #pragma unroll
                 for (int i = 0; i < M; ++i) zero[i] = T(0);
-                st<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, zero);
+                st<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, zero);
             }
         } else {
             T uc[M];
-            ld<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
-            ld<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
-            ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+            ld<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, uc);
+            ld<T, M, V, NT>(pp, c.idx, c.ok, p.k0, g.nz, pc);
+            ld<T, M, V, NT>(q, c.idx, c.ok, p.k0, g.nz, qc);
 #pragma unroll
             for (int i = 0; i < M; ++i) {
                 uc[i] = uc[i] + alpha * pc[i];
@@ -664,14 +679,14 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
                 qc[i] = az[i] + beta * qc[i];
                 acc[0] += double(pc[i]) * double(qc[i]);
             }
-            st<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
+            st<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, uc);
         }
-        st<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
-        st<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+        st<T, M, V, NT>(pp, c.idx, c.ok, p.k0, g.nz, pc);
+        st<T, M, V, NT>(q, c.idx, c.ok, p.k0, g.nz, qc);
     }
 }
 
-template <typename T, int M, bool V, bool G>
+template <typename T, int M, bool V, bool G, bool NT>
 __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
 {
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
@@ -679,8 +694,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[1] = {0.0};
-    if (s->iter == 0) fused_apply_body<T, M, V, true, G>(a, s, rhs, blk, acc);
-    else fused_apply_body<T, M, V, false, G>(a, s, rhs, blk, acc);
+    if (s->iter == 0) fused_apply_body<T, M, V, true, G, NT>(a, s, rhs, blk, acc);
+    else fused_apply_body<T, M, V, false, G, NT>(a, s, rhs, blk, acc);
     double tot[1];
     if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
                    &s->ticket, a.red_mode, tot)) {
@@ -691,7 +706,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
 // Exit correction u += alpha p (the fused iteration leaves u one step
 // behind r).  Runs once: the last workgroup (or the finalize launch) marks
 // it done.
-template <typename T, int M, bool V>
+template <typename T, int M, bool V, bool NT>
 __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
 {
     const Geom& g = a.g;
@@ -721,12 +736,12 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
             for (int i = 0; i < M; ++i) uc[i] = T(0);
         } else {
             T pc[M];
-            ld<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
-            ld<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, pc);
+            ld<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, uc);
+            ld<T, M, V, NT>(pp, c.idx, c.ok, p.k0, g.nz, pc);
 #pragma unroll
             for (int i = 0; i < M; ++i) uc[i] += alpha * pc[i];
         }
-        st<T, M, V>(u, c.idx, c.ok, p.k0, g.nz, uc);
+        st<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, uc);
     }
     if (a.red_mode == 0) {   // mode 1: the finalize launch marks it done
         double acc[1] = {0.0}, tot[1];
@@ -912,7 +927,7 @@ const void* finalize_func(Kind kind)
     }
 }
 
-template <typename T, int M, bool V, bool G>
+template <typename T, int M, bool V, bool G, bool NT>
 const void* main_func_m(Kind kind)
 {
     switch (kind) {
@@ -920,9 +935,9 @@ const void* main_func_m(Kind kind)
     case Kind::Precond: return reinterpret_cast<const void*>(&k_precond<T, M, V, G>);
     case Kind::InitFull: return reinterpret_cast<const void*>(&k_init<T, M, V, false, G>);
     case Kind::InitZero: return reinterpret_cast<const void*>(&k_init<T, M, V, true, false>);
-    case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G>);
-    case Kind::FusedApply: return reinterpret_cast<const void*>(&k_fused_apply<T, M, V, G>);
-    case Kind::Fixup: return reinterpret_cast<const void*>(&k_fixup<T, M, V>);
+    case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G, NT>);
+    case Kind::FusedApply: return reinterpret_cast<const void*>(&k_fused_apply<T, M, V, G, NT>);
+    case Kind::Fixup: return reinterpret_cast<const void*>(&k_fixup<T, M, V, NT>);
     case Kind::TrueResidual:
         if constexpr (sizeof(T) == 8)
             return reinterpret_cast<const void*>(&k_true_residual<M, V, G>);
@@ -937,51 +952,78 @@ const void* main_func_m(Kind kind)
     return nullptr;
 }
 
+template <typename T, int M, bool V, bool G>
+const void* main_func_n(Kind kind, bool nt)
+{
+    return nt ? main_func_m<T, M, V, G, true>(kind) : main_func_m<T, M, V, G, false>(kind);
+}
+
 template <typename T, int M>
-const void* main_func_v(Kind kind, const ColArgs& a)
+const void* main_func_v(Kind kind, const ColArgs& a, bool nt)
 {
     // vector path: whole chunks valid and 16-byte aligned rows and chunks
     const bool vec = (a.g.nz % M == 0) && ((M * sizeof(T)) % 16 == 0) &&
                      ((a.g.nz * sizeof(T)) % 16 == 0);
-    if (a.hgeo) return vec ? main_func_m<T, M, true, true>(kind) : main_func_m<T, M, false, true>(kind);
-    return vec ? main_func_m<T, M, true, false>(kind) : main_func_m<T, M, false, false>(kind);
+    if (a.hgeo)
+        return vec ? main_func_n<T, M, true, true>(kind, nt) : main_func_n<T, M, false, true>(kind, nt);
+    return vec ? main_func_n<T, M, true, false>(kind, nt) : main_func_n<T, M, false, false>(kind, nt);
 }
 
+// Vectors of the fused iteration larger than this are streamed with the
+// nontemporal hint: they cannot stay in the caches (32 MB of L2, 256 MB of
+// Infinity Cache) from one kernel to the next.  Only when a lane moves one
+// 16-byte chunk per vector, so that every store instruction of a wavefront
+// covers whole cache lines: with two or more chunks per lane each
+// instruction writes every other chunk, and nontemporal stores of such
+// partial lines raised the measured write traffic by a tenth.
+constexpr int64_t kStreamBytes = int64_t(64) << 20;
+
 template <typename T>
-const void* main_func(Kind kind, const ColArgs& a)
+const void* main_func(Kind kind, const ColArgs& a, int64_t batch)
 {
     const int M = a.L > 0 ? (a.g.nz + a.L - 1) / a.L : 0;
     int Mp = 1;
     while (Mp < M) Mp <<= 1;
+    const bool nt = a.g.n * batch * (int64_t)sizeof(T) >= kStreamBytes && Mp * sizeof(T) == 16;
     switch (Mp) {
-    case 1: return main_func_v<T, 1>(kind, a);
-    case 2: return main_func_v<T, 2>(kind, a);
-    case 4: return main_func_v<T, 4>(kind, a);
-    case 8: return main_func_v<T, 8>(kind, a);
-    case 16: return main_func_v<T, 16>(kind, a);
+    case 1: return main_func_v<T, 1>(kind, a, nt);
+    case 2: return main_func_v<T, 2>(kind, a, nt);
+    case 4: return main_func_v<T, 4>(kind, a, nt);
+    case 8: return main_func_v<T, 8>(kind, a, nt);
+    case 16: return main_func_v<T, 16>(kind, a, nt);
     default: return nullptr;
     }
 }
 
 }  // namespace
 
+// Kernels dominated by the line solve run with their own launch shape.
+static bool line_solve_kind(Kind k) { return k == Kind::FusedPrec || k == Kind::Precond; }
+
 template <typename T>
-int column_launches(Kind kind, const ColArgs& a, int64_t batch, KernelLaunch out[2])
+int column_launches(Kind kind, const ColArgs& a0, int64_t batch, KernelLaunch out[2])
 {
-    out[0].func = main_func<T>(kind, a);
+    ColArgs a = a0;
+    if (line_solve_kind(kind)) {
+        a.L = a0.L_b;
+        a.blocks_per_rhs = a0.bpr_b;
+    }
+    out[0].func = main_func<T>(kind, a, batch);
     if (!out[0].func) return 0;
     out[0].grid = dim3((unsigned)(a.blocks_per_rhs * batch));
     out[0].block = dim3(kBlock);
+    out[0].args = a;
     if (a.red_mode == 0 || !has_finalize(kind)) return 1;
     out[1].func = finalize_func(kind);
     out[1].grid = dim3((unsigned)batch);
     out[1].block = dim3(kFinalThreads);
+    out[1].args = a;
     return 2;
 }
 
-hipError_t issue(const KernelLaunch& k, const ColArgs& a, hipStream_t s)
+hipError_t issue(const KernelLaunch& k, hipStream_t s)
 {
-    void* args[] = {const_cast<ColArgs*>(&a)};
+    void* args[] = {const_cast<ColArgs*>(&k.args)};
     return hipLaunchKernel(k.func, k.grid, k.block, args, 0, s);
 }
 
@@ -990,7 +1032,7 @@ hipError_t launch_column_main(Kind kind, const ColArgs& a, int64_t batch, hipStr
 {
     KernelLaunch k[2];
     if (column_launches<T>(kind, a, batch, k) < 1) return hipErrorInvalidValue;
-    return issue(k[0], a, s);
+    return issue(k[0], s);
 }
 
 template <typename T>
@@ -998,7 +1040,7 @@ hipError_t launch_column_finalize(Kind kind, const ColArgs& a, int64_t batch, hi
 {
     KernelLaunch k[2];
     if (column_launches<T>(kind, a, batch, k) < 2) return hipSuccess;
-    return issue(k[1], a, s);
+    return issue(k[1], s);
 }
 
 template <typename T>
@@ -1008,7 +1050,7 @@ hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t
     const int n = column_launches<T>(kind, a, batch, k);
     if (n < 1) return hipErrorInvalidValue;
     for (int i = 0; i < n; ++i) {
-        const hipError_t e = issue(k[i], a, s);
+        const hipError_t e = issue(k[i], s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -19,15 +19,17 @@ struct GraphKey {
     int L;
     int red_mode;
     int64_t bpr;
+    int L_b;
+    int64_t bpr_b;
     int64_t nrhs;
     const void* ptrs[8];
     bool operator<(const GraphKey& o) const
     {
-        return std::tie(dtype, kind, iters, L, red_mode, bpr, nrhs, ptrs[0], ptrs[1], ptrs[2],
-                        ptrs[3], ptrs[4], ptrs[5], ptrs[6], ptrs[7]) <
-               std::tie(o.dtype, o.kind, o.iters, o.L, o.red_mode, o.bpr, o.nrhs, o.ptrs[0],
-                        o.ptrs[1], o.ptrs[2], o.ptrs[3], o.ptrs[4], o.ptrs[5], o.ptrs[6],
-                        o.ptrs[7]);
+        return std::tie(dtype, kind, iters, L, red_mode, bpr, L_b, bpr_b, nrhs, ptrs[0], ptrs[1],
+                        ptrs[2], ptrs[3], ptrs[4], ptrs[5], ptrs[6], ptrs[7]) <
+               std::tie(o.dtype, o.kind, o.iters, o.L, o.red_mode, o.bpr, o.L_b, o.bpr_b, o.nrhs,
+                        o.ptrs[0], o.ptrs[1], o.ptrs[2], o.ptrs[3], o.ptrs[4], o.ptrs[5],
+                        o.ptrs[6], o.ptrs[7]);
     }
 };
 
@@ -67,6 +69,21 @@ struct pcg_problem {
 };
 
 namespace pcg {
+
+// Workgroups per right-hand side of the kernels of one precision with the
+// problem's current tuning: the line-solve kernels (b) and all others.
+int64_t blocks_per_rhs(const pcg_problem* P, int dtype);
+int64_t blocks_per_rhs_b(const pcg_problem* P, int dtype);
+
+// Launch shapes and reduction mode of one precision in a kernel argument block.
+inline void set_launch(ColArgs& a, const pcg_problem* P, int dtype)
+{
+    a.L = P->tune[dtype].shape.L;
+    a.blocks_per_rhs = blocks_per_rhs(P, dtype);
+    a.L_b = P->tune[dtype].shape_b.L;
+    a.bpr_b = blocks_per_rhs_b(P, dtype);
+    a.red_mode = P->tune[dtype].red_mode;
+}
 
 // Table pointers of one precision in a kernel argument block.
 inline void set_tables(ColArgs& a, const pcg_problem* P, int dtype)

@@ -36,6 +36,12 @@ int64_t blocks_per_rhs(const pcg_problem* P, int dtype)
     return std::max<int64_t>(1, std::min(t.block_cap, column_blocks(P->geom, t.shape)));
 }
 
+int64_t blocks_per_rhs_b(const pcg_problem* P, int dtype)
+{
+    const Tuning& t = P->tune[dtype];
+    return std::max<int64_t>(1, std::min(t.block_cap_b, column_blocks(P->geom, t.shape_b)));
+}
+
 namespace {
 
 struct Layout {
@@ -81,8 +87,10 @@ Layout plan_n(int64_t cells, const pcg_solve_opts& o, int64_t nrhs, int64_t slot
 // change may be too small afterwards; pcg_solve then reports PCG_E_NOMEM).
 Layout plan(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
 {
-    return plan_n(P->geom.n, o, nrhs,
-                  std::max(blocks_per_rhs(P, PCG_F64), blocks_per_rhs(P, PCG_F32)));
+    int64_t slots = 1;
+    for (int d = 0; d < 2; ++d)
+        slots = std::max({slots, blocks_per_rhs(P, d), blocks_per_rhs_b(P, d)});
+    return plan_n(P->geom.n, o, nrhs, slots);
 }
 
 std::string hip_msg(hipError_t e, const char* what)
@@ -202,6 +210,8 @@ pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, int64_t nrhs
     key.L = a.L;
     key.red_mode = a.red_mode;
     key.bpr = a.blocks_per_rhs;
+    key.L_b = a.L_b;
+    key.bpr_b = a.bpr_b;
     key.nrhs = nrhs;
     const void* ptrs[8] = {a.io0, a.io1, a.io2, a.io3, a.io4, a.st, a.part, a.lu};
     std::memcpy(key.ptrs, ptrs, sizeof(ptrs));
@@ -228,10 +238,9 @@ pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, int64_t nrhs
     }
     hipGraph_t graph = nullptr;
     PCG_HIP(hipGraphCreate(&graph, 0), "hipGraphCreate");
-    ColArgs args = a;   // node parameters are copied when the node is added
-    void* params[] = {&args};
     hipGraphNode_t prev = nullptr;
-    for (const KernelLaunch& l : seq) {
+    for (KernelLaunch& l : seq) {
+        void* params[] = {&l.args};   // copied when the node is added
         hipKernelNodeParams np{};
         np.func = const_cast<void*>(l.func);
         np.gridDim = l.grid;
@@ -366,8 +375,7 @@ ColArgs base_args(const pcg_problem* P, int dtype, char* ws, const Layout& w, in
 {
     ColArgs a{};
     a.g = P->geom;
-    a.L = P->tune[dtype].shape.L;
-    a.red_mode = P->tune[dtype].red_mode;
+    set_launch(a, P, dtype);
     a.blocks_per_rhs = bpr;
     set_tables(a, P, dtype);
     a.part = reinterpret_cast<double*>(ws + w.part);
@@ -652,7 +660,7 @@ pcg_status solve_mixed(pcg_problem* P, const double* b, double* x, char* ws, con
 // the timed work never depends on convergence.  Returns ms per iteration.
 template <typename T>
 pcg_status time_tuning(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const Layout& w,
-                       void* u, hipStream_t s, float* ms_per_iter)
+                       void* u, hipStream_t s, float* ms_b, float* ms_a)
 {
     const int64_t bpr = blocks_per_rhs(P, dtype);
     ColArgs a = base_args(P, dtype, ws, w, bpr);
@@ -665,7 +673,7 @@ pcg_status time_tuning(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
     a.in1 = a.io1;                      // zero start in place: r keeps its data
     a.st = reinterpret_cast<SolverState*>(ws + w.st);
     const int reps = 4;
-    if (ensure_events(P, 2 * reps) != PCG_OK) return PCG_E_DEVICE;
+    if (ensure_events(P, 3 * reps) != PCG_OK) return PCG_E_DEVICE;
     // iter = 1: time the general kernels (alpha = beta = 0, p = q = 0 after
     // the start kernel), not the first-iteration specialisations
     std::vector<SolverState> hs(nrhs, fresh_state(0.0, 0.0, 1 << 30, 1.0));
@@ -677,18 +685,22 @@ pcg_status time_tuning(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
     for (int i = -1; i < reps; ++i) {   // rep -1 warms up
         if (upload_states(P, a.st, hs.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
         if (launch<T>(Kind::InitZero, a, nrhs, s, cnt)) return PCG_E_DEVICE;
-        if (i >= 0) PCG_HIP(hipEventRecord(P->events[2 * i], s), "hipEventRecord");
+        if (i >= 0) PCG_HIP(hipEventRecord(P->events[3 * i], s), "hipEventRecord");
         if (launch<T>(Kind::FusedPrec, a, nrhs, s, cnt)) return PCG_E_DEVICE;
+        if (i >= 0) PCG_HIP(hipEventRecord(P->events[3 * i + 1], s), "hipEventRecord");
         if (launch<T>(Kind::FusedApply, a, nrhs, s, cnt)) return PCG_E_DEVICE;
-        if (i >= 0) PCG_HIP(hipEventRecord(P->events[2 * i + 1], s), "hipEventRecord");
+        if (i >= 0) PCG_HIP(hipEventRecord(P->events[3 * i + 2], s), "hipEventRecord");
     }
-    PCG_HIP(hipEventSynchronize(P->events[2 * reps - 1]), "hipEventSynchronize");
-    float total = 0.f;
+    PCG_HIP(hipEventSynchronize(P->events[3 * reps - 1]), "hipEventSynchronize");
+    float tb = 0.f, ta = 0.f;
     for (int i = 0; i < reps; ++i) {
-        float ms = 0.f;
-        PCG_HIP(hipEventElapsedTime(&ms, P->events[2 * i], P->events[2 * i + 1]),
+        float b = 0.f, a2 = 0.f;
+        PCG_HIP(hipEventElapsedTime(&b, P->events[3 * i], P->events[3 * i + 1]),
                 "hipEventElapsedTime");
-        total += ms;
+        PCG_HIP(hipEventElapsedTime(&a2, P->events[3 * i + 1], P->events[3 * i + 2]),
+                "hipEventElapsedTime");
+        tb += b;
+        ta += a2;
     }
     std::vector<SolverState> out(nrhs);
     if (read_states(P, a.st, out.data(), nrhs, s) != PCG_OK) return PCG_E_DEVICE;
@@ -697,7 +709,8 @@ pcg_status time_tuning(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
             set_error("autotune: the synthetic first iteration did not complete (internal)");
             return PCG_E_DEVICE;
         }
-    *ms_per_iter = total / reps;
+    *ms_b = tb / reps;
+    *ms_a = ta / reps;
     return PCG_OK;
 }
 
@@ -745,8 +758,14 @@ pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
                               0x3f800000, vec_bytes / 4, s),
             "hipMemsetD32Async");
     const Tuning saved = P->tune[dtype];
-    Tuning best_t = saved;
-    float best_ms = 1e30f;
+    // per reduction mode: fastest kernel A (all but the line solve) and
+    // fastest kernel B, each with its launch shape and block cap
+    struct Pick {
+        float ms = 1e30f;
+        Shape sh;
+        int64_t cap = kDefaultCap;
+    };
+    Pick best_a[2], best_b[2];
     const int nz = P->geom.nz;
     for (int L = 1; L <= kWave; L <<= 1) {
         Shape sh;
@@ -762,23 +781,30 @@ pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
                 t.shape = sh;
                 t.block_cap = cap;
                 t.red_mode = mode;
+                t.shape_b = sh;
+                t.block_cap_b = cap;
                 P->tune[dtype] = t;
                 if (column_blocks(P->geom, sh) < cap && total > 512) continue;  // no change
-                float ms = 0.f;
-                pcg_status st = dtype == PCG_F64
-                                    ? time_tuning<double>(P, dtype, nrhs, ws, w, u, s, &ms)
-                                    : time_tuning<float>(P, dtype, nrhs, ws, w, u, s, &ms);
+                float ms_b = 0.f, ms_a = 0.f;
+                pcg_status st =
+                    dtype == PCG_F64 ? time_tuning<double>(P, dtype, nrhs, ws, w, u, s, &ms_b, &ms_a)
+                                     : time_tuning<float>(P, dtype, nrhs, ws, w, u, s, &ms_b, &ms_a);
                 if (st != PCG_OK) {
                     P->tune[dtype] = saved;
                     return st;
                 }
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best_t = t;
-                }
+                if (ms_a < best_a[mode].ms) best_a[mode] = Pick{ms_a, sh, cap};
+                if (ms_b < best_b[mode].ms) best_b[mode] = Pick{ms_b, sh, cap};
             }
         }
     }
+    const int m = best_a[0].ms + best_b[0].ms < best_a[1].ms + best_b[1].ms ? 0 : 1;
+    Tuning best_t;
+    best_t.shape = best_a[m].sh;
+    best_t.block_cap = best_a[m].cap;
+    best_t.shape_b = best_b[m].sh;
+    best_t.block_cap_b = best_b[m].cap;
+    best_t.red_mode = m;
     P->tune[dtype] = best_t;
     if (best) *best = best_t;
     return PCG_OK;

@@ -8,8 +8,10 @@
 //
 // File format, one entry per line ('#' starts a comment):
 //   arch geom nx ny nz dtype nrhs lanes_per_column block_cap reduction
+//        lanes_per_column_prec block_cap_prec
 // with geom "uniform" or "stretched" (the stretched kernels also factorise
-// the column blocks, so their best launch shape differs).
+// the column blocks, so their best launch shape differs); without the last
+// two fields the line-solve kernels take the same shape as the others.
 #include <dlfcn.h>
 
 #include <cstdio>
@@ -69,18 +71,31 @@ bool parse_into(const std::string& path, std::map<Key, Tuning>& table)
         int32_t nx, ny, nz, dtype, L, mode;
         int64_t nrhs, cap;
         if (!(ls >> arch >> geom >> nx >> ny >> nz >> dtype >> nrhs >> L >> cap >> mode)) continue;
+        int32_t L_b = L;
+        int64_t cap_b = cap;
+        if (ls >> L_b) {
+            if (!(ls >> cap_b)) continue;
+        } else {
+            L_b = L;
+        }
         if (geom != "uniform" && geom != "stretched") continue;
-        Shape sh;
+        Shape sh, sh_b;
         sh.L = L;
-        if (dtype < 0 || dtype > 1 || !shape_supported(nz, sh) || cap < 1 || cap > kMaxBlocks ||
+        sh_b.L = L_b;
+        if (dtype < 0 || dtype > 1 || !shape_supported(nz, sh) || !shape_supported(nz, sh_b) ||
+            cap < 1 || cap > kMaxBlocks || cap_b < 1 || cap_b > kMaxBlocks ||
             (mode != 0 && mode != 1))
             continue;   // ignore malformed entries
         sh.M = 1;
         while (sh.M * L < nz) sh.M <<= 1;
+        sh_b.M = 1;
+        while (sh_b.M * L_b < nz) sh_b.M <<= 1;
         Tuning t;
         t.shape = sh;
         t.block_cap = cap;
         t.red_mode = mode;
+        t.shape_b = sh_b;
+        t.block_cap_b = cap_b;
         table[Key(arch, geom, nx, ny, nz, dtype, nrhs)] = t;
     }
     return true;
@@ -160,14 +175,15 @@ pcg_status pcg_tuning_cache_save(const char* path)
         return PCG_E_INVALID;
     }
     out << "# libpcg launch parameters found by pcg_autotune\n"
-        << "# arch geom nx ny nz dtype nrhs lanes_per_column block_cap reduction\n";
+        << "# arch geom nx ny nz dtype nrhs lanes_per_column block_cap reduction "
+           "lanes_per_column_prec block_cap_prec\n";
     for (const auto& kv : c.table) {
         const Key& k = kv.first;
         const Tuning& t = kv.second;
         out << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' '
             << std::get<3>(k) << ' ' << std::get<4>(k) << ' ' << std::get<5>(k) << ' '
             << std::get<6>(k) << ' ' << t.shape.L << ' ' << t.block_cap << ' ' << t.red_mode
-            << '\n';
+            << ' ' << t.shape_b.L << ' ' << t.block_cap_b << '\n';
     }
     return out ? PCG_OK : PCG_E_INVALID;
 }

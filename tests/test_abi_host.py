@@ -104,7 +104,8 @@ def test_tuning_cache_file_round_trip(lib, tmp_path):
     src = tmp_path / "in.txt"
     src.write_text("# comment line\n"
                    "gfx950 uniform 97 89 61 0 1 16 2048 1   # trailing comment\n"
-                   "gfx950 stretched 97 89 61 1 64 32 65536 0\n"
+                   "gfx950 stretched 97 89 61 1 64 32 65536 0 8 1024\n"
+                   "gfx950 stretched 97 89 61 0 64 32 65536 0 8\n"       # prec cap missing
                    "gfx950 uniform 97 89 61 0 1 48 2048 1\n"      # L not a power of two
                    "gfx950 uniform 97 89 61 0 1 16 0 1\n"         # block cap below 1
                    "gfx950 uniform 97 89 61 2 1 16 2048 1\n"      # unknown dtype
@@ -118,8 +119,10 @@ def test_tuning_cache_file_round_trip(lib, tmp_path):
     assert lib.pcg_tuning_cache_save(str(out).encode()) == 0
     rows = [ln.split() for ln in out.read_text().splitlines() if ln and not ln.startswith("#")]
     mine = sorted(r for r in rows if r[2:5] == ["97", "89", "61"])
-    assert mine == [["gfx950", "stretched", "97", "89", "61", "1", "64", "32", "65536", "0"],
-                    ["gfx950", "uniform", "97", "89", "61", "0", "1", "16", "2048", "1"]]
+    assert mine == [["gfx950", "stretched", "97", "89", "61", "1", "64", "32", "65536", "0", "8",
+                     "1024"],
+                    ["gfx950", "uniform", "97", "89", "61", "0", "1", "16", "2048", "1", "16",
+                     "2048"]]
 
 
 def test_stretched_create_rejects_bad_widths_before_touching_a_device(lib):

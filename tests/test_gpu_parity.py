@@ -405,10 +405,56 @@ def test_fp64_solve_parity_under_tunings(L, cap, mode):
     assert err <= 1e-10, err
 
 
+@pytest.mark.parametrize("dtype", [pcg.PCG_F64, pcg.PCG_F32])
+def test_separate_launch_shapes_for_the_line_solve_kernels(dtype):
+    """Kernel B (and the preconditioner alone) with its own lanes per column
+    and block cap: FP64 parity with the oracle at equal iterations, mixed
+    precision to the FP64 tolerance, graph and direct launches bitwise
+    equal, and the preconditioner still the exact line solve."""
+    d = GRIDS["6x11x100-mixedbc"]()
+    b = si.rhs_uniform(d.nx, d.ny, d.nz, 45)
+    A, ref = oracle_run(d, b, rtol=1e-8)
+    k = ref["iterations"]
+    outs = []
+    for gc in (0, 3):
+        p = pcg.Problem(d)
+        pcg.pcg_set_tuning(p, dtype, lanes_per_column=8, block_cap=5, reduction=1,
+                           lanes_per_column_prec=64, block_cap_prec=2)
+        t = pcg.pcg_get_tuning(p, dtype)
+        assert (t.lanes_per_column, t.block_cap, t.lanes_per_column_prec, t.block_cap_prec) == \
+            (8, 5, 64, 2)
+        if dtype == pcg.PCG_F64:
+            o = pcg.pcg_default_opts(rtol=0.0, max_iter=k, graph_chunk=gc)
+        else:
+            o = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED, graph_chunk=gc)
+        bt = cuda(b)
+        x = torch.zeros_like(bt)
+        st, r = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
+        outs.append(x.cpu())
+        if dtype == pcg.PCG_F64:
+            assert r["iterations"] == k
+            err = np.linalg.norm(x.cpu().numpy() - ref["x"]) / np.linalg.norm(ref["x"])
+            assert err <= 1e-10, err
+        else:
+            assert st == pcg.PCG_OK
+            assert oracle.residual_norm(A, b, x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
+    assert torch.equal(outs[0], outs[1])
+    tdt, u = DT[dtype]
+    r = cuda(si.uniform_pm1(46, p.n), tdt)
+    z = torch.full_like(r, float("nan"))
+    pcg.pcg_precond(p, dtype, r, z)
+    torch.cuda.synchronize()
+    M = oracle.line_blocks(A, d.nz)
+    zo = oracle.line_solve(M, r.double().cpu().numpy())
+    fwd = np.linalg.norm(z.double().cpu().numpy() - zo) / np.linalg.norm(zo)
+    assert fwd <= (1e-9 if dtype == pcg.PCG_F64 else 1e-3), fwd
+
+
 def test_set_tuning_rejects_bad_values():
     p = pcg.Problem(GRIDS["7x6x1024-tall"]())
     for bad in (dict(lanes_per_column=32), dict(lanes_per_column=3), dict(block_cap=0),
-                dict(block_cap=70000), dict(reduction=2)):
+                dict(block_cap=70000), dict(reduction=2), dict(lanes_per_column_prec=16),
+                dict(block_cap_prec=0)):
         with pytest.raises(pcg.PCGError):
             pcg.pcg_set_tuning(p, pcg.PCG_F64, **bad)
     t = pcg.pcg_get_tuning(p, pcg.PCG_F64)
