@@ -91,7 +91,23 @@ typedef struct {
                              (direct launches); fills the *_kernel_* fields */
     int32_t true_residual;/* 1: also compute ||b - A x|| / ||r0|| in FP64    */
     int32_t x0_zero;      /* 1: start from x0 = 0 without reading x          */
+    int32_t preconditioner; /* PCG_PRECOND_LINE (default) or PCG_PRECOND_MG  */
+    int32_t mg_levels;    /* MG: at most this many levels (0: every level the
+                             grid allows; 1: line-Jacobi sweeps only)        */
 } pcg_solve_opts;
+
+/* Preconditioners.  LINE: the vertical line preconditioner (one tridiagonal
+ * solve per column, Sec. 4.1-4.2).  MG: one V-cycle of a tensor-product
+ * multigrid built on it, the extension the paper names as its next step
+ * (Sec. 1, Sec. 8): only the horizontal grid is coarsened (2 x 2 cells
+ * merged per level while n_x and n_y are even and the halves have >= 4
+ * cells), coarse operators are the same discretisation on the coarse grid,
+ * prolongation copies a coarse column to its four children and restriction
+ * sums them, the smoother is vertical-line Jacobi damped by 0.8 with one
+ * pre- and one post-smoothing sweep (4 sweeps on the coarsest level).  The
+ * V-cycle is symmetric positive definite, so the same CG applies.  MG runs
+ * in the fused iteration only (fused = 1; FP64 or mixed precision). */
+enum { PCG_PRECOND_LINE = 0, PCG_PRECOND_MG = 1 };
 
 typedef struct {
     int32_t status;            /* pcg_status of the solve                    */
@@ -163,6 +179,18 @@ pcg_status pcg_apply(pcg_problem *p, int32_t dtype, const void *x, void *y, void
  * MatrixFreeTridiagonalSystem).  r and z: n values of dtype; may alias.
  * Asynchronous on stream. */
 pcg_status pcg_precond(pcg_problem *p, int32_t dtype, const void *r, void *z, void *stream);
+
+/* Multigrid preconditioner alone: z = B r for one V-cycle B (see
+ * PCG_PRECOND_MG) over at most mg_levels levels (0: all).  r and z: n values
+ * of dtype, distinct.  workspace: at least pcg_mg_bytes(p, dtype, mg_levels)
+ * bytes of device memory (16-byte aligned) for the coarse levels and one
+ * fine-level vector.  pcg_mg_levels: the number of levels the grid allows.
+ * Asynchronous on stream. */
+int32_t pcg_mg_levels(const pcg_problem *p);
+size_t pcg_mg_bytes(const pcg_problem *p, int32_t dtype, int32_t mg_levels);
+pcg_status pcg_mg_precond(pcg_problem *p, int32_t dtype, const void *r, void *z,
+                          int32_t mg_levels, void *workspace, size_t workspace_bytes,
+                          void *stream);
 
 /* Solve A x = b.  b, x: n FP64 values; x holds x0 on entry and the solution
  * on return.  workspace: at least pcg_workspace_bytes(p, opts, 1) bytes of

@@ -31,6 +31,7 @@ PCG_E_NOCONV, PCG_E_BREAKDOWN, PCG_E_AGAIN, PCG_E_CANCELLED = -4, -5, -6, -7
 PCG_BC_DIRICHLET, PCG_BC_PERIODIC = 0, 1
 PCG_F64, PCG_F32 = 0, 1
 PCG_PREC_FP64, PCG_PREC_MIXED = 0, 1
+PCG_PRECOND_LINE, PCG_PRECOND_MG = 0, 1
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_NOCONV",
                 -5: "E_BREAKDOWN", -6: "E_AGAIN", -7: "E_CANCELLED"}
 
@@ -48,7 +49,8 @@ class pcg_solve_opts(ctypes.Structure):
                 ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("fused", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("true_residual", ctypes.c_int32),
-                ("x0_zero", ctypes.c_int32)]
+                ("x0_zero", ctypes.c_int32), ("preconditioner", ctypes.c_int32),
+                ("mg_levels", ctypes.c_int32)]
 
 
 class pcg_tuning(ctypes.Structure):
@@ -102,6 +104,9 @@ _sig = {
     "pcg_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(pcg_solve_opts), ctypes.c_int32]),
     "pcg_apply": (_S, [_P, ctypes.c_int32, _P, _P, _P]),
     "pcg_precond": (_S, [_P, ctypes.c_int32, _P, _P, _P]),
+    "pcg_mg_levels": (ctypes.c_int32, [_P]),
+    "pcg_mg_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "pcg_mg_precond": (_S, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "pcg_solve": (_S, [_P, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(pcg_solve_opts),
                        ctypes.POINTER(pcg_result), _P]),
     "pcg_solve_batched": (_S, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t,
@@ -267,6 +272,23 @@ def pcg_precond(p: Problem, dtype: int, r, z, stream=None) -> int:
     td = _TORCH_DTYPE[dtype]
     return _check(_lib.pcg_precond(p.handle, dtype, _vec(r, p.n, td, "r"), _vec(z, p.n, td, "z"),
                                    _stream(stream)), "pcg_precond")
+
+
+def pcg_mg_levels(p: Problem) -> int:
+    return _lib.pcg_mg_levels(p.handle)
+
+
+def pcg_mg_bytes(p: Problem, dtype: int, mg_levels: int = 0) -> int:
+    return _lib.pcg_mg_bytes(p.handle, dtype, mg_levels)
+
+
+def pcg_mg_precond(p: Problem, dtype: int, r, z, ws, mg_levels: int = 0, stream=None) -> int:
+    td = _TORCH_DTYPE[dtype]
+    need = pcg_mg_bytes(p, dtype, mg_levels)
+    return _check(_lib.pcg_mg_precond(p.handle, dtype, _vec(r, p.n, td, "r"), _vec(z, p.n, td, "z"),
+                                      mg_levels, _buf(ws, need, "workspace"),
+                                      ws.numel() * ws.element_size(), _stream(stream)),
+                  "pcg_mg_precond")
 
 
 def pcg_solve(p: Problem, b, x, ws, opts: pcg_solve_opts | None = None, stream=None):

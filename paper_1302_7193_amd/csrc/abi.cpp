@@ -18,6 +18,9 @@ std::string stretched_geometry(const pcg_problem_desc& d, const double* xw, cons
 void build_tables(const pcg_problem_desc& d, Geom& g, std::vector<double>& vert,
                   std::vector<double>& lu);
 size_t workspace_bytes(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs);
+size_t mg_bytes(const pcg_problem* P, int dtype, int levels_req);
+pcg_status mg_precond(pcg_problem* P, int dtype, const void* r, void* z, int levels_req,
+                      void* workspace, size_t ws_bytes, hipStream_t s);
 int64_t blocks_per_rhs(const pcg_problem* P, int dtype);
 pcg_status autotune(pcg_problem* P, int dtype, int64_t nrhs, hipStream_t s, Tuning* best);
 pcg_status solve(pcg_problem* P, const double* b, double* x, void* workspace, size_t ws_bytes,
@@ -102,6 +105,15 @@ pcg_status check_opts(const pcg_solve_opts& o)
         set_error("graph_chunk must be -1, 0 or positive");
         return PCG_E_INVALID;
     }
+    if ((o.preconditioner != PCG_PRECOND_LINE && o.preconditioner != PCG_PRECOND_MG) ||
+        o.mg_levels < 0) {
+        set_error("preconditioner must be PCG_PRECOND_LINE or PCG_PRECOND_MG, mg_levels >= 0");
+        return PCG_E_INVALID;
+    }
+    if (o.preconditioner == PCG_PRECOND_MG && !o.fused) {
+        set_error("the multigrid preconditioner runs in the fused iteration only");
+        return PCG_E_INVALID;
+    }
     return PCG_OK;
 }
 
@@ -161,6 +173,74 @@ pcg_status pcg_desc_from_ratio(int32_t nx, int32_t ny, int32_t nz, double gradin
         return PCG_E_INVALID;
     }
     *out = d;
+    return PCG_OK;
+}
+
+// Coarse multigrid levels: 2 x 2 horizontal cells merged per level (widths
+// of neighbouring cells summed) while n_x and n_y are even and both halves
+// keep kMgMinCells cells; every level's column LU factors (uniform) or
+// per-index geometry (stretched), in one device allocation.
+static pcg_status build_mg_levels(pcg_problem* P, const double* xw, const double* yw)
+{
+    pcg_problem_desc d = P->desc;
+    std::vector<double> wx, wy;
+    if (xw) {
+        wx.assign(xw, xw + d.nx);
+        wy.assign(yw, yw + d.ny);
+    }
+    std::vector<double> vert;
+    while (d.nx % 2 == 0 && d.ny % 2 == 0 && d.nx / 2 >= kMgMinCells && d.ny / 2 >= kMgMinCells) {
+        d.nx /= 2;
+        d.ny /= 2;
+        d.dx *= 2.0;
+        d.dy *= 2.0;
+        MgLevel m;
+        build_tables(d, m.g, vert, m.lu64);
+        if (xw) {
+            for (int i = 0; i < d.nx; ++i) wx[i] = wx[2 * i] + wx[2 * i + 1];
+            for (int j = 0; j < d.ny; ++j) wy[j] = wy[2 * j] + wy[2 * j + 1];
+            wx.resize(d.nx);
+            wy.resize(d.ny);
+            const std::string err = stretched_geometry(d, wx.data(), wy.data(), m.hgeo);
+            if (!err.empty()) {
+                set_error(err);
+                return PCG_E_INVALID;
+            }
+        }
+        P->mg.push_back(std::move(m));
+    }
+    if (P->mg.empty()) return PCG_OK;
+    size_t total = 0;
+    for (const MgLevel& m : P->mg)
+        total += al256(8 * m.lu64.size()) + al256(4 * m.lu64.size()) + al256(8 * m.hgeo.size());
+    hipError_t e = hipMalloc(&P->mg_tables, total);
+    if (e != hipSuccess) {
+        set_error(hip_msg(e, "hipMalloc(multigrid tables)"));
+        return PCG_E_NOMEM;
+    }
+    std::vector<char> host(total, 0);
+    size_t off = 0;
+    char* base = static_cast<char*>(P->mg_tables);
+    for (MgLevel& m : P->mg) {
+        const size_t nl = m.lu64.size(), ng = m.hgeo.size();
+        std::memcpy(host.data() + off, m.lu64.data(), 8 * nl);
+        m.d_lu64 = reinterpret_cast<const double*>(base + off);
+        off += al256(8 * nl);
+        float* l32 = reinterpret_cast<float*>(host.data() + off);
+        for (size_t i = 0; i < nl; ++i) l32[i] = (float)m.lu64[i];
+        m.d_lu32 = reinterpret_cast<const float*>(base + off);
+        off += al256(4 * nl);
+        if (ng) {
+            std::memcpy(host.data() + off, m.hgeo.data(), 8 * ng);
+            m.d_hgeo = reinterpret_cast<const double*>(base + off);
+        }
+        off += al256(8 * ng);
+    }
+    e = hipMemcpy(P->mg_tables, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        set_error(hip_msg(e, "hipMemcpy(multigrid tables)"));
+        return PCG_E_DEVICE;
+    }
     return PCG_OK;
 }
 
@@ -239,6 +319,11 @@ static pcg_status create_problem(const pcg_problem_desc* desc, const double* xw,
     P->d_vert32 = reinterpret_cast<const float*>(base + b64v + b64l);
     P->d_lu32 = reinterpret_cast<const float*>(base + b64v + b64l + b32v);
     if (ng) P->d_hgeo = reinterpret_cast<const double*>(base + b64v + b64l + b32v + b32l);
+    const pcg_status mst = build_mg_levels(P, xw, yw);
+    if (mst != PCG_OK) {
+        pcg_problem_destroy(P);
+        return mst;
+    }
     *out = P;
     return PCG_OK;
 }
@@ -269,6 +354,7 @@ void pcg_problem_destroy(pcg_problem* P)
     for (hipEvent_t e : P->events) (void)hipEventDestroy(e);
     if (P->pinned_states) (void)hipHostFree(P->pinned_states);
     if (P->dev_tables) (void)hipFree(P->dev_tables);
+    if (P->mg_tables) (void)hipFree(P->mg_tables);
     if (cur >= 0) (void)hipSetDevice(cur);
     delete P;
 }
@@ -335,6 +421,33 @@ pcg_status pcg_precond(pcg_problem* P, int32_t dtype, const void* r, void* z, vo
             return PCG_E_DEVICE;
         }
         return PCG_OK;
+    });
+}
+
+int32_t pcg_mg_levels(const pcg_problem* P) { return P ? 1 + (int32_t)P->mg.size() : 0; }
+
+size_t pcg_mg_bytes(const pcg_problem* P, int32_t dtype, int32_t mg_levels)
+{
+    if (!P || !valid_dtype(dtype) || mg_levels < 0) return 0;
+    return mg_bytes(P, dtype, mg_levels);
+}
+
+pcg_status pcg_mg_precond(pcg_problem* P, int32_t dtype, const void* r, void* z,
+                          int32_t mg_levels, void* workspace, size_t workspace_bytes,
+                          void* stream)
+{
+    if (!P || !r || !z || !workspace || !valid_dtype(dtype) || mg_levels < 0) {
+        set_error("pcg_mg_precond: NULL argument, bad dtype or mg_levels < 0");
+        return PCG_E_INVALID;
+    }
+    if (r == z) {
+        set_error("pcg_mg_precond: r and z must not overlap");
+        return PCG_E_INVALID;
+    }
+    if (check_aligned({r, z, workspace}, "pcg_mg_precond") != PCG_OK) return PCG_E_INVALID;
+    return on_device(P->device, [&]() -> pcg_status {
+        return mg_precond(P, dtype, r, z, mg_levels, workspace, workspace_bytes,
+                          static_cast<hipStream_t>(stream));
     });
 }
 

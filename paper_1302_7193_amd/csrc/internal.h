@@ -20,6 +20,9 @@ constexpr int kClasses = 9;        // column classes: Dirichlet faces in x (0..2
 constexpr int kRedSlots = 2;       // doubles per workgroup in the partial-sum buffer
 constexpr int64_t kMaxBlocks = 65536;   // largest workgroup cap per right-hand side
 constexpr int64_t kDefaultCap = 16384;  // default workgroup cap per right-hand side
+constexpr double kMgOmega = 0.8;   // multigrid: damping of the line-Jacobi smoother
+constexpr int kMgMinCells = 4;     // coarsen while both halves keep >= 4 cells
+constexpr int kMgCoarseSweeps = 4; // smoothing sweeps from zero on the coarsest level
 
 // Solver flags kept in device memory.
 enum : int32_t {
@@ -109,6 +112,14 @@ enum class Kind : int {
     Residual64,   // FP64 r = b - A x, ||r||; FP32 copy r * scale  (refinement)
     Update64,     // FP64 x += u32 / scale                         (refinement)
     TrueResidual, // FP64 ||b - A x||
+    // tensor-product multigrid preconditioner (mg.hip), on one level each:
+    MgPre,        // z = omega M^{-1} r                      (pre-smoothing from zero)
+    MgPreFused,   // the same, first: r -= alpha q, as kernel B does
+    MgRestrict,   // coarse r = P^T (r - A z)                 (tiles of the coarse level)
+    MgPost,       // z += P z_c; z += omega M^{-1}(r - A z)   (post-smoothing)
+    MgPostFinal,  // the same, then R, kappa; exit test; beta  (ends kernel B's work)
+    MgSmooth,     // z += omega M^{-1}(r - A z)               (coarsest level)
+    MgSmoothFinal,// the same, then R, kappa; exit test; beta  (single-level hierarchy)
 };
 
 // One argument block serves every column kernel; unused pointers are null.
@@ -137,7 +148,17 @@ struct ColArgs {
     int x0_zero;        // refinement kernels: x is zero (not read)
     const double* hgeo; // stretched grids: per-index widths and face weights
                         // [w_x m_x p_x](n_x) [w_y m_y p_y](n_y); null when uniform
+    // multigrid kernels: the other level of an intergrid transfer (the fine
+    // level for MgRestrict, the coarse one for MgPost*), its geometry table,
+    // and the smoother's damping
+    Geom g2;
+    const double* hgeo2;
+    double omega;
 };
+
+// Multigrid kernels (mg.hip): kernel for a Kind >= MgPre, or null.
+template <typename T>
+const void* mg_func(Kind kind, const ColArgs& a);
 
 // Host launchers (kernels.hip): T = double or float.  column_launches
 // returns the kernel (and, for mode-1 reductions, its finalize kernel) with

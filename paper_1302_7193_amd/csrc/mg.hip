@@ -1,0 +1,245 @@
+// Tensor-product multigrid preconditioner (gfx950).
+//
+// Sec. 1 and Sec. 8 of the paper name the next step: a geometric multigrid
+// in the tensor-product spirit, with the vertical line relaxation of
+// Sec. 4.1 as the smoother and only the horizontal grid coarsened.  Level
+// l+1 merges 2 x 2 horizontal cells of level l and keeps every vertical
+// column, so every level is the same kind of operator (the column kernels'
+// stencil and line solve apply unchanged with the level's geometry).
+// Prolongation is piecewise constant in the horizontal (a fine column takes
+// its parent's values), restriction its transpose (a coarse residual is the
+// sum of its four children's), and the smoother is damped line Jacobi.
+//
+// Kernels, each over one level and fused to read every vector once:
+//   k_mg_pre       t = omega M^{-1} r            (FUSED: r -= alpha q first,
+//                                                 as kernel B of the fused
+//                                                 iteration does)
+//   k_mg_restrict  r_c = P^T (r - A t)           (one coarse column per lane
+//                                                 segment: four children)
+//   k_mg_post      w = t + P z_c;                (PROLONG: the correction is
+//                  z = w + omega M^{-1}(r - A w)  added as neighbours load)
+//                  FINAL: R = <r,r>, kappa = <r,z>; exit test; beta
+// A sweep reads neighbouring columns of its input iterate, so it writes a
+// different vector (t and z alternate).
+// A V-cycle is pre / restrict down the levels, sweeps on the coarsest, and
+// post back up; the fused iteration ends its kernel-B work with the fine
+// level's FINAL post-smoothing.
+#include "column.h"
+
+namespace pcg {
+namespace {
+
+// Writes t = a.io2 from r (FUSED: from r or b with the update of kernel B,
+// r written back to a.io1).
+template <typename T, int M, bool V, bool G, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_mg_pre(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st ? a.st + rhs : nullptr;
+    if (s && s->flag != kRunning) return;
+    const int64_t off = rhs * g.n;
+    const T* src;
+    T* r = nullptr;
+    const T* q = nullptr;
+    T alpha = T(0);
+    bool first = false, store_r = false;
+    if constexpr (FUSED) {
+        first = s->iter == 0;
+        const bool from_b = first && s->zero_start;
+        src = static_cast<const T*>(from_b ? a.in1 : a.io1) + off;
+        r = static_cast<T*>(a.io1) + off;
+        store_r = !(from_b && a.in1 == a.io1);
+        q = static_cast<const T*>(a.io4) + off;
+        alpha = T(s->alpha);
+    } else {
+        src = static_cast<const T*>(a.in0) + off;
+    }
+    T* z = static_cast<T*>(a.io2) + off;
+    const T* lu = static_cast<const T*>(a.lu);
+    const T omega = T(a.omega);
+    const Lane p = lane_pos<M>(L);
+    const SolveCoef<T, M, G> sc = load_solve<T, M, V, G>(g, a, p.k0);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        T rc[M], zc[M];
+        ld<T, M, V>(src, c.idx, c.ok, p.k0, g.nz, rc);
+        if constexpr (FUSED) {
+            if (!first) {
+                T qc[M];
+                ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+#pragma unroll
+                for (int i = 0; i < M; ++i) rc[i] = rc[i] - alpha * qc[i];
+            }
+            if (!first || store_r) st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+        }
+        line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, rc, zc);
+#pragma unroll
+        for (int i = 0; i < M; ++i) zc[i] *= omega;
+        st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
+    }
+}
+
+// Tiles of the coarse level a.g; the fine level is a.g2 (geometry a.hgeo2);
+// reads r = a.in0 and t = a.in1 of the fine level, writes a.io0.
+template <typename T, int M, bool V, bool G>
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(ColArgs a)
+{
+    const Geom& gc = a.g;
+    const Geom& gf = a.g2;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    if (a.st && a.st[rhs].flag != kRunning) return;
+    const T* r = static_cast<const T*>(a.in0) + rhs * gf.n;
+    const T* z = static_cast<const T*>(a.in1) + rhs * gf.n;
+    T* rc_out = static_cast<T*>(a.io0) + rhs * gc.n;
+    const Lane p = lane_pos<M>(L);
+    const VertCoef<T, M> vc = load_vert<T, M, V>(gf, static_cast<const T*>(a.vert), p.k0);
+    int64_t t0, t1;
+    block_tiles(gc, L, blk, a.blocks_per_rhs, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t cc = tile_col(tile, p, L);
+        const bool ok = cc < gc.nh;
+        const int64_t I = ok ? cc / gc.ny : 0, J = ok ? cc - (cc / gc.ny) * gc.ny : 0;
+        T acc[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc[i] = T(0);
+#pragma unroll
+        for (int child = 0; child < 4; ++child) {
+            const int64_t fcol = (2 * I + (child >> 1)) * gf.ny + (2 * J + (child & 1));
+            const Col c = make_col<G>(gf, ok ? fcol : gf.nh, a.hgeo2);
+            T zf[M], az[M], rf[M];
+            ld<T, M, V>(z, c.idx, c.ok, p.k0, gf.nz, zf);
+            stencil<T, M, V, G>(gf, c, p.l, L, p.k0, z, zf, vc, az);
+            ld<T, M, V>(r, c.idx, c.ok, p.k0, gf.nz, rf);
+#pragma unroll
+            for (int i = 0; i < M; ++i) acc[i] += rf[i] - az[i];
+        }
+        st<T, M, V>(rc_out, ok ? cc : 0, ok, p.k0, gc.nz, acc);
+    }
+}
+
+// Column of the coarse level a.g2 that contains fine column col of a.g.
+__device__ __forceinline__ int64_t parent_col(const Geom& g, const Geom& gc, int64_t col)
+{
+    const int64_t i = col / g.ny, j = col - i * g.ny;
+    return (i >> 1) * gc.ny + (j >> 1);
+}
+
+// Reads r = a.in0, the iterate t = a.io3 and (PROLONG) the coarse
+// correction a.in1 on level a.g2; writes z = a.io2 (never t).
+template <typename T, int M, bool V, bool G, bool PROLONG, bool FINAL>
+__global__ __launch_bounds__(kBlock) void k_mg_post(ColArgs a)
+{
+    const Geom& g = a.g;
+    const Geom& gc = a.g2;
+    const int L = a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st ? a.st + rhs : nullptr;
+    if (s && s->flag != kRunning) return;
+    const int64_t off = rhs * g.n;
+    const T* r = static_cast<const T*>(a.in0) + off;
+    const T* zin = static_cast<const T*>(a.io3) + off;
+    T* z = static_cast<T*>(a.io2) + off;
+    const T* zc = PROLONG ? static_cast<const T*>(a.in1) + rhs * gc.n : nullptr;
+    const T* lu = static_cast<const T*>(a.lu);
+    const T omega = T(a.omega);
+    const Lane p = lane_pos<M>(L);
+    const VertCoef<T, M> vc = load_vert<T, M, V>(g, static_cast<const T*>(a.vert), p.k0);
+    const SolveCoef<T, M, G> sc = load_solve<T, M, V, G>(g, a, p.k0);
+    // the corrected iterate t + P z_c on any column of this level
+    auto load_z = [&](int64_t col, bool ok, T (&o)[M]) {
+        ld<T, M, V>(zin, col, ok, p.k0, g.nz, o);
+        if constexpr (PROLONG) {
+            T pc[M];
+            ld<T, M, V>(zc, ok ? parent_col(g, gc, col) : 0, ok, p.k0, g.nz, pc);
+#pragma unroll
+            for (int i = 0; i < M; ++i) o[i] += pc[i];
+        }
+    };
+    double acc[2] = {0.0, 0.0};
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        T zo[M], az[M], rc[M], dz[M];
+        load_z(c.idx, c.ok, zo);
+        stencil_nb<T, M, G>(g, c, p.l, L, zo, vc, load_z, az);
+        ld<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+#pragma unroll
+        for (int i = 0; i < M; ++i) az[i] = rc[i] - az[i];
+        line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, az, dz);
+#pragma unroll
+        for (int i = 0; i < M; ++i) zo[i] += omega * dz[i];
+        st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zo);
+        if constexpr (FINAL) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                acc[0] += double(rc[i]) * double(rc[i]);
+                acc[1] += double(rc[i]) * double(zo[i]);
+            }
+        }
+    }
+    if constexpr (FINAL) {
+        double tot[2];
+        if (publish<2>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                       &s->ticket, a.red_mode, tot)) {
+            if (threadIdx.x == 0) finish_prec(s, tot[0], tot[1]);
+        }
+    }
+}
+
+template <typename T, int M, bool V, bool G>
+const void* mg_func_m(Kind kind)
+{
+    switch (kind) {
+    case Kind::MgPre: return reinterpret_cast<const void*>(&k_mg_pre<T, M, V, G, false>);
+    case Kind::MgPreFused: return reinterpret_cast<const void*>(&k_mg_pre<T, M, V, G, true>);
+    case Kind::MgRestrict: return reinterpret_cast<const void*>(&k_mg_restrict<T, M, V, G>);
+    case Kind::MgPost: return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, true, false>);
+    case Kind::MgPostFinal: return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, true, true>);
+    case Kind::MgSmooth: return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, false, false>);
+    case Kind::MgSmoothFinal:
+        return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, false, true>);
+    default: return nullptr;
+    }
+}
+
+template <typename T, int M>
+const void* mg_func_v(Kind kind, const ColArgs& a)
+{
+    const bool vec = (a.g.nz % M == 0) && ((M * sizeof(T)) % 16 == 0) &&
+                     ((a.g.nz * sizeof(T)) % 16 == 0);
+    if (a.hgeo || a.hgeo2)
+        return vec ? mg_func_m<T, M, true, true>(kind) : mg_func_m<T, M, false, true>(kind);
+    return vec ? mg_func_m<T, M, true, false>(kind) : mg_func_m<T, M, false, false>(kind);
+}
+
+}  // namespace
+
+template <typename T>
+const void* mg_func(Kind kind, const ColArgs& a)
+{
+    const int M = a.L > 0 ? (a.g.nz + a.L - 1) / a.L : 0;
+    int Mp = 1;
+    while (Mp < M) Mp <<= 1;
+    switch (Mp) {
+    case 1: return mg_func_v<T, 1>(kind, a);
+    case 2: return mg_func_v<T, 2>(kind, a);
+    case 4: return mg_func_v<T, 4>(kind, a);
+    case 8: return mg_func_v<T, 8>(kind, a);
+    case 16: return mg_func_v<T, 16>(kind, a);
+    default: return nullptr;
+    }
+}
+
+template const void* mg_func<double>(Kind, const ColArgs&);
+template const void* mg_func<float>(Kind, const ColArgs&);
+
+}  // namespace pcg

@@ -39,6 +39,17 @@ struct pcg_problem;
 
 namespace pcg {
 
+// A coarse level of the multigrid hierarchy (level 1, 2, ...; level 0 is the
+// problem itself): its geometry and device tables (the vertical tables are
+// the same on every level).
+struct MgLevel {
+    Geom g{};
+    std::vector<double> lu64, hgeo;
+    const double* d_lu64 = nullptr;
+    const float* d_lu32 = nullptr;
+    const double* d_hgeo = nullptr;   // stretched grids only
+};
+
 // Tuning cache (tuning_cache.cpp).
 bool tuning_lookup(const pcg_problem* P, int dtype, int64_t nrhs, Tuning* out);
 void tuning_store(const pcg_problem* P, int dtype, int64_t nrhs, const Tuning& t);
@@ -52,6 +63,8 @@ struct pcg_problem {
     int device = 0;
     std::vector<double> vert64, lu64;      // host copies of the tables
     std::vector<double> hgeo;              // stretched grids: per-index geometry (else empty)
+    std::vector<pcg::MgLevel> mg;          // coarse multigrid levels
+    void* mg_tables = nullptr;             // their device tables
     void* dev_tables = nullptr;            // vert64 | lu64 | vert32 | lu32 | hgeo
     const double* d_hgeo = nullptr;        // null for uniform grids
     const double* d_vert64 = nullptr;

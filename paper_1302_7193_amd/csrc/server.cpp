@@ -33,7 +33,7 @@
 
 namespace pcg {
 
-size_t request_bytes(int64_t n, const pcg_solve_opts& o);
+size_t request_bytes(const pcg_problem_desc& d, const pcg_solve_opts& o);
 pcg_status solve(pcg_problem* P, const double* b, double* x, void* workspace, size_t ws_bytes,
                  const pcg_solve_opts& o, int64_t nrhs, pcg_result* res, hipStream_t s);
 std::string validate(const pcg_problem_desc& d);
@@ -216,7 +216,7 @@ size_t pcg_request_bytes(const pcg_problem_desc* desc, const pcg_solve_opts* opt
     if (opts) o = *opts;
     else pcg_default_opts(&o);
     const int64_t n = (int64_t)desc->nx * desc->ny * desc->nz;
-    return 2 * al256(8 * (size_t)n) + pcg::request_bytes(n, o);
+    return 2 * al256(8 * (size_t)n) + pcg::request_bytes(*desc, o);
 }
 
 pcg_status pcg_server_create(const pcg_server_opts* opts, void* arena, size_t arena_bytes,
@@ -295,8 +295,7 @@ static pcg_status submit(pcg_server* S, const pcg_problem_desc* desc, const pcg_
     r->device_io = device_io;
     r->need = pcg_request_bytes(desc, &r->opts);
     if (device_io) {   // only the workspace lives in the arena
-        const int64_t n = (int64_t)desc->nx * desc->ny * desc->nz;
-        r->need = pcg::request_bytes(n, r->opts);
+        r->need = pcg::request_bytes(*desc, r->opts);
         // order the solve after the work already queued on the producer stream
         if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
             hipEventRecord(r->ready, producer) != hipSuccess) {
