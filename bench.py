@@ -230,6 +230,7 @@ def extras(pcg, si, torch, main):
     del P3, b3, x3
 
     out["stretched_512x512x128_fp64"] = stretched(pcg, si, torch, out["fused_fp64_graph"])
+    out["multigrid_512x512x128"] = multigrid(pcg, si, torch)
     out["batched_256x256x64x64"] = batched(pcg, si, torch)
     out["serving_512_requests"] = serving(pcg, si, torch)
 
@@ -270,6 +271,47 @@ def stretched(pcg, si, torch, uniform):
                precond_us=t_pc * 1e3, precond_GBps=BYTES["precond"] * n / (t_pc * 1e-3) / 1e9,
                tuning=pcg.pcg_get_tuning(P, pcg.PCG_F64).as_dict())
     log("stretched 512x512x128: %.3f ms/solve, %.1f it" % (ms, its))
+    return out
+
+
+def multigrid(pcg, si, torch):
+    """Tensor-product multigrid preconditioner vs vertical line relaxation on
+    512 x 512 x 128 Dirichlet with weak anisotropy (1e2: line relaxation
+    alone needs many iterations) and on the main workload's operator
+    (anisotropy 1e5, periodic): FP64 fused solves on the graph path, mixed
+    precision on the weak case, and the V-cycle's share of an iteration from
+    per-phase events."""
+    out = {}
+    for tag, g2, bc in (("anisotropy_1e2_dirichlet", 1e2, pcg.PCG_BC_DIRICHLET),
+                        ("anisotropy_1e5_periodic", 1e5, pcg.PCG_BC_PERIODIC)):
+        d = pcg.pcg_desc_from_ratio(512, 512, 128, 1.05, g2, bc)
+        P = pcg.Problem(d)
+        b = torch.from_numpy(si.rhs_uniform(512, 512, 128, 1)).cuda()
+        x = torch.empty_like(b)
+        res = dict(levels=pcg.pcg_mg_levels(P))
+        for name, kw in (("line_fp64", dict()), ("mg_fp64", dict(preconditioner=pcg.PCG_PRECOND_MG)),
+                         ("line_mixed", dict(precision=pcg.PCG_PREC_MIXED)),
+                         ("mg_mixed", dict(precision=pcg.PCG_PREC_MIXED,
+                                           preconditioner=pcg.PCG_PRECOND_MG))):
+            if "mixed" in name and g2 > 1e4:
+                continue
+            o = pcg.pcg_default_opts(x0_zero=1, graph_chunk=-1, true_residual=1, **kw)
+            ws = pcg.workspace(P, o)
+            ms, its, st, r = timed_solves(pcg, torch, P, b, x, ws, o, 3)
+            res[name] = dict(ms_per_solve=ms, iterations=its, outer=r["outer_iterations"],
+                             status=pcg.STATUS_NAMES[st], rel_res_true=r["rel_res_true"],
+                             ms_per_iteration=ms / max(its, 1))
+            if name.endswith("fp64"):
+                op = pcg.pcg_default_opts(x0_zero=1, profile=1, **kw)
+                st, rp = pcg.pcg_solve(P, b, x, ws, op)
+                res[name]["kernel_a_ms_per_launch"] = rp["ms_apply_kernel"] / max(rp["n_apply_kernel"], 1)
+                res[name]["kernel_b_phase_ms_per_launch"] = (rp["ms_precond_kernel"] /
+                                                             max(rp["n_precond_kernel"], 1))
+            del ws
+            log("multigrid %s %s: %.2f ms, %.1f it" % (tag, name, ms, its))
+        res["mg_speedup_fp64"] = res["line_fp64"]["ms_per_solve"] / res["mg_fp64"]["ms_per_solve"]
+        out[tag] = res
+        del P, b, x
     return out
 
 
@@ -421,7 +463,7 @@ def _working(values, frac=0.1):
     return [v for v in values if v >= frac * top]
 
 
-def summarize_rocprof(directory, kernel_filter="k_fused|k_init|k_fixup|k_finalize|copy|elementwise"):
+def summarize_rocprof(directory, kernel_filter="k_fused|k_init|k_fixup|k_finalize|k_mg|copy|elementwise"):
     """Condense rocprofv3 CSV output under `directory` into a few lines:
     the per-kernel stats table, per-dispatch durations from the kernel trace
     (all dispatches and the ones that did work), and counter means."""

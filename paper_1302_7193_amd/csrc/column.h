@@ -47,6 +47,7 @@ namespace {
 struct Col {
     int64_t idx;
     int64_t im, ip, jm, jp;  // neighbour columns, -1 across a Dirichlet face
+    int i, j;                // horizontal position
     int cls;                 // column class: 3 * (#Dirichlet x faces) + #Dirichlet y faces
     double alpha_t;          // alpha_T = sum of alpha_{T,T'}, Dirichlet faces twice
     double area;             // stretched grids: |T| and the face weights alpha_{T,T'}
@@ -54,17 +55,21 @@ struct Col {
     bool ok;
 };
 
-// Per-column geometry, recomputed from (i, j) (Sec. 4.2: |T| and
-// alpha_{T,T'} are evaluated once per column).  Dirichlet faces use the
-// half-cell distance, i.e. they add 2*alpha_{T,T'} to alpha_T.
+// Per-column geometry of column (i, j) (Sec. 4.2: |T| and alpha_{T,T'} are
+// evaluated once per column).  Dirichlet faces use the half-cell distance,
+// i.e. they add 2*alpha_{T,T'} to alpha_T.  ok = false: a column past the
+// grid (its lanes still take part in the shuffles; i = j = 0 stand in).
 template <bool G = false>
-__device__ __forceinline__ Col make_col(const Geom& g, int64_t c, const double* hgeo = nullptr)
+__device__ __forceinline__ Col make_col_ij(const Geom& g, int i, int j, bool ok,
+                                           const double* hgeo = nullptr)
 {
     Col o;
-    o.ok = c < g.nh;
-    const int64_t cc = o.ok ? c : 0;
+    o.ok = ok;
+    if (!ok) i = j = 0;
+    o.i = i;
+    o.j = j;
+    const int64_t cc = (int64_t)i * g.ny + j;
     o.idx = cc;
-    const int64_t i = cc / g.ny, j = cc - i * g.ny;
     int cx = 0, cy = 0;
     if (i > 0) o.im = cc - g.ny;
     else if (g.per_x) o.im = cc + (int64_t)(g.nx - 1) * g.ny;
@@ -95,6 +100,17 @@ __device__ __forceinline__ Col make_col(const Geom& g, int64_t c, const double* 
         o.alpha_t = (2 + cx) * g.ax + (2 + cy) * g.ay;
     }
     return o;
+}
+
+// The same for column index c (i*n_y + j); the grid has fewer than 2^31
+// columns, so the split into (i, j) is a 32-bit division.
+template <bool G = false>
+__device__ __forceinline__ Col make_col(const Geom& g, int64_t c, const double* hgeo = nullptr)
+{
+    const bool ok = c < g.nh;
+    const uint32_t cc = ok ? (uint32_t)c : 0u;
+    const uint32_t i = cc / (uint32_t)g.ny;
+    return make_col_ij<G>(g, (int)i, (int)(cc - i * (uint32_t)g.ny), ok, hgeo);
 }
 
 // Load / store the M levels k0..k0+M-1 of column `col`.  V: n_z is a
@@ -203,7 +219,8 @@ __device__ __forceinline__ VertCoef<T, M> load_vert(const Geom& g, const T* __re
 }
 
 // The same with the four horizontal neighbours' levels supplied by
-// nb(column, valid, out) (a column of -1 or valid = false must give zeros).
+// nb(direction, column, valid, out), direction 0..3 for the neighbours
+// i-1, i+1, j-1, j+1 (valid = false must give zeros).
 template <typename T, int M, bool G, typename NbLoad>
 __device__ __forceinline__ void stencil_nb(const Geom& g, const Col& c, int l, int L,
                                            const T (&xc)[M], const VertCoef<T, M>& vc,
@@ -215,10 +232,10 @@ __device__ __forceinline__ void stencil_nb(const Geom& g, const Col& c, int l, i
     if (l == L - 1) above = T(0);
 
     T xim[M], xip[M], xjm[M], xjp[M];
-    nb(c.im, c.ok && c.im >= 0, xim);
-    nb(c.ip, c.ok && c.ip >= 0, xip);
-    nb(c.jm, c.ok && c.jm >= 0, xjm);
-    nb(c.jp, c.ok && c.jp >= 0, xjp);
+    nb(0, c.im, c.ok && c.im >= 0, xim);
+    nb(1, c.ip, c.ok && c.ip >= 0, xip);
+    nb(2, c.jm, c.ok && c.jm >= 0, xjm);
+    nb(3, c.jp, c.ok && c.jp >= 0, xjp);
 
     const T at = T(c.alpha_t);
     if constexpr (G) {
@@ -253,7 +270,9 @@ __device__ __forceinline__ void stencil(const Geom& g, const Col& c, int l, int 
                                         const VertCoef<T, M>& vc, T (&y)[M])
 {
     stencil_nb<T, M, G>(g, c, l, L, xc, vc,
-                        [&](int64_t col, bool ok, T (&o)[M]) { ld<T, M, V>(x, col, ok, k0, g.nz, o); },
+                        [&](int, int64_t col, bool ok, T (&o)[M]) {
+                            ld<T, M, V>(x, col, ok, k0, g.nz, o);
+                        },
                         y);
 }
 

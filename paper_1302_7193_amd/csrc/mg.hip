@@ -103,16 +103,14 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(ColArgs a)
     int64_t t0, t1;
     block_tiles(gc, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const int64_t cc = tile_col(tile, p, L);
-        const bool ok = cc < gc.nh;
-        const int64_t I = ok ? cc / gc.ny : 0, J = ok ? cc - (cc / gc.ny) * gc.ny : 0;
+        const Col cp = make_col<false>(gc, tile_col(tile, p, L));   // the coarse column
         T acc[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[i] = T(0);
 #pragma unroll
         for (int child = 0; child < 4; ++child) {
-            const int64_t fcol = (2 * I + (child >> 1)) * gf.ny + (2 * J + (child & 1));
-            const Col c = make_col<G>(gf, ok ? fcol : gf.nh, a.hgeo2);
+            const Col c = make_col_ij<G>(gf, 2 * cp.i + (child >> 1), 2 * cp.j + (child & 1),
+                                         cp.ok, a.hgeo2);
             T zf[M], az[M], rf[M];
             ld<T, M, V>(z, c.idx, c.ok, p.k0, gf.nz, zf);
             stencil<T, M, V, G>(gf, c, p.l, L, p.k0, z, zf, vc, az);
@@ -120,15 +118,14 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(ColArgs a)
 #pragma unroll
             for (int i = 0; i < M; ++i) acc[i] += rf[i] - az[i];
         }
-        st<T, M, V>(rc_out, ok ? cc : 0, ok, p.k0, gc.nz, acc);
+        st<T, M, V>(rc_out, cp.idx, cp.ok, p.k0, gc.nz, acc);
     }
 }
 
-// Column of the coarse level a.g2 that contains fine column col of a.g.
-__device__ __forceinline__ int64_t parent_col(const Geom& g, const Geom& gc, int64_t col)
+// Coarse column (of level gc) containing fine column (i, j).
+__device__ __forceinline__ int64_t parent_ij(const Geom& gc, int i, int j)
 {
-    const int64_t i = col / g.ny, j = col - i * g.ny;
-    return (i >> 1) * gc.ny + (j >> 1);
+    return (int64_t)(i >> 1) * gc.ny + (j >> 1);
 }
 
 // Reads r = a.in0, the iterate t = a.io3 and (PROLONG) the coarse
@@ -153,24 +150,36 @@ __global__ __launch_bounds__(kBlock) void k_mg_post(ColArgs a)
     const Lane p = lane_pos<M>(L);
     const VertCoef<T, M> vc = load_vert<T, M, V>(g, static_cast<const T*>(a.vert), p.k0);
     const SolveCoef<T, M, G> sc = load_solve<T, M, V, G>(g, a, p.k0);
-    // the corrected iterate t + P z_c on any column of this level
-    auto load_z = [&](int64_t col, bool ok, T (&o)[M]) {
-        ld<T, M, V>(zin, col, ok, p.k0, g.nz, o);
-        if constexpr (PROLONG) {
-            T pc[M];
-            ld<T, M, V>(zc, ok ? parent_col(g, gc, col) : 0, ok, p.k0, g.nz, pc);
-#pragma unroll
-            for (int i = 0; i < M; ++i) o[i] += pc[i];
-        }
-    };
     double acc[2] = {0.0, 0.0};
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        // parents of the column and of its neighbours (periodic wrap as in
+        // make_col; absent neighbours are never loaded)
+        const int im = c.i > 0 ? c.i - 1 : g.nx - 1, ip = c.i < g.nx - 1 ? c.i + 1 : 0;
+        const int jm = c.j > 0 ? c.j - 1 : g.ny - 1, jp = c.j < g.ny - 1 ? c.j + 1 : 0;
+        // the corrected iterate t + P z_c on a column whose parent is pc
+        auto load_z = [&](int64_t col, bool ok, int64_t pc, T (&o)[M]) {
+            ld<T, M, V>(zin, col, ok, p.k0, g.nz, o);
+            if constexpr (PROLONG) {
+                T q[M];
+                ld<T, M, V>(zc, pc, ok, p.k0, g.nz, q);
+#pragma unroll
+                for (int i = 0; i < M; ++i) o[i] += q[i];
+            }
+        };
         T zo[M], az[M], rc[M], dz[M];
-        load_z(c.idx, c.ok, zo);
-        stencil_nb<T, M, G>(g, c, p.l, L, zo, vc, load_z, az);
+        load_z(c.idx, c.ok, parent_ij(gc, c.i, c.j), zo);
+        stencil_nb<T, M, G>(g, c, p.l, L, zo, vc,
+                            [&](int dir, int64_t col, bool ok, T (&o)[M]) {
+                                const int64_t pc = dir == 0   ? parent_ij(gc, im, c.j)
+                                                   : dir == 1 ? parent_ij(gc, ip, c.j)
+                                                   : dir == 2 ? parent_ij(gc, c.i, jm)
+                                                              : parent_ij(gc, c.i, jp);
+                                load_z(col, ok, pc, o);
+                            },
+                            az);
         ld<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
 #pragma unroll
         for (int i = 0; i < M; ++i) az[i] = rc[i] - az[i];
