@@ -555,6 +555,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mg-only", action="store_true",
+                    help="only FP64 multigrid-preconditioned solves of 512x512x128 Dirichlet "
+                         "with anisotropy 1e2 (for profiler runs of the V-cycle kernels)")
     ap.add_argument("--main-only", action="store_true",
                     help="only the timed loop (for profiler runs): no extras, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -589,6 +592,19 @@ def main():
     import paper_1302_7193_amd as pcg
     import synth_inputs as si
     torch.cuda.set_device(0)
+
+    if args.mg_only:
+        d = pcg.pcg_desc_from_ratio(512, 512, 128, 1.05, 1e2, pcg.PCG_BC_DIRICHLET)
+        P = pcg.Problem(d)
+        b = torch.from_numpy(si.rhs_uniform(512, 512, 128, 1)).cuda()
+        x = torch.empty_like(b)
+        o = pcg.pcg_default_opts(x0_zero=1, preconditioner=pcg.PCG_PRECOND_MG, graph_chunk=-1)
+        ws = pcg.workspace(P, o)
+        ms, its, st, r = timed_solves(pcg, torch, P, b, x, ws, o, args.steps)
+        print(json.dumps(dict(workload="512x512x128 Dirichlet anisotropy 1e2, FP64 MG-PCG",
+                              ms_per_solve=ms, iterations=its, status=pcg.STATUS_NAMES[st],
+                              levels=pcg.pcg_mg_levels(P))))
+        return
 
     log("main loop: %d warm-up + %d timed solves of 512x512x128" % (args.warmup, args.steps))
     m = run_main(pcg, si, torch, args.steps, args.warmup)
