@@ -91,7 +91,7 @@ typedef struct {
                              (direct launches); fills the *_kernel_* fields */
     int32_t true_residual;/* 1: also compute ||b - A x|| / ||r0|| in FP64    */
     int32_t x0_zero;      /* 1: start from x0 = 0 without reading x          */
-    int32_t preconditioner; /* PCG_PRECOND_LINE (default) or PCG_PRECOND_MG  */
+    int32_t preconditioner; /* PCG_PRECOND_LINE (default), _MG or _RBGS       */
     int32_t mg_levels;    /* MG: at most this many levels (0: every level the
                              grid allows; 1: line-Jacobi sweeps only)        */
 } pcg_solve_opts;
@@ -106,8 +106,14 @@ typedef struct {
  * sums them, the smoother is vertical-line Jacobi damped by 0.8 with one
  * pre- and one post-smoothing sweep (4 sweeps on the coarsest level).  The
  * V-cycle is symmetric positive definite, so the same CG applies.  MG runs
- * in the fused iteration only (fused = 1; FP64 or mixed precision). */
-enum { PCG_PRECOND_LINE = 0, PCG_PRECOND_MG = 1 };
+ * in the fused iteration only (fused = 1; FP64 or mixed precision).
+ * RBGS: the block-SOR alternative of Sec. 4.1 (the same column solves plus
+ * one more sparse product): symmetric block Gauss-Seidel over the vertical
+ * columns ordered red-black by horizontal position (i + j even: red), one
+ * forward and one backward sweep, relaxation factor 1.  Needs an even
+ * number of cells in every periodic direction (PCG_E_INVALID otherwise);
+ * fused iteration only. */
+enum { PCG_PRECOND_LINE = 0, PCG_PRECOND_MG = 1, PCG_PRECOND_RBGS = 2 };
 
 typedef struct {
     int32_t status;            /* pcg_status of the solve                    */
@@ -186,6 +192,11 @@ pcg_status pcg_precond(pcg_problem *p, int32_t dtype, const void *r, void *z, vo
  * bytes of device memory (16-byte aligned) for the coarse levels and one
  * fine-level vector.  pcg_mg_levels: the number of levels the grid allows.
  * Asynchronous on stream. */
+/* Block Gauss-Seidel preconditioner alone: z = M^{-1} r for the symmetric
+ * red-black block Gauss-Seidel M (see PCG_PRECOND_RBGS).  r and z: n values
+ * of dtype, distinct.  Asynchronous on stream. */
+pcg_status pcg_rbgs_precond(pcg_problem *p, int32_t dtype, const void *r, void *z, void *stream);
+
 int32_t pcg_mg_levels(const pcg_problem *p);
 size_t pcg_mg_bytes(const pcg_problem *p, int32_t dtype, int32_t mg_levels);
 pcg_status pcg_mg_precond(pcg_problem *p, int32_t dtype, const void *r, void *z,

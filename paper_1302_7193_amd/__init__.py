@@ -31,7 +31,7 @@ PCG_E_NOCONV, PCG_E_BREAKDOWN, PCG_E_AGAIN, PCG_E_CANCELLED = -4, -5, -6, -7
 PCG_BC_DIRICHLET, PCG_BC_PERIODIC = 0, 1
 PCG_F64, PCG_F32 = 0, 1
 PCG_PREC_FP64, PCG_PREC_MIXED = 0, 1
-PCG_PRECOND_LINE, PCG_PRECOND_MG = 0, 1
+PCG_PRECOND_LINE, PCG_PRECOND_MG, PCG_PRECOND_RBGS = 0, 1, 2
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_NOCONV",
                 -5: "E_BREAKDOWN", -6: "E_AGAIN", -7: "E_CANCELLED"}
 
@@ -105,6 +105,7 @@ _sig = {
     "pcg_apply": (_S, [_P, ctypes.c_int32, _P, _P, _P]),
     "pcg_precond": (_S, [_P, ctypes.c_int32, _P, _P, _P]),
     "pcg_mg_levels": (ctypes.c_int32, [_P]),
+    "pcg_rbgs_precond": (_S, [_P, ctypes.c_int32, _P, _P, _P]),
     "pcg_mg_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32]),
     "pcg_mg_precond": (_S, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "pcg_solve": (_S, [_P, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(pcg_solve_opts),
@@ -272,6 +273,13 @@ def pcg_precond(p: Problem, dtype: int, r, z, stream=None) -> int:
     td = _TORCH_DTYPE[dtype]
     return _check(_lib.pcg_precond(p.handle, dtype, _vec(r, p.n, td, "r"), _vec(z, p.n, td, "z"),
                                    _stream(stream)), "pcg_precond")
+
+
+def pcg_rbgs_precond(p: Problem, dtype: int, r, z, stream=None) -> int:
+    td = _TORCH_DTYPE[dtype]
+    return _check(_lib.pcg_rbgs_precond(p.handle, dtype, _vec(r, p.n, td, "r"),
+                                        _vec(z, p.n, td, "z"), _stream(stream)),
+                  "pcg_rbgs_precond")
 
 
 def pcg_mg_levels(p: Problem) -> int:

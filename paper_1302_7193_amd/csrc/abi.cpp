@@ -19,6 +19,8 @@ void build_tables(const pcg_problem_desc& d, Geom& g, std::vector<double>& vert,
                   std::vector<double>& lu);
 size_t workspace_bytes(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs);
 size_t mg_bytes(const pcg_problem* P, int dtype, int levels_req);
+pcg_status rbgs_precond(pcg_problem* P, int dtype, const void* r, void* z, hipStream_t s);
+bool rbgs_supported(const pcg_problem* P);
 pcg_status mg_precond(pcg_problem* P, int dtype, const void* r, void* z, int levels_req,
                       void* workspace, size_t ws_bytes, hipStream_t s);
 int64_t blocks_per_rhs(const pcg_problem* P, int dtype);
@@ -105,13 +107,15 @@ pcg_status check_opts(const pcg_solve_opts& o)
         set_error("graph_chunk must be -1, 0 or positive");
         return PCG_E_INVALID;
     }
-    if ((o.preconditioner != PCG_PRECOND_LINE && o.preconditioner != PCG_PRECOND_MG) ||
+    if ((o.preconditioner != PCG_PRECOND_LINE && o.preconditioner != PCG_PRECOND_MG &&
+         o.preconditioner != PCG_PRECOND_RBGS) ||
         o.mg_levels < 0) {
-        set_error("preconditioner must be PCG_PRECOND_LINE or PCG_PRECOND_MG, mg_levels >= 0");
+        set_error("preconditioner must be PCG_PRECOND_LINE, _MG or _RBGS, mg_levels >= 0");
         return PCG_E_INVALID;
     }
-    if (o.preconditioner == PCG_PRECOND_MG && !o.fused) {
-        set_error("the multigrid preconditioner runs in the fused iteration only");
+    if (o.preconditioner != PCG_PRECOND_LINE && !o.fused) {
+        set_error("the multigrid and block Gauss-Seidel preconditioners run in the fused "
+                  "iteration only");
         return PCG_E_INVALID;
     }
     return PCG_OK;
@@ -425,6 +429,26 @@ pcg_status pcg_precond(pcg_problem* P, int32_t dtype, const void* r, void* z, vo
 }
 
 int32_t pcg_mg_levels(const pcg_problem* P) { return P ? 1 + (int32_t)P->mg.size() : 0; }
+
+pcg_status pcg_rbgs_precond(pcg_problem* P, int32_t dtype, const void* r, void* z, void* stream)
+{
+    if (!P || !r || !z || !valid_dtype(dtype)) {
+        set_error("pcg_rbgs_precond: NULL argument or bad dtype");
+        return PCG_E_INVALID;
+    }
+    if (r == z) {
+        set_error("pcg_rbgs_precond: r and z must not overlap");
+        return PCG_E_INVALID;
+    }
+    if (!rbgs_supported(P)) {
+        set_error("pcg_rbgs_precond: red-black ordering needs an even size in periodic directions");
+        return PCG_E_INVALID;
+    }
+    if (check_aligned({r, z}, "pcg_rbgs_precond") != PCG_OK) return PCG_E_INVALID;
+    return on_device(P->device, [&]() -> pcg_status {
+        return rbgs_precond(P, dtype, r, z, static_cast<hipStream_t>(stream));
+    });
+}
 
 size_t pcg_mg_bytes(const pcg_problem* P, int32_t dtype, int32_t mg_levels)
 {

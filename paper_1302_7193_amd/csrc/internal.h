@@ -120,6 +120,12 @@ enum class Kind : int {
     MgPostFinal,  // the same, then R, kappa; exit test; beta  (ends kernel B's work)
     MgSmooth,     // z += omega M^{-1}(r - A z)               (coarsest level)
     MgSmoothFinal,// the same, then R, kappa; exit test; beta  (single-level hierarchy)
+    // symmetric red-black block Gauss-Seidel (rbgs.hip):
+    RbFirst,      // red columns: z = D^{-1} r
+    RbFirstFused, // the same, first: r -= alpha q on every column, as kernel B does
+    RbBlack,      // black columns: z = D^{-1}(r - A_BR z)
+    RbRed,        // red columns:   z = D^{-1}(r - A_RB z)
+    RbRedFinal,   // the same, then R, kappa over all columns; exit test; beta
 };
 
 // One argument block serves every column kernel; unused pointers are null.
@@ -156,9 +162,12 @@ struct ColArgs {
     double omega;
 };
 
-// Multigrid kernels (mg.hip): kernel for a Kind >= MgPre, or null.
+// Multigrid kernels (mg.hip): kernel for a Kind in MgPre..MgSmoothFinal, or
+// null; block Gauss-Seidel kernels (rbgs.hip): Kind >= RbFirst.
 template <typename T>
 const void* mg_func(Kind kind, const ColArgs& a);
+template <typename T>
+const void* rb_func(Kind kind, const ColArgs& a);
 
 // Host launchers (kernels.hip): T = double or float.  column_launches
 // returns the kernel (and, for mode-1 reductions, its finalize kernel) with

@@ -454,7 +454,7 @@ bool has_finalize(Kind k)
 {
     return k == Kind::FusedPrec || k == Kind::FusedApply || k == Kind::Fixup ||
            k == Kind::TrueResidual || k == Kind::Residual64 || k == Kind::MgPostFinal ||
-           k == Kind::MgSmoothFinal;
+           k == Kind::MgSmoothFinal || k == Kind::RbRedFinal;
 }
 
 const void* finalize_func(Kind kind)
@@ -462,7 +462,8 @@ const void* finalize_func(Kind kind)
     switch (kind) {
     case Kind::FusedPrec:
     case Kind::MgPostFinal:
-    case Kind::MgSmoothFinal: return reinterpret_cast<const void*>(&k_finalize<Kind::FusedPrec>);
+    case Kind::MgSmoothFinal:
+    case Kind::RbRedFinal: return reinterpret_cast<const void*>(&k_finalize<Kind::FusedPrec>);
     case Kind::FusedApply: return reinterpret_cast<const void*>(&k_finalize<Kind::FusedApply>);
     case Kind::Fixup: return reinterpret_cast<const void*>(&k_finalize<Kind::Fixup>);
     case Kind::TrueResidual: return reinterpret_cast<const void*>(&k_finalize<Kind::TrueResidual>);
@@ -525,6 +526,7 @@ constexpr int64_t kStreamBytes = int64_t(64) << 20;
 template <typename T>
 const void* main_func(Kind kind, const ColArgs& a, int64_t batch)
 {
+    if (kind >= Kind::RbFirst) return rb_func<T>(kind, a);
     if (kind >= Kind::MgPre) return mg_func<T>(kind, a);
     const int M = a.L > 0 ? (a.g.nz + a.L - 1) / a.L : 0;
     int Mp = 1;
@@ -547,7 +549,7 @@ static bool line_solve_kind(Kind k)
 {
     return k == Kind::FusedPrec || k == Kind::Precond || k == Kind::MgPre ||
            k == Kind::MgPreFused || k == Kind::MgPost || k == Kind::MgPostFinal ||
-           k == Kind::MgSmooth || k == Kind::MgSmoothFinal;
+           k == Kind::MgSmooth || k == Kind::MgSmoothFinal || k >= Kind::RbFirst;
 }
 
 template <typename T>

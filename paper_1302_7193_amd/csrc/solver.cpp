@@ -341,7 +341,12 @@ pcg_status b_phase(const pcg_problem* P, int dtype, const ColArgs& a, int64_t nr
                    const pcg_solve_opts& o, char* ws, const Layout& w, Phase& ph)
 {
     bool ok;
-    if (o.preconditioner != PCG_PRECOND_MG) {
+    if (o.preconditioner == PCG_PRECOND_RBGS) {
+        ColArgs x = a;
+        x.in0 = a.io1;   // the later half-sweeps read r
+        ok = add_kind<T>(ph, Kind::RbFirstFused, a, nrhs) && add_kind<T>(ph, Kind::RbBlack, x, nrhs) &&
+             add_kind<T>(ph, Kind::RbRedFinal, x, nrhs);
+    } else if (o.preconditioner != PCG_PRECOND_MG) {
         ok = add_kind<T>(ph, Kind::FusedPrec, a, nrhs);
     } else {
         MgVecs v{};
@@ -463,7 +468,7 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a,
 {
     Phase bph;
     if (b_phase<T>(P, dtype, a, nrhs, o, ws, w, bph) != PCG_OK) return PCG_E_DEVICE;
-    const int bkind = o.preconditioner == PCG_PRECOND_MG ? 100 + w.mg_levels : 0;
+    const int bkind = o.preconditioner == PCG_PRECOND_MG ? 100 + w.mg_levels : o.preconditioner;
     const bool profile = o.profile != 0 && nrhs == 1;
     int K = o.graph_chunk > 0 ? o.graph_chunk : P->last_iters[prec_slot];
     if (K <= 0) K = 8;
@@ -1055,6 +1060,36 @@ pcg_status mg_precond(pcg_problem* P, int dtype, const void* r, void* z, int lev
     return issue_phase(ph, s, count);
 }
 
+bool rbgs_supported(const pcg_problem* P)
+{
+    return !((P->geom.per_x && P->geom.nx % 2) || (P->geom.per_y && P->geom.ny % 2));
+}
+
+// Block Gauss-Seidel preconditioner alone: z = M^{-1} r.
+pcg_status rbgs_precond(pcg_problem* P, int dtype, const void* r, void* z, hipStream_t s)
+{
+    TuneScope ts(P, 1);
+    ColArgs a{};
+    a.g = P->geom;
+    set_launch(a, P, dtype);
+    set_tables(a, P, dtype);
+    a.in0 = r;
+    a.io2 = z;
+    Phase ph;
+    const bool ok =
+        dtype == PCG_F64
+            ? add_kind<double>(ph, Kind::RbFirst, a, 1) && add_kind<double>(ph, Kind::RbBlack, a, 1) &&
+                  add_kind<double>(ph, Kind::RbRed, a, 1)
+            : add_kind<float>(ph, Kind::RbFirst, a, 1) && add_kind<float>(ph, Kind::RbBlack, a, 1) &&
+                  add_kind<float>(ph, Kind::RbRed, a, 1);
+    if (!ok) {
+        set_error("no kernel for this shape (internal)");
+        return PCG_E_DEVICE;
+    }
+    int count = 0;
+    return issue_phase(ph, s, count);
+}
+
 // Workspace of one served request, enough for any tuning of its shape (and
 // the coarse levels of the multigrid preconditioner when it is chosen).
 size_t request_bytes(const pcg_problem_desc& d, const pcg_solve_opts& o)
@@ -1088,6 +1123,11 @@ pcg_status solve(pcg_problem* P, const double* b, double* x, void* workspace, si
                  const pcg_solve_opts& o, int64_t nrhs, pcg_result* res, hipStream_t s)
 {
     TuneScope ts(P, nrhs);
+    if (o.preconditioner == PCG_PRECOND_RBGS && !rbgs_supported(P)) {
+        set_error("block Gauss-Seidel: red-black ordering needs an even size in periodic "
+                  "directions");
+        return PCG_E_INVALID;
+    }
     const Layout w = plan(P, o, nrhs);
     if (ws_bytes < w.total) {
         std::ostringstream m;

@@ -1,0 +1,146 @@
+"""Symmetric red-black block Gauss-Seidel preconditioner on the GPU, through
+the C ABI, against the oracle (oracle/rbgs.py): the preconditioner alone,
+FP64 PCG iterates at equal iteration counts (graph and direct launches),
+convergence, mixed precision, batched solves, and the rejection of odd
+periodic sizes."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import oracle.mg as omg  # noqa: E402
+import oracle.rbgs as orb  # noqa: E402
+import paper_1302_7193_amd as pcg  # noqa: E402
+import synth_inputs as si  # noqa: E402
+
+RB = pcg.PCG_PRECOND_RBGS
+
+
+def desc(nx, ny, nz, g2, bcx=0, bcy=0, q=1.05):
+    d = pcg.pcg_desc_from_ratio(nx, ny, nz, q, g2, 0)
+    d.bc_x, d.bc_y = bcx, bcy
+    return d
+
+
+CASES = {
+    "32x24x32-dir-1e2": lambda: (desc(32, 24, 32, 1e2), None, None),
+    "13x7x33-dir-ragged": lambda: (desc(13, 7, 33, 1e3), None, None),
+    "16x10x17-per-even": lambda: (desc(16, 10, 17, 1e4, 1, 1), None, None),
+    "9x12x64-mixedbc": lambda: (desc(9, 12, 64, 1e2, 0, 1, q=1.1), None, None),
+    "1x9x8-one-row": lambda: (desc(1, 9, 8, 1e3), None, None),
+    "20x16x128-stretched": lambda: (desc(20, 16, 128, 1e2), si.widths_sine(20),
+                                    si.widths_random(16, 5)),
+}
+
+
+def grid_of(d, xw, yw):
+    return oracle.Grid(d.nx, d.ny, d.nz, d.dx, d.dy, d.height, d.grading, d.k_h, d.k_v,
+                       d.bc_x == 1, d.bc_y == 1, None if xw is None else tuple(xw),
+                       None if yw is None else tuple(yw))
+
+
+def problem(d, xw, yw):
+    return pcg.Problem(d, xw, yw) if xw is not None else pcg.Problem(d)
+
+
+def cuda(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dtype", [pcg.PCG_F64, pcg.PCG_F32])
+def test_preconditioner_matches_oracle(name, dtype):
+    d, xw, yw = CASES[name]()
+    print("rbgs", name, dtype, flush=True)
+    p = problem(d, xw, yw)
+    tdt = torch.float64 if dtype == pcg.PCG_F64 else torch.float32
+    for L in (None, 1, 4, 16, 64):
+        if L is not None:
+            if 16 * L < d.nz:
+                continue
+            pcg.pcg_set_tuning(p, dtype, lanes_per_column=L, block_cap=7, reduction=1)
+        r = cuda(si.uniform_pm1(60, p.n), tdt)
+        z = torch.full_like(r, float("nan"))
+        pcg.pcg_rbgs_precond(p, dtype, r, z)
+        torch.cuda.synchronize()
+        want = orb.RBGS(grid_of(d, xw, yw)).apply(r.double().cpu().numpy())
+        err = np.linalg.norm(z.double().cpu().numpy() - want) / np.linalg.norm(want)
+        assert err <= (1e-11 if dtype == pcg.PCG_F64 else 1e-4), (L, err)
+
+
+def gpu_solve(p, b, **kw):
+    o = pcg.pcg_default_opts(preconditioner=RB, **kw)
+    bt = cuda(b)
+    x = torch.zeros_like(bt)
+    st, res = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), st, res
+
+
+@pytest.mark.parametrize("name", ["32x24x32-dir-1e2", "13x7x33-dir-ragged", "16x10x17-per-even",
+                                  "9x12x64-mixedbc", "20x16x128-stretched"])
+@pytest.mark.parametrize("gc", [3, 0])
+def test_fp64_pcg_equal_iterations(name, gc):
+    d, xw, yw = CASES[name]()
+    print("rbgs solve", name, gc, flush=True)
+    g = grid_of(d, xw, yw)
+    A = oracle.assemble(g)
+    b = si.rhs_uniform(d.nx, d.ny, d.nz, 3)
+    ref = omg.pcg(A, orb.RBGS(g, A).apply, b, rtol=1e-8)
+    k = ref["iterations"]
+    p = problem(d, xw, yw)
+    x, st, res = gpu_solve(p, b, rtol=0.0, max_iter=k, graph_chunk=gc)
+    assert res["iterations"] == k
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+    assert err <= 1e-10, err
+    x, st, res = gpu_solve(p, b, rtol=1e-8, graph_chunk=gc)
+    assert st == pcg.PCG_OK and abs(res["iterations"] - k) <= 1
+    assert oracle.residual_norm(A, b, x) / np.linalg.norm(b) < 1.05e-8
+
+
+def test_mixed_precision_and_fewer_iterations_than_line():
+    d, _, _ = CASES["32x24x32-dir-1e2"]()
+    p = pcg.Problem(d)
+    b = si.rhs_smooth_noise(d.nx, d.ny, d.nz, 2)
+    x, st, res = gpu_solve(p, b, precision=pcg.PCG_PREC_MIXED)
+    assert st == pcg.PCG_OK
+    A = oracle.assemble(grid_of(d, None, None))
+    assert oracle.residual_norm(A, b, x) / np.linalg.norm(b) < 1e-8
+    _, _, r_rb = gpu_solve(p, b)
+    o = pcg.pcg_default_opts()
+    bt = cuda(b)
+    xl = torch.zeros_like(bt)
+    _, r_line = pcg.pcg_solve(p, bt, xl, pcg.workspace(p, o), o)
+    assert r_rb["iterations"] <= 0.6 * r_line["iterations"], (r_rb["iterations"], r_line["iterations"])
+
+
+def test_batched_equals_single_and_profiled():
+    d, _, _ = CASES["13x7x33-dir-ragged"]()
+    p = pcg.Problem(d)
+    nrhs = 3
+    B = np.stack([si.rhs_uniform(d.nx, d.ny, d.nz, 300 + s) for s in range(nrhs)])
+    o = pcg.pcg_default_opts(preconditioner=RB)
+    bt = cuda(B.ravel())
+    x = torch.zeros_like(bt)
+    st, res = pcg.pcg_solve_batched(p, nrhs, bt, x, pcg.workspace(p, o, nrhs), o)
+    X = x.cpu().numpy().reshape(nrhs, p.n)
+    for s in range(nrhs):
+        for kw in (dict(), dict(profile=1)):
+            xs, sts, rs = gpu_solve(p, B[s], **kw)
+            assert sts == pcg.PCG_OK and rs["iterations"] == res[s]["iterations"]
+            np.testing.assert_array_equal(xs, X[s])
+
+
+def test_odd_periodic_rejected():
+    p = pcg.Problem(desc(9, 8, 8, 1e3, 1, 0))
+    b = cuda(si.rhs_uniform(9, 8, 8, 1))
+    with pytest.raises(pcg.PCGError):
+        pcg.pcg_rbgs_precond(p, pcg.PCG_F64, b, torch.empty_like(b))
+    o = pcg.pcg_default_opts(preconditioner=RB)
+    with pytest.raises(pcg.PCGError):
+        pcg.pcg_solve(p, b, torch.zeros_like(b), pcg.workspace(p, o), o)
