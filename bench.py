@@ -230,7 +230,7 @@ def extras(pcg, si, torch, main):
     del P3, b3, x3
 
     out["stretched_512x512x128_fp64"] = stretched(pcg, si, torch, out["fused_fp64_graph"])
-    out["multigrid_512x512x128"] = multigrid(pcg, si, torch)
+    out["preconditioners_512x512x128"] = multigrid(pcg, si, torch)
     out["batched_256x256x64x64"] = batched(pcg, si, torch)
     out["serving_512_requests"] = serving(pcg, si, torch)
 
@@ -275,7 +275,8 @@ def stretched(pcg, si, torch, uniform):
 
 
 def multigrid(pcg, si, torch):
-    """Tensor-product multigrid preconditioner vs vertical line relaxation on
+    """Tensor-product multigrid and red-black block Gauss-Seidel
+    preconditioners vs vertical line relaxation on
     512 x 512 x 128 Dirichlet with weak anisotropy (1e2: line relaxation
     alone needs many iterations) and on the main workload's operator
     (anisotropy 1e5, periodic): FP64 fused solves on the graph path, mixed
@@ -290,6 +291,7 @@ def multigrid(pcg, si, torch):
         x = torch.empty_like(b)
         res = dict(levels=pcg.pcg_mg_levels(P))
         for name, kw in (("line_fp64", dict()), ("mg_fp64", dict(preconditioner=pcg.PCG_PRECOND_MG)),
+                         ("rbgs_fp64", dict(preconditioner=pcg.PCG_PRECOND_RBGS)),
                          ("line_mixed", dict(precision=pcg.PCG_PREC_MIXED)),
                          ("mg_mixed", dict(precision=pcg.PCG_PREC_MIXED,
                                            preconditioner=pcg.PCG_PRECOND_MG))):
@@ -310,6 +312,8 @@ def multigrid(pcg, si, torch):
             del ws
             log("multigrid %s %s: %.2f ms, %.1f it" % (tag, name, ms, its))
         res["mg_speedup_fp64"] = res["line_fp64"]["ms_per_solve"] / res["mg_fp64"]["ms_per_solve"]
+        res["rbgs_speedup_fp64"] = (res["line_fp64"]["ms_per_solve"] /
+                                    res["rbgs_fp64"]["ms_per_solve"])
         out[tag] = res
         del P, b, x
     return out
