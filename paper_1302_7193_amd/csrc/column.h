@@ -504,5 +504,13 @@ __device__ __forceinline__ int64_t tile_col(int64_t tile, const Lane& p, int L)
     return (tile * (kBlock / kWave) + p.wave) * (kWave / L) + p.seg;
 }
 
+// The same for one column per wavefront (L = 64): the index is the same in
+// every lane, so it is made a scalar (and with it the column's geometry and
+// the base addresses of its loads and stores).  Columns number < 2^31.
+__device__ __forceinline__ int64_t wave_col(int64_t tile, const Lane& p)
+{
+    return __builtin_amdgcn_readfirstlane((int)(tile * (kBlock / kWave) + p.wave));
+}
+
 }  // namespace
 }  // namespace pcg

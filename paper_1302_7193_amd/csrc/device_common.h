@@ -3,6 +3,8 @@
 // of the conjugate gradient iteration.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace pcg {
@@ -75,18 +77,25 @@ __device__ __forceinline__ void sum_partials(const double* part, int64_t nblk, d
             return COHERENT ? __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *q;
         };
         int64_t b = v;
-        // eight loads in flight, added in slot order
-        for (; b + 7 * kFinalThreads < nblk; b += 8 * kFinalThreads) {
-            double t[8][NV];
+        // U loads in flight, added in slot order: the latency of reading
+        // partials written by other XCDs sets the finalize launch's time (32
+        // in flight); inside a main kernel (COHERENT) 8 keep its registers low
+        auto chunk = [&](auto U_) {
+            constexpr int U = decltype(U_)::value;
+            for (; b + (U - 1) * (int64_t)kFinalThreads < nblk; b += U * (int64_t)kFinalThreads) {
+                double t[U][NV];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int i = 0; i < NV; ++i) t[u][i] = load(b + (int64_t)u * kFinalThreads, i);
+                    for (int i = 0; i < NV; ++i) t[u][i] = load(b + (int64_t)u * kFinalThreads, i);
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int i = 0; i < NV; ++i) acc[r][i] += t[u][i];
-        }
+                    for (int i = 0; i < NV; ++i) acc[r][i] += t[u][i];
+            }
+        };
+        if constexpr (!COHERENT) chunk(std::integral_constant<int, 32>{});
+        chunk(std::integral_constant<int, 8>{});
         for (; b < nblk; b += kFinalThreads) {
 #pragma unroll
             for (int i = 0; i < NV; ++i) acc[r][i] += load(b, i);

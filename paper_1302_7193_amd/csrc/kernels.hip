@@ -112,12 +112,13 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
 // FIRST (no iteration done yet): alpha = 0 and q is unset, so q is not read;
 // with a zero start r is taken from b (no start-up kernel), and not stored
 // when b is r itself.
-template <typename T, int M, bool V, bool FIRST, bool G, bool NT>
+// W: one column per wavefront (L = 64, column index scalar).
+template <typename T, int M, bool V, bool FIRST, bool G, bool NT, bool W>
 __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s, int64_t rhs,
                                                 int64_t blk, double (&acc)[2])
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t off = rhs * g.n;
     const bool from_b = FIRST && s->zero_start;
     const T* src = static_cast<const T*>(from_b ? a.in1 : a.io1) + off;
@@ -132,7 +133,7 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         T rc[M], zc[M];
         ld<T, M, V, NT>(src, c.idx, c.ok, p.k0, g.nz, rc);
         if (!FIRST) {
@@ -151,7 +152,7 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
     }
 }
 
-template <typename T, int M, bool V, bool G, bool NT>
+template <typename T, int M, bool V, bool G, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
 {
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
@@ -159,8 +160,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[2] = {0.0, 0.0};
-    if (s->iter == 0) fused_prec_body<T, M, V, true, G, NT>(a, s, rhs, blk, acc);
-    else fused_prec_body<T, M, V, false, G, NT>(a, s, rhs, blk, acc);
+    if (s->iter == 0) fused_prec_body<T, M, V, true, G, NT, W>(a, s, rhs, blk, acc);
+    else fused_prec_body<T, M, V, false, G, NT, W>(a, s, rhs, blk, acc);
     double tot[2];
     if (publish<2>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
                    &s->ticket, a.red_mode, tot)) {
@@ -172,12 +173,12 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
 // q = A z + beta q; sigma = <p,q> (FP64); scalar step: alpha.
 // FIRST: alpha = 0 and p = q = 0, so p = z, q = A z, and u keeps x0 (written
 // as zero for a zero start); u, p and q are not read.
-template <typename T, int M, bool V, bool FIRST, bool G, bool NT>
+template <typename T, int M, bool V, bool FIRST, bool G, bool NT, bool W>
 __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* s, int64_t rhs,
                                                  int64_t blk, double (&acc)[1])
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t off = rhs * g.n;
     T* u = static_cast<T*>(a.io0) + off;
     const T* z = static_cast<const T*>(a.io2) + off;
@@ -191,7 +192,7 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         T zc[M], az[M], pc[M], qc[M];
         ld<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
         stencil<T, M, V, G>(g, c, p.l, L, p.k0, z, zc, vc, az);
@@ -227,7 +228,7 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
     }
 }
 
-template <typename T, int M, bool V, bool G, bool NT>
+template <typename T, int M, bool V, bool G, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
 {
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
@@ -235,8 +236,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[1] = {0.0};
-    if (s->iter == 0) fused_apply_body<T, M, V, true, G, NT>(a, s, rhs, blk, acc);
-    else fused_apply_body<T, M, V, false, G, NT>(a, s, rhs, blk, acc);
+    if (s->iter == 0) fused_apply_body<T, M, V, true, G, NT, W>(a, s, rhs, blk, acc);
+    else fused_apply_body<T, M, V, false, G, NT, W>(a, s, rhs, blk, acc);
     double tot[1];
     if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
                    &s->ticket, a.red_mode, tot)) {
@@ -472,7 +473,7 @@ const void* finalize_func(Kind kind)
     }
 }
 
-template <typename T, int M, bool V, bool G, bool NT>
+template <typename T, int M, bool V, bool G, bool NT, bool W>
 const void* main_func_m(Kind kind)
 {
     switch (kind) {
@@ -480,8 +481,8 @@ const void* main_func_m(Kind kind)
     case Kind::Precond: return reinterpret_cast<const void*>(&k_precond<T, M, V, G>);
     case Kind::InitFull: return reinterpret_cast<const void*>(&k_init<T, M, V, false, G>);
     case Kind::InitZero: return reinterpret_cast<const void*>(&k_init<T, M, V, true, false>);
-    case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G, NT>);
-    case Kind::FusedApply: return reinterpret_cast<const void*>(&k_fused_apply<T, M, V, G, NT>);
+    case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G, NT, W>);
+    case Kind::FusedApply: return reinterpret_cast<const void*>(&k_fused_apply<T, M, V, G, NT, W>);
     case Kind::Fixup: return reinterpret_cast<const void*>(&k_fixup<T, M, V, NT>);
     case Kind::TrueResidual:
         if constexpr (sizeof(T) == 8)
@@ -498,9 +499,12 @@ const void* main_func_m(Kind kind)
 }
 
 template <typename T, int M, bool V, bool G>
-const void* main_func_n(Kind kind, bool nt)
+const void* main_func_n(Kind kind, bool nt, bool w)
 {
-    return nt ? main_func_m<T, M, V, G, true>(kind) : main_func_m<T, M, V, G, false>(kind);
+    // one column per wavefront: only the two fused kernels have that variant
+    if (w && (kind == Kind::FusedApply || kind == Kind::FusedPrec))
+        return nt ? main_func_m<T, M, V, G, true, true>(kind) : main_func_m<T, M, V, G, false, true>(kind);
+    return nt ? main_func_m<T, M, V, G, true, false>(kind) : main_func_m<T, M, V, G, false, false>(kind);
 }
 
 template <typename T, int M>
@@ -509,9 +513,10 @@ const void* main_func_v(Kind kind, const ColArgs& a, bool nt)
     // vector path: whole chunks valid and 16-byte aligned rows and chunks
     const bool vec = (a.g.nz % M == 0) && ((M * sizeof(T)) % 16 == 0) &&
                      ((a.g.nz * sizeof(T)) % 16 == 0);
+    const bool w = a.L == kWave;
     if (a.hgeo)
-        return vec ? main_func_n<T, M, true, true>(kind, nt) : main_func_n<T, M, false, true>(kind, nt);
-    return vec ? main_func_n<T, M, true, false>(kind, nt) : main_func_n<T, M, false, false>(kind, nt);
+        return vec ? main_func_n<T, M, true, true>(kind, nt, w) : main_func_n<T, M, false, true>(kind, nt, w);
+    return vec ? main_func_n<T, M, true, false>(kind, nt, w) : main_func_n<T, M, false, false>(kind, nt, w);
 }
 
 // Vectors of the fused iteration larger than this are streamed with the
