@@ -233,6 +233,8 @@ def extras(pcg, si, torch, main):
     out["preconditioners_512x512x128"] = multigrid(pcg, si, torch)
     out["batched_256x256x64x64"] = batched(pcg, si, torch)
     out["serving_512_requests"] = serving(pcg, si, torch)
+    out["serving_512_requests_auto_preconditioner"] = serving(
+        pcg, si, torch, preconditioner=pcg.PCG_PRECOND_AUTO)
 
     # plain copy kernel: attainable HBM bandwidth
     a = torch.empty(1 << 29, dtype=torch.float64, device="cuda")   # 4 GiB
@@ -358,7 +360,7 @@ def batched(pcg, si, torch, nrhs=64):
     return out
 
 
-def serving(pcg, si, torch, n_requests=512, max_active=4):
+def serving(pcg, si, torch, n_requests=512, max_active=4, preconditioner=0):
     """Poisson arrivals (mean 200/s, seed 5) of mixed-precision solves with
     n x n x n_z grids, n in {64,128,256,512}, n_z in {32,64,128}, anisotropy
     log-uniform in [1e2,1e5], U[-1,1) right-hand sides (seed 1000 + id),
@@ -366,7 +368,7 @@ def serving(pcg, si, torch, n_requests=512, max_active=4):
     once to warm the per-shape state, then timed."""
     import numpy as np
     trace = si.serving_trace(n_requests, 200.0, seed=5)
-    opts = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED)
+    opts = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED, preconditioner=preconditioner)
     descs, bs, xs = [], [], []
     for r in trace:
         descs.append(pcg.pcg_desc_from_ratio(r["nx"], r["ny"], r["nz"], 1.05, r["gamma2"],

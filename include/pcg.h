@@ -112,8 +112,16 @@ typedef struct {
  * columns ordered red-black by horizontal position (i + j even: red), one
  * forward and one backward sweep, relaxation factor 1.  Needs an even
  * number of cells in every periodic direction (PCG_E_INVALID otherwise);
- * fused iteration only. */
-enum { PCG_PRECOND_LINE = 0, PCG_PRECOND_MG = 1, PCG_PRECOND_RBGS = 2 };
+ * fused iteration only.
+ *
+ * AUTO chooses by the anisotropy ratio gamma^2 = (K_v / (H/n_z)^2) /
+ * (K_h / dx^2) of the descriptor (dx: desc->dx; for stretched grids the
+ * mean x width) and the size, from time-to-solution measured on MI355X:
+ * MG when gamma^2 <= 300 and n >= 2^22 unknowns (its fixed cost per level
+ * pays off only on large grids), else RBGS when gamma^2 <= 1e4 and
+ * red-black ordering applies, else LINE; the unfused iteration always
+ * takes LINE.  pcg_result.preconditioner reports the choice. */
+enum { PCG_PRECOND_LINE = 0, PCG_PRECOND_MG = 1, PCG_PRECOND_RBGS = 2, PCG_PRECOND_AUTO = 3 };
 
 typedef struct {
     int32_t status;            /* pcg_status of the solve                    */
@@ -129,6 +137,8 @@ typedef struct {
     double ms_precond_kernel;  /* profile: summed time of fused precond kernel */
     int32_t n_apply_kernel;    /* profile: launches timed                    */
     int32_t n_precond_kernel;
+    int32_t preconditioner;    /* the preconditioner used (AUTO resolved)    */
+    int32_t reserved;
 } pcg_result;
 
 typedef struct pcg_problem pcg_problem; /* opaque */

@@ -31,7 +31,7 @@ PCG_E_NOCONV, PCG_E_BREAKDOWN, PCG_E_AGAIN, PCG_E_CANCELLED = -4, -5, -6, -7
 PCG_BC_DIRICHLET, PCG_BC_PERIODIC = 0, 1
 PCG_F64, PCG_F32 = 0, 1
 PCG_PREC_FP64, PCG_PREC_MIXED = 0, 1
-PCG_PRECOND_LINE, PCG_PRECOND_MG, PCG_PRECOND_RBGS = 0, 1, 2
+PCG_PRECOND_LINE, PCG_PRECOND_MG, PCG_PRECOND_RBGS, PCG_PRECOND_AUTO = 0, 1, 2, 3
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_NOCONV",
                 -5: "E_BREAKDOWN", -6: "E_AGAIN", -7: "E_CANCELLED"}
 
@@ -83,7 +83,8 @@ class pcg_result(ctypes.Structure):
                 ("rel_res_recursive", ctypes.c_double), ("rel_res_true", ctypes.c_double),
                 ("r0_norm", ctypes.c_double), ("elapsed_ms", ctypes.c_double),
                 ("ms_apply_kernel", ctypes.c_double), ("ms_precond_kernel", ctypes.c_double),
-                ("n_apply_kernel", ctypes.c_int32), ("n_precond_kernel", ctypes.c_int32)]
+                ("n_apply_kernel", ctypes.c_int32), ("n_precond_kernel", ctypes.c_int32),
+                ("preconditioner", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -107,13 +107,12 @@ pcg_status check_opts(const pcg_solve_opts& o)
         set_error("graph_chunk must be -1, 0 or positive");
         return PCG_E_INVALID;
     }
-    if ((o.preconditioner != PCG_PRECOND_LINE && o.preconditioner != PCG_PRECOND_MG &&
-         o.preconditioner != PCG_PRECOND_RBGS) ||
+    if (o.preconditioner < PCG_PRECOND_LINE || o.preconditioner > PCG_PRECOND_AUTO ||
         o.mg_levels < 0) {
-        set_error("preconditioner must be PCG_PRECOND_LINE, _MG or _RBGS, mg_levels >= 0");
+        set_error("preconditioner must be PCG_PRECOND_LINE, _MG, _RBGS or _AUTO, mg_levels >= 0");
         return PCG_E_INVALID;
     }
-    if (o.preconditioner != PCG_PRECOND_LINE && !o.fused) {
+    if (o.preconditioner != PCG_PRECOND_LINE && o.preconditioner != PCG_PRECOND_AUTO && !o.fused) {
         set_error("the multigrid and block Gauss-Seidel preconditioners run in the fused "
                   "iteration only");
         return PCG_E_INVALID;

@@ -89,6 +89,38 @@ Layout plan_n(int64_t cells, const pcg_solve_opts& o, int64_t nrhs, int64_t slot
 
 }  // namespace
 
+// The preconditioner PCG_PRECOND_AUTO stands for (see include/pcg.h), from
+// the descriptor and a representative x width.
+int resolve_precond(const pcg_problem_desc& d, double dx, const pcg_solve_opts& o)
+{
+    if (o.preconditioner != PCG_PRECOND_AUTO) return o.preconditioner;
+    if (!o.fused) return PCG_PRECOND_LINE;
+    const double dz = d.height / d.nz;
+    const double gamma2 = d.k_h > 0.0 ? (d.k_v / (dz * dz)) / (d.k_h / (dx * dx)) : 1e300;
+    const int64_t n = (int64_t)d.nx * d.ny * d.nz;
+    const bool coarsens = d.nx % 2 == 0 && d.ny % 2 == 0 && d.nx / 2 >= kMgMinCells &&
+                          d.ny / 2 >= kMgMinCells;
+    if (gamma2 <= 300.0 && n >= (int64_t(1) << 22) && coarsens) return PCG_PRECOND_MG;
+    const bool red_black = !((d.bc_x == PCG_BC_PERIODIC && d.nx % 2) ||
+                             (d.bc_y == PCG_BC_PERIODIC && d.ny % 2));
+    if (gamma2 <= 1e4 && red_black) return PCG_PRECOND_RBGS;
+    return PCG_PRECOND_LINE;
+}
+
+// The options with AUTO resolved for problem P.
+pcg_solve_opts resolved_opts(const pcg_problem* P, const pcg_solve_opts& o)
+{
+    pcg_solve_opts r = o;
+    double dx = P->desc.dx;
+    if (P->d_hgeo) {   // stretched: the mean x width
+        double sum = 0.0;
+        for (int i = 0; i < P->desc.nx; ++i) sum += P->hgeo[i];
+        dx = sum / P->desc.nx;
+    }
+    r.preconditioner = resolve_precond(P->desc, dx, o);
+    return r;
+}
+
 // Multigrid levels a solve with these options uses (1: the fine level only).
 int mg_levels_used(const pcg_problem* P, int requested)
 {
@@ -118,8 +150,9 @@ void plan_mg(const pcg_problem* P, int levels, int64_t nrhs, size_t elem, Layout
 
 // With the problem's current tunings (a workspace sized before a tuning
 // change may be too small afterwards; pcg_solve then reports PCG_E_NOMEM).
-Layout plan(const pcg_problem* P, const pcg_solve_opts& o, int64_t nrhs)
+Layout plan(const pcg_problem* P, const pcg_solve_opts& o0, int64_t nrhs)
 {
+    const pcg_solve_opts o = resolved_opts(P, o0);
     int64_t slots = 1;
     for (int d = 0; d < 2; ++d)
         slots = std::max({slots, blocks_per_rhs(P, d), blocks_per_rhs_b(P, d)});
@@ -1092,8 +1125,10 @@ pcg_status rbgs_precond(pcg_problem* P, int dtype, const void* r, void* z, hipSt
 
 // Workspace of one served request, enough for any tuning of its shape (and
 // the coarse levels of the multigrid preconditioner when it is chosen).
-size_t request_bytes(const pcg_problem_desc& d, const pcg_solve_opts& o)
+size_t request_bytes(const pcg_problem_desc& d, const pcg_solve_opts& o0)
 {
+    pcg_solve_opts o = o0;
+    o.preconditioner = resolve_precond(d, d.dx, o0);
     const int64_t n = (int64_t)d.nx * d.ny * d.nz;
     size_t total = plan_n(n, o, 1, kMaxBlocks).total;
     if (o.preconditioner == PCG_PRECOND_MG) {
@@ -1120,9 +1155,10 @@ size_t workspace_bytes(const pcg_problem* Pc, const pcg_solve_opts& o, int64_t n
 }
 
 pcg_status solve(pcg_problem* P, const double* b, double* x, void* workspace, size_t ws_bytes,
-                 const pcg_solve_opts& o, int64_t nrhs, pcg_result* res, hipStream_t s)
+                 const pcg_solve_opts& o0, int64_t nrhs, pcg_result* res, hipStream_t s)
 {
     TuneScope ts(P, nrhs);
+    const pcg_solve_opts o = resolved_opts(P, o0);
     if (o.preconditioner == PCG_PRECOND_RBGS && !rbgs_supported(P)) {
         set_error("block Gauss-Seidel: red-black ordering needs an even size in periodic "
                   "directions");
@@ -1147,6 +1183,7 @@ pcg_status solve(pcg_problem* P, const double* b, double* x, void* workspace, si
     pcg_status worst = PCG_OK;
     for (int64_t i = 0; i < nrhs; ++i) {
         res[i].elapsed_ms = ms;
+        res[i].preconditioner = o.preconditioner;
         if (res[i].status == PCG_E_BREAKDOWN) worst = PCG_E_BREAKDOWN;
         else if (res[i].status == PCG_E_NOCONV && worst == PCG_OK) worst = PCG_E_NOCONV;
     }

@@ -144,3 +144,26 @@ def test_odd_periodic_rejected():
     o = pcg.pcg_default_opts(preconditioner=RB)
     with pytest.raises(pcg.PCGError):
         pcg.pcg_solve(p, b, torch.zeros_like(b), pcg.workspace(p, o), o)
+
+
+@pytest.mark.parametrize("args,want", [((256, 256, 128, 1e2, 0), pcg.PCG_PRECOND_MG),
+                                       ((64, 64, 32, 1e2, 0), pcg.PCG_PRECOND_RBGS),
+                                       ((64, 48, 32, 1e3, 1), pcg.PCG_PRECOND_RBGS),
+                                       ((63, 48, 32, 1e3, 1), pcg.PCG_PRECOND_LINE),
+                                       ((64, 64, 32, 1e5, 0), pcg.PCG_PRECOND_LINE)])
+def test_auto_preconditioner_choice(args, want):
+    nx, ny, nz, g2, bc = args
+    d = desc(nx, ny, nz, g2, bc, bc)
+    p = pcg.Problem(d)
+    b = si.rhs_uniform(nx, ny, nz, 9)
+    o = pcg.pcg_default_opts(preconditioner=pcg.PCG_PRECOND_AUTO, x0_zero=1)
+    bt = cuda(b)
+    x = torch.zeros_like(bt)
+    st, r = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
+    assert st == pcg.PCG_OK and r["preconditioner"] == want, r
+    if p.n <= 1 << 18:
+        A = oracle.assemble(grid_of(d, None, None))
+        assert oracle.residual_norm(A, b, x.cpu().numpy()) / np.linalg.norm(b) < 1.05e-8
+    o.fused = 0
+    st, r = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
+    assert st == pcg.PCG_OK and r["preconditioner"] == pcg.PCG_PRECOND_LINE
