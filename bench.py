@@ -44,15 +44,17 @@ def solve_kernel_bytes(kernel, iterations, n):
     if kernel == "fused_apply":
         return n * (BYTES["fused_apply_first"] + BYTES["fused_apply"] * (iterations - 1))
     return n * (BYTES["fused_prec_first"] + BYTES["fused_prec"] * iterations)
-KERNEL_PATTERN = {"fused_apply": r"k_fused_apply<double, \d+, (true|false), false, (true|false)>",
-                  "fused_prec": r"k_fused_prec<double, \d+, (true|false), false, (true|false)>"}
+KERNEL_PATTERN = {
+    "fused_apply": r"k_fused_apply<double, \d+, (true|false), false, (true|false), (true|false)>",
+    "fused_prec": r"k_fused_prec<double, \d+, (true|false), false, (true|false), (true|false)>"}
 STREAM_BYTES = 64 << 20       # vectors at least this large use nontemporal accesses
 
 
 def kernel_symbol(kernel, lanes_per_column, n, nz, elem=8, stretched=False, nrhs=1):
     """Template instance of a fused kernel that runs for this launch shape:
     M levels per lane, 16-byte vector path when whole chunks are aligned,
-    nontemporal accesses for vectors that cannot stay in the caches."""
+    nontemporal accesses for vectors that cannot stay in the caches, one
+    column per wavefront (64 lanes per column)."""
     m = 1
     while m * lanes_per_column < nz:
         m *= 2
@@ -60,7 +62,8 @@ def kernel_symbol(kernel, lanes_per_column, n, nz, elem=8, stretched=False, nrhs
     nt = n * nrhs * elem >= STREAM_BYTES and m * elem == 16
     t = "double" if elem == 8 else "float"
     b = lambda v: str(v).lower()
-    return "k_%s<%s, %d, %s, %s, %s>" % (kernel, t, m, b(vec), b(stretched), b(nt))
+    return "k_%s<%s, %d, %s, %s, %s, %s>" % (kernel, t, m, b(vec), b(stretched), b(nt),
+                                             b(lanes_per_column == 64))
 
 
 def log(*a):
