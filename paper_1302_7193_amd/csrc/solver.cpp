@@ -990,14 +990,28 @@ pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
                               0x3f800000, vec_bytes / 4, s),
             "hipMemsetD32Async");
     const Tuning saved = P->tune[dtype];
-    // per reduction mode: fastest kernel A (all but the line solve) and
-    // fastest kernel B, each with its launch shape and block cap
+    // per reduction mode: the three fastest launch shapes of kernel A (all
+    // but the line solve) and of kernel B, timed with the same shape for both
     struct Pick {
         float ms = 1e30f;
         Shape sh;
         int64_t cap = kDefaultCap;
     };
-    Pick best_a[2], best_b[2];
+    constexpr int kTop = 3;
+    Pick top_a[2][kTop], top_b[2][kTop];
+    auto keep = [](Pick (&top)[kTop], const Pick& p) {
+        for (int i = 0; i < kTop; ++i)
+            if (p.ms < top[i].ms) {
+                for (int j = kTop - 1; j > i; --j) top[j] = top[j - 1];
+                top[i] = p;
+                return;
+            }
+    };
+    auto time_pair = [&](const Tuning& t, float* ms_b, float* ms_a) -> pcg_status {
+        P->tune[dtype] = t;
+        return dtype == PCG_F64 ? time_tuning<double>(P, dtype, nrhs, ws, w, u, s, ms_b, ms_a)
+                                : time_tuning<float>(P, dtype, nrhs, ws, w, u, s, ms_b, ms_a);
+    };
     const int nz = P->geom.nz;
     for (int L = 1; L <= kWave; L <<= 1) {
         Shape sh;
@@ -1008,6 +1022,7 @@ pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
         if (sh.M * L >= 2 * nz && L > 1 && sh.M > 1) continue;   // lanes idle: skip
         for (int64_t total = 512; total <= kMaxBlocks; total <<= 1) {
             const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(kMaxBlocks, total / nrhs));
+            if (column_blocks(P->geom, sh) < cap && total > 512) continue;  // no change
             for (int mode = 0; mode < 2; ++mode) {
                 Tuning t;
                 t.shape = sh;
@@ -1015,28 +1030,42 @@ pcg_status autotune_in(pcg_problem* P, int dtype, int64_t nrhs, char* ws, const 
                 t.red_mode = mode;
                 t.shape_b = sh;
                 t.block_cap_b = cap;
-                P->tune[dtype] = t;
-                if (column_blocks(P->geom, sh) < cap && total > 512) continue;  // no change
                 float ms_b = 0.f, ms_a = 0.f;
-                pcg_status st =
-                    dtype == PCG_F64 ? time_tuning<double>(P, dtype, nrhs, ws, w, u, s, &ms_b, &ms_a)
-                                     : time_tuning<float>(P, dtype, nrhs, ws, w, u, s, &ms_b, &ms_a);
+                const pcg_status st = time_pair(t, &ms_b, &ms_a);
                 if (st != PCG_OK) {
                     P->tune[dtype] = saved;
                     return st;
                 }
-                if (ms_a < best_a[mode].ms) best_a[mode] = Pick{ms_a, sh, cap};
-                if (ms_b < best_b[mode].ms) best_b[mode] = Pick{ms_b, sh, cap};
+                keep(top_a[mode], Pick{ms_a, sh, cap});
+                keep(top_b[mode], Pick{ms_b, sh, cap});
             }
         }
     }
-    const int m = best_a[0].ms + best_b[0].ms < best_a[1].ms + best_b[1].ms ? 0 : 1;
+    // the shapes of A and B interact (how B stores z changes A's reads of
+    // it), so the final choice times the combinations of the leaders
     Tuning best_t;
-    best_t.shape = best_a[m].sh;
-    best_t.block_cap = best_a[m].cap;
-    best_t.shape_b = best_b[m].sh;
-    best_t.block_cap_b = best_b[m].cap;
-    best_t.red_mode = m;
+    float best_ms = 1e30f;
+    for (int mode = 0; mode < 2; ++mode)
+        for (int i = 0; i < kTop; ++i)
+            for (int j = 0; j < kTop; ++j) {
+                if (top_a[mode][i].ms >= 1e30f || top_b[mode][j].ms >= 1e30f) continue;
+                Tuning t;
+                t.shape = top_a[mode][i].sh;
+                t.block_cap = top_a[mode][i].cap;
+                t.shape_b = top_b[mode][j].sh;
+                t.block_cap_b = top_b[mode][j].cap;
+                t.red_mode = mode;
+                float ms_b = 0.f, ms_a = 0.f;
+                const pcg_status st = time_pair(t, &ms_b, &ms_a);
+                if (st != PCG_OK) {
+                    P->tune[dtype] = saved;
+                    return st;
+                }
+                if (ms_a + ms_b < best_ms) {
+                    best_ms = ms_a + ms_b;
+                    best_t = t;
+                }
+            }
     P->tune[dtype] = best_t;
     if (best) *best = best_t;
     return PCG_OK;
