@@ -232,6 +232,7 @@ def extras(pcg, si, torch, main):
     out["mixed_1024x1024x128"] = res3
     del P3, b3, x3
 
+    out["end_to_end_512x512x128_fp64"] = end_to_end(pcg, si, torch)
     out["stretched_512x512x128_fp64"] = stretched(pcg, si, torch, out["fused_fp64_graph"])
     out["preconditioners_512x512x128"] = multigrid(pcg, si, torch)
     out["batched_256x256x64x64"] = batched(pcg, si, torch)
@@ -245,6 +246,49 @@ def extras(pcg, si, torch, main):
     t_cp = cuda_time(torch, lambda: c.copy_(a), 10)
     out["hbm_copy_probe_GBps"] = 2 * a.numel() * 8 / (t_cp * 1e-3) / 1e9
     del a, c
+    return out
+
+
+def end_to_end(pcg, si, torch, reps=5):
+    """Whole solve as a host program sees it: problem set-up (geometry tables,
+    tuning lookup), workspace, right-hand side host -> device, the solve (its
+    first call on a new problem builds the graph chunks), solution device ->
+    host.  Pinned host buffers; median over reps fresh problems."""
+    nx, ny, nz = 512, 512, 128
+    desc = pcg.pcg_desc_from_ratio(nx, ny, nz, 1.05, 1e5, pcg.PCG_BC_PERIODIC)
+    n = nx * ny * nz
+    b_host = torch.from_numpy(si.rhs_uniform(nx, ny, nz, 1)).pin_memory()
+    x_host = torch.empty(n, dtype=torch.float64, pin_memory=True)
+    o = pcg.pcg_default_opts(x0_zero=1, graph_chunk=-1)
+    rows = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = pcg.Problem(desc)
+        ws = pcg.workspace(P, o)
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        x = torch.empty_like(b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        b.copy_(b_host, non_blocking=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st, r = pcg.pcg_solve(P, b, x, ws, o)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        x_host.copy_(x, non_blocking=True)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        assert st == pcg.PCG_OK, r
+        rows.append((t1 - t0, t2 - t1, t3 - t2, t4 - t3, t4 - t0, r["iterations"]))
+        del P, ws, b, x
+    rows.sort(key=lambda t: t[4])
+    setup, h2d, solve, d2h, total, its = rows[len(rows) // 2]
+    out = dict(setup_ms=setup * 1e3, h2d_ms=h2d * 1e3, first_solve_ms=solve * 1e3, d2h_ms=d2h * 1e3,
+               total_ms=total * 1e3, iterations=its, h2d_GBps=8 * n / h2d / 1e9,
+               unknowns_iter_per_s_incl_setup_and_transfers=n * its / total)
+    log("end to end: %.2f ms (set-up %.2f, H2D %.2f, solve %.2f, D2H %.2f)"
+        % (total * 1e3, setup * 1e3, h2d * 1e3, solve * 1e3, d2h * 1e3))
     return out
 
 

@@ -355,6 +355,7 @@ void pcg_problem_destroy(pcg_problem* P)
     (void)hipSetDevice(P->device);
     for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : P->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : P->gevents) (void)hipEventDestroy(e);
     if (P->pinned_states) (void)hipHostFree(P->pinned_states);
     if (P->dev_tables) (void)hipFree(P->dev_tables);
     if (P->mg_tables) (void)hipFree(P->mg_tables);

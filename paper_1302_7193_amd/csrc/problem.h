@@ -79,6 +79,7 @@ struct pcg_problem {
     int64_t pinned_cap = 0;
     std::map<pcg::GraphKey, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> events;
+    std::vector<hipEvent_t> gevents;       // event nodes of profiled graph chunks
 };
 
 namespace pcg {

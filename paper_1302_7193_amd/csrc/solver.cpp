@@ -235,9 +235,11 @@ pcg_status read_states(pcg_problem* P, const SolverState* dev, SolverState* host
 
 pcg_status ensure_events(pcg_problem* P, size_t count)
 {
+    // timing only: no system-scope fence (and its cache write-back) when
+    // an event is recorded; results are read after a stream synchronisation
     while (P->events.size() < count) {
         hipEvent_t e;
-        PCG_HIP(hipEventCreate(&e), "hipEventCreate");
+        PCG_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
         P->events.push_back(e);
     }
     return PCG_OK;
@@ -415,13 +417,15 @@ pcg_status issue_chunk(const ColArgs& a, const Phase& bph, int64_t nrhs, int K, 
 // The chunk as an explicitly built HIP graph (kernel nodes in sequence).  No
 // stream capture is involved, so building is independent of what other host
 // threads do with their streams.
+// profiled: event record nodes around every kernel A and kernel B's launches
+// up to its last main kernel, events P->gevents[4i .. 4i+3] for iteration i.
 template <typename T>
 pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, const Phase& bph,
-                       int bkind, int64_t nrhs, int K, hipGraphExec_t* out)
+                       int bkind, int64_t nrhs, int K, bool profiled, hipGraphExec_t* out)
 {
     GraphKey key{};
     key.dtype = dtype;
-    key.kind = bkind;
+    key.kind = bkind + (profiled ? 1000 : 0);
     key.iters = K;
     key.L = a.L;
     key.red_mode = a.red_mode;
@@ -436,7 +440,17 @@ pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, const Phase&
         *out = it->second;
         return PCG_OK;
     }
+    if (profiled) {
+        while (P->gevents.size() < 4 * (size_t)K) {
+            hipEvent_t e;
+            PCG_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
+            P->gevents.push_back(e);
+        }
+    }
+    // kernel launches in order; event e is recorded before launch i when
+    // marks holds (i, e) (i == seq.size(): after the last)
     std::vector<KernelLaunch> seq;
+    std::vector<std::pair<size_t, hipEvent_t>> marks;
     auto add = [&](Kind k) -> bool {
         KernelLaunch l[2];
         const int n = column_launches<T>(k, a, nrhs, l);
@@ -444,11 +458,17 @@ pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, const Phase&
         return n > 0;
     };
     for (int i = 0; i < K; ++i) {
+        const size_t a_main = seq.size();
+        if (profiled) marks.emplace_back(a_main, P->gevents[4 * i]);
         if (!add(Kind::FusedApply)) {
             set_error("graph: no kernel for this shape (internal)");
             return PCG_E_DEVICE;
         }
+        if (profiled) marks.emplace_back(a_main + 1, P->gevents[4 * i + 1]);   // before its finalize
+        const size_t b0 = seq.size();
+        if (profiled) marks.emplace_back(b0, P->gevents[4 * i + 2]);
         seq.insert(seq.end(), bph.k.begin(), bph.k.end());
+        if (profiled) marks.emplace_back(b0 + bph.last_main + 1, P->gevents[4 * i + 3]);
     }
     if (!add(Kind::Fixup)) {
         set_error("graph: no kernel for this shape (internal)");
@@ -457,7 +477,24 @@ pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, const Phase&
     hipGraph_t graph = nullptr;
     PCG_HIP(hipGraphCreate(&graph, 0), "hipGraphCreate");
     hipGraphNode_t prev = nullptr;
-    for (KernelLaunch& l : seq) {
+    size_t next_mark = 0;
+    auto add_marks = [&](size_t at) -> pcg_status {
+        for (; next_mark < marks.size() && marks[next_mark].first == at; ++next_mark) {
+            hipGraphNode_t node = nullptr;
+            const hipError_t e = hipGraphAddEventRecordNode(&node, graph, prev ? &prev : nullptr,
+                                                            prev ? 1 : 0, marks[next_mark].second);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                set_error(hip_msg(e, "hipGraphAddEventRecordNode"));
+                return PCG_E_DEVICE;
+            }
+            prev = node;
+        }
+        return PCG_OK;
+    };
+    for (size_t li = 0; li < seq.size(); ++li) {
+        if (add_marks(li) != PCG_OK) return PCG_E_DEVICE;
+        KernelLaunch& l = seq[li];
         void* params[] = {&l.args};   // copied when the node is added
         hipKernelNodeParams np{};
         np.func = const_cast<void*>(l.func);
@@ -476,6 +513,7 @@ pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, const Phase&
         }
         prev = node;
     }
+    if (add_marks(seq.size()) != PCG_OK) return PCG_E_DEVICE;
     hipGraphExec_t exec = nullptr;
     const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
@@ -506,7 +544,7 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a,
     int K = o.graph_chunk > 0 ? o.graph_chunk : P->last_iters[prec_slot];
     if (K <= 0) K = 8;
     K = std::min(K, std::max(1, o.max_iter));
-    const bool use_graph = o.graph_chunk != 0 && !profile;
+    const bool use_graph = o.graph_chunk != 0;
 
     // zero start: the first kernel B reads b itself; otherwise r = b - A x0
     if (!zero_start && launch<T>(Kind::InitFull, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
@@ -518,17 +556,27 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a,
         set_error("no kernel for this shape (internal)");
         return PCG_E_DEVICE;
     }
-    std::vector<char> is_a;
+    // timings in launch order: kernel A or B, and either an event pair of
+    // P->events (direct launches, each its own pair, read at the end; -1
+    // once read) or the time already read (graph chunks reuse their events
+    // on every replay, so each replay's are read after it)
+    struct Timing {
+        char is_a;
+        int pair;
+        float ms;
+    };
+    std::vector<Timing> tms;
+    int pairs = 0;
     auto timed = [&](const Phase& ph, char kind_a) -> pcg_status {
-        const size_t i = is_a.size();
-        if (ensure_events(P, 2 * i + 2) != PCG_OK) return PCG_E_DEVICE;
+        const int i = pairs++;
+        if (ensure_events(P, 2 * (size_t)i + 2) != PCG_OK) return PCG_E_DEVICE;
         PCG_HIP(hipEventRecord(P->events[2 * i], s), "hipEventRecord");
         for (size_t j = 0; j < ph.k.size(); ++j) {
             PCG_HIP(issue(ph.k[j], s), "kernel launch");
             if (j == ph.last_main) PCG_HIP(hipEventRecord(P->events[2 * i + 1], s), "hipEventRecord");
         }
         info.launches += ph.mains;
-        is_a.push_back(kind_a);
+        tms.push_back(Timing{kind_a, i, 0.f});
         return PCG_OK;
     };
     if (profile) {
@@ -540,7 +588,7 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a,
     const int max_chunks = o.max_iter / K + 3;
     int chunks = 0;
     for (;;) {
-        if (profile) {
+        if (profile && !use_graph) {
             for (int i = 0; i < K; ++i) {
                 if (timed(aph, 1) != PCG_OK) return PCG_E_DEVICE;
                 if (timed(bph, 0) != PCG_OK) return PCG_E_DEVICE;
@@ -548,7 +596,7 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a,
             if (launch<T>(Kind::Fixup, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
         } else if (use_graph) {
             hipGraphExec_t exec;
-            if (chunk_graph<T>(P, dtype, a, bph, bkind, nrhs, K, &exec) != PCG_OK)
+            if (chunk_graph<T>(P, dtype, a, bph, bkind, nrhs, K, profile, &exec) != PCG_OK)
                 return PCG_E_DEVICE;
             PCG_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
             info.launches += (1 + bph.mains) * K + 1;
@@ -557,6 +605,17 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a,
         }
         ++chunks;
         if (read_states(P, a.st, host_states, nrhs, s) != PCG_OK) return PCG_E_DEVICE;
+        if (profile && use_graph) {   // the replay is complete: read its events
+            for (int i = 0; i < K; ++i) {
+                float ma = 0.f, mb = 0.f;
+                PCG_HIP(hipEventElapsedTime(&ma, P->gevents[4 * i], P->gevents[4 * i + 1]),
+                        "hipEventElapsedTime");
+                PCG_HIP(hipEventElapsedTime(&mb, P->gevents[4 * i + 2], P->gevents[4 * i + 3]),
+                        "hipEventElapsedTime");
+                tms.push_back(Timing{1, -1, ma});
+                tms.push_back(Timing{0, -1, mb});
+            }
+        }
         bool running = false;
         for (int64_t i = 0; i < nrhs; ++i) running |= host_states[i].flag == kRunning;
         if (!running) break;
@@ -566,18 +625,19 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a,
         }
     }
     if (profile) {
-        // kernel i spans events[i] .. events[i+1]; count the launches that did work
+        for (Timing& t : tms)
+            if (t.pair >= 0)
+                PCG_HIP(hipEventElapsedTime(&t.ms, P->events[2 * t.pair], P->events[2 * t.pair + 1]),
+                        "hipEventElapsedTime");
+        // count the launches that did work (later ones returned at once)
         const int done_a = host_states[0].iter;
         int na = 0, nb = 0;
-        for (size_t i = 0; i < is_a.size(); ++i) {
-            float ms = 0.f;
-            PCG_HIP(hipEventElapsedTime(&ms, P->events[2 * i], P->events[2 * i + 1]),
-                    "hipEventElapsedTime");
-            if (is_a[i] && na < done_a) {
-                info.ms_a += ms;
+        for (const Timing& t : tms) {
+            if (t.is_a && na < done_a) {
+                info.ms_a += t.ms;
                 ++na;
-            } else if (!is_a[i] && nb < done_a + 1) {
-                info.ms_b += ms;
+            } else if (!t.is_a && nb < done_a + 1) {
+                info.ms_b += t.ms;
                 ++nb;
             }
         }

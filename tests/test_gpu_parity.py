@@ -201,10 +201,13 @@ def test_graph_and_direct_launches_bitwise_equal():
     xg, _, rg = gpu_solve(d, b, graph_chunk=2)
     xd, _, rd = gpu_solve(d, b, graph_chunk=0)
     xp, _, rp = gpu_solve(d, b, graph_chunk=0, profile=1)
-    assert rg["iterations"] == rd["iterations"] == rp["iterations"]
-    assert np.array_equal(xg, xd) and np.array_equal(xg, xp)
-    assert rp["n_apply_kernel"] == rp["iterations"] and rp["n_precond_kernel"] == rp["iterations"] + 1
-    assert rp["ms_apply_kernel"] > 0 and rp["ms_precond_kernel"] > 0
+    # profiled graph chunks: event nodes inside the graph, several replays
+    xq, _, rq = gpu_solve(d, b, graph_chunk=2, profile=1)
+    assert rg["iterations"] == rd["iterations"] == rp["iterations"] == rq["iterations"]
+    assert np.array_equal(xg, xd) and np.array_equal(xg, xp) and np.array_equal(xg, xq)
+    for r in (rp, rq):
+        assert r["n_apply_kernel"] == r["iterations"] and r["n_precond_kernel"] == r["iterations"] + 1
+        assert r["ms_apply_kernel"] > 0 and r["ms_precond_kernel"] > 0
 
 
 def test_repeated_solves_bitwise_reproducible():
