@@ -18,6 +18,14 @@ constexpr int kBlock = 256;        // threads per workgroup of the column kernel
 constexpr int kMaxNz = 1024;       // columns up to 64 lanes x 16 levels
 constexpr int kClasses = 9;        // column classes: Dirichlet faces in x (0..2) x in y (0..2)
 constexpr int kRedSlots = 2;       // doubles per workgroup in the partial-sum buffer
+// Vectors of the fused iteration larger than this are streamed with the
+// nontemporal hint: they cannot stay in the caches (32 MB of L2, 256 MB of
+// Infinity Cache) from one kernel to the next.  Only when a lane moves one
+// 16-byte chunk per vector, so that every store instruction of a wavefront
+// covers whole cache lines: with two or more chunks per lane each
+// instruction writes every other chunk, and nontemporal stores of such
+// partial lines raised the measured write traffic by a tenth.
+constexpr int64_t kStreamBytes = int64_t(64) << 20;
 constexpr int64_t kMaxBlocks = 65536;   // largest workgroup cap per right-hand side
 constexpr int64_t kDefaultCap = 16384;  // default workgroup cap per right-hand side
 constexpr double kMgOmega = 0.8;   // multigrid: damping of the line-Jacobi smoother
@@ -165,9 +173,9 @@ struct ColArgs {
 // Multigrid kernels (mg.hip): kernel for a Kind in MgPre..MgSmoothFinal, or
 // null; block Gauss-Seidel kernels (rbgs.hip): Kind >= RbFirst.
 template <typename T>
-const void* mg_func(Kind kind, const ColArgs& a);
+const void* mg_func(Kind kind, const ColArgs& a, int64_t batch);
 template <typename T>
-const void* rb_func(Kind kind, const ColArgs& a);
+const void* rb_func(Kind kind, const ColArgs& a, int64_t batch);
 
 // Host launchers (kernels.hip): T = double or float.  column_launches
 // returns the kernel (and, for mode-1 reductions, its finalize kernel) with

@@ -502,9 +502,17 @@ template <typename T, int M, bool V, bool G>
 const void* main_func_n(Kind kind, bool nt, bool w)
 {
     // one column per wavefront: only the two fused kernels have that variant
-    if (w && (kind == Kind::FusedApply || kind == Kind::FusedPrec))
-        return nt ? main_func_m<T, M, V, G, true, true>(kind) : main_func_m<T, M, V, G, false, true>(kind);
-    return nt ? main_func_m<T, M, V, G, true, false>(kind) : main_func_m<T, M, V, G, false, false>(kind);
+    // the nontemporal variants exist only where the hint is used: one
+    // 16-byte chunk per lane and vector
+    if constexpr (M * sizeof(T) == 16) {
+        if (w && (kind == Kind::FusedApply || kind == Kind::FusedPrec))
+            return nt ? main_func_m<T, M, V, G, true, true>(kind) : main_func_m<T, M, V, G, false, true>(kind);
+        return nt ? main_func_m<T, M, V, G, true, false>(kind) : main_func_m<T, M, V, G, false, false>(kind);
+    } else {
+        if (w && (kind == Kind::FusedApply || kind == Kind::FusedPrec))
+            return main_func_m<T, M, V, G, false, true>(kind);
+        return main_func_m<T, M, V, G, false, false>(kind);
+    }
 }
 
 template <typename T, int M>
@@ -519,20 +527,11 @@ const void* main_func_v(Kind kind, const ColArgs& a, bool nt)
     return vec ? main_func_n<T, M, true, false>(kind, nt, w) : main_func_n<T, M, false, false>(kind, nt, w);
 }
 
-// Vectors of the fused iteration larger than this are streamed with the
-// nontemporal hint: they cannot stay in the caches (32 MB of L2, 256 MB of
-// Infinity Cache) from one kernel to the next.  Only when a lane moves one
-// 16-byte chunk per vector, so that every store instruction of a wavefront
-// covers whole cache lines: with two or more chunks per lane each
-// instruction writes every other chunk, and nontemporal stores of such
-// partial lines raised the measured write traffic by a tenth.
-constexpr int64_t kStreamBytes = int64_t(64) << 20;
-
 template <typename T>
 const void* main_func(Kind kind, const ColArgs& a, int64_t batch)
 {
-    if (kind >= Kind::RbFirst) return rb_func<T>(kind, a);
-    if (kind >= Kind::MgPre) return mg_func<T>(kind, a);
+    if (kind >= Kind::RbFirst) return rb_func<T>(kind, a, batch);
+    if (kind >= Kind::MgPre) return mg_func<T>(kind, a, batch);
     const int M = a.L > 0 ? (a.g.nz + a.L - 1) / a.L : 0;
     int Mp = 1;
     while (Mp < M) Mp <<= 1;

@@ -10,6 +10,9 @@
 // its parent's values), restriction its transpose (a coarse residual is the
 // sum of its four children's), and the smoother is damped line Jacobi.
 //
+// The kernels and their dispatch; mg_f64.hip and mg_f32.hip instantiate
+// them for one precision each (two translation units compile in parallel).
+//
 // Kernels, each over one level and fused to read every vector once:
 //   k_mg_pre       t = omega M^{-1} r            (FUSED: r -= alpha q first,
 //                                                 as kernel B of the fused
@@ -24,18 +27,25 @@
 // A V-cycle is pre / restrict down the levels, sweeps on the coarsest, and
 // post back up; the fused iteration ends its kernel-B work with the fine
 // level's FINAL post-smoothing.
+#pragma once
+
 #include "column.h"
 
 namespace pcg {
 namespace {
 
+// NT: the vectors read or written once per sweep (r, q and the result) go
+// with the nontemporal hint, the iterate whose neighbour columns are re-read
+// and the coarse vectors without it.  W: one column per wavefront (L = 64,
+// column index scalar), as in the fused kernels.
+
 // Writes t = a.io2 from r (FUSED: from r or b with the update of kernel B,
 // r written back to a.io1).
-template <typename T, int M, bool V, bool G, bool FUSED>
+template <typename T, int M, bool V, bool G, bool FUSED, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_mg_pre(ColArgs a)
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st ? a.st + rhs : nullptr;
@@ -65,33 +75,33 @@ __global__ __launch_bounds__(kBlock) void k_mg_pre(ColArgs a)
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         T rc[M], zc[M];
-        ld<T, M, V>(src, c.idx, c.ok, p.k0, g.nz, rc);
+        ld<T, M, V, NT>(src, c.idx, c.ok, p.k0, g.nz, rc);
         if constexpr (FUSED) {
             if (!first) {
                 T qc[M];
-                ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+                ld<T, M, V, NT>(q, c.idx, c.ok, p.k0, g.nz, qc);
 #pragma unroll
                 for (int i = 0; i < M; ++i) rc[i] = rc[i] - alpha * qc[i];
             }
-            if (!first || store_r) st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+            if (!first || store_r) st<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
         }
         line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, rc, zc);
 #pragma unroll
         for (int i = 0; i < M; ++i) zc[i] *= omega;
-        st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
+        st<T, M, V, NT>(z, c.idx, c.ok, p.k0, g.nz, zc);
     }
 }
 
 // Tiles of the coarse level a.g; the fine level is a.g2 (geometry a.hgeo2);
 // reads r = a.in0 and t = a.in1 of the fine level, writes a.io0.
-template <typename T, int M, bool V, bool G>
+template <typename T, int M, bool V, bool G, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_mg_restrict(ColArgs a)
 {
     const Geom& gc = a.g;
     const Geom& gf = a.g2;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     if (a.st && a.st[rhs].flag != kRunning) return;
@@ -103,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(ColArgs a)
     int64_t t0, t1;
     block_tiles(gc, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col cp = make_col<false>(gc, tile_col(tile, p, L));   // the coarse column
+        const Col cp = make_col<false>(gc, W ? wave_col(tile, p) : tile_col(tile, p, L));   // the coarse column
         T acc[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[i] = T(0);
@@ -114,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(ColArgs a)
             T zf[M], az[M], rf[M];
             ld<T, M, V>(z, c.idx, c.ok, p.k0, gf.nz, zf);
             stencil<T, M, V, G>(gf, c, p.l, L, p.k0, z, zf, vc, az);
-            ld<T, M, V>(r, c.idx, c.ok, p.k0, gf.nz, rf);
+            ld<T, M, V, NT>(r, c.idx, c.ok, p.k0, gf.nz, rf);
 #pragma unroll
             for (int i = 0; i < M; ++i) acc[i] += rf[i] - az[i];
         }
@@ -130,12 +140,12 @@ __device__ __forceinline__ int64_t parent_ij(const Geom& gc, int i, int j)
 
 // Reads r = a.in0, the iterate t = a.io3 and (PROLONG) the coarse
 // correction a.in1 on level a.g2; writes z = a.io2 (never t).
-template <typename T, int M, bool V, bool G, bool PROLONG, bool FINAL>
+template <typename T, int M, bool V, bool G, bool PROLONG, bool FINAL, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_mg_post(ColArgs a)
 {
     const Geom& g = a.g;
     const Geom& gc = a.g2;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st ? a.st + rhs : nullptr;
@@ -154,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_post(ColArgs a)
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         // parents of the column and of its neighbours (periodic wrap as in
         // make_col; absent neighbours are never loaded)
         const int im = c.i > 0 ? c.i - 1 : g.nx - 1, ip = c.i < g.nx - 1 ? c.i + 1 : 0;
@@ -180,13 +190,13 @@ __global__ __launch_bounds__(kBlock) void k_mg_post(ColArgs a)
                                 load_z(col, ok, pc, o);
                             },
                             az);
-        ld<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+        ld<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
 #pragma unroll
         for (int i = 0; i < M; ++i) az[i] = rc[i] - az[i];
         line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, az, dz);
 #pragma unroll
         for (int i = 0; i < M; ++i) zo[i] += omega * dz[i];
-        st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zo);
+        st<T, M, V, NT>(z, c.idx, c.ok, p.k0, g.nz, zo);
         if constexpr (FINAL) {
 #pragma unroll
             for (int i = 0; i < M; ++i) {
@@ -204,51 +214,69 @@ __global__ __launch_bounds__(kBlock) void k_mg_post(ColArgs a)
     }
 }
 
-template <typename T, int M, bool V, bool G>
+template <typename T, int M, bool V, bool G, bool NT, bool W>
 const void* mg_func_m(Kind kind)
 {
     switch (kind) {
-    case Kind::MgPre: return reinterpret_cast<const void*>(&k_mg_pre<T, M, V, G, false>);
-    case Kind::MgPreFused: return reinterpret_cast<const void*>(&k_mg_pre<T, M, V, G, true>);
-    case Kind::MgRestrict: return reinterpret_cast<const void*>(&k_mg_restrict<T, M, V, G>);
-    case Kind::MgPost: return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, true, false>);
-    case Kind::MgPostFinal: return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, true, true>);
-    case Kind::MgSmooth: return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, false, false>);
+    case Kind::MgPre: return reinterpret_cast<const void*>(&k_mg_pre<T, M, V, G, false, NT, W>);
+    case Kind::MgPreFused: return reinterpret_cast<const void*>(&k_mg_pre<T, M, V, G, true, NT, W>);
+    case Kind::MgRestrict: return reinterpret_cast<const void*>(&k_mg_restrict<T, M, V, G, NT, W>);
+    case Kind::MgPost:
+        return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, true, false, NT, W>);
+    case Kind::MgPostFinal:
+        return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, true, true, NT, W>);
+    case Kind::MgSmooth:
+        return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, false, false, NT, W>);
     case Kind::MgSmoothFinal:
-        return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, false, true>);
+        return reinterpret_cast<const void*>(&k_mg_post<T, M, V, G, false, true, NT, W>);
     default: return nullptr;
     }
 }
 
+template <typename T, int M, bool V, bool G>
+const void* mg_func_n(Kind kind, bool nt, bool w)
+{
+    // the nontemporal variants exist only where the hint is used: one
+    // 16-byte chunk per lane and vector
+    if constexpr (M * sizeof(T) == 16) {
+        if (w) return nt ? mg_func_m<T, M, V, G, true, true>(kind) : mg_func_m<T, M, V, G, false, true>(kind);
+        return nt ? mg_func_m<T, M, V, G, true, false>(kind) : mg_func_m<T, M, V, G, false, false>(kind);
+    } else {
+        return w ? mg_func_m<T, M, V, G, false, true>(kind) : mg_func_m<T, M, V, G, false, false>(kind);
+    }
+}
+
 template <typename T, int M>
-const void* mg_func_v(Kind kind, const ColArgs& a)
+const void* mg_func_v(Kind kind, const ColArgs& a, bool nt)
 {
     const bool vec = (a.g.nz % M == 0) && ((M * sizeof(T)) % 16 == 0) &&
                      ((a.g.nz * sizeof(T)) % 16 == 0);
+    const bool w = a.L == kWave;
     if (a.hgeo || a.hgeo2)
-        return vec ? mg_func_m<T, M, true, true>(kind) : mg_func_m<T, M, false, true>(kind);
-    return vec ? mg_func_m<T, M, true, false>(kind) : mg_func_m<T, M, false, false>(kind);
+        return vec ? mg_func_n<T, M, true, true>(kind, nt, w) : mg_func_n<T, M, false, true>(kind, nt, w);
+    return vec ? mg_func_n<T, M, true, false>(kind, nt, w) : mg_func_n<T, M, false, false>(kind, nt, w);
 }
 
 }  // namespace
 
 template <typename T>
-const void* mg_func(Kind kind, const ColArgs& a)
+const void* mg_func(Kind kind, const ColArgs& a, int64_t batch)
 {
     const int M = a.L > 0 ? (a.g.nz + a.L - 1) / a.L : 0;
     int Mp = 1;
     while (Mp < M) Mp <<= 1;
+    // the fine level's vectors of a large problem, as in the fused kernels
+    // (restriction: the fine level is a.g2)
+    const Geom& fine = kind == Kind::MgRestrict ? a.g2 : a.g;
+    const bool nt = fine.n * batch * (int64_t)sizeof(T) >= kStreamBytes && Mp * sizeof(T) == 16;
     switch (Mp) {
-    case 1: return mg_func_v<T, 1>(kind, a);
-    case 2: return mg_func_v<T, 2>(kind, a);
-    case 4: return mg_func_v<T, 4>(kind, a);
-    case 8: return mg_func_v<T, 8>(kind, a);
-    case 16: return mg_func_v<T, 16>(kind, a);
+    case 1: return mg_func_v<T, 1>(kind, a, nt);
+    case 2: return mg_func_v<T, 2>(kind, a, nt);
+    case 4: return mg_func_v<T, 4>(kind, a, nt);
+    case 8: return mg_func_v<T, 8>(kind, a, nt);
+    case 16: return mg_func_v<T, 16>(kind, a, nt);
     default: return nullptr;
     }
 }
-
-template const void* mg_func<double>(Kind, const ColArgs&);
-template const void* mg_func<float>(Kind, const ColArgs&);
 
 }  // namespace pcg

@@ -14,6 +14,9 @@
 // Each half-sweep reads only the other colour, so all three write into the
 // same vector z.  The first kernel also does kernel B's update of r, the
 // last its reductions and scalar step.
+// NT: r, q and the stores of z go with the nontemporal hint (the colour read
+// through the neighbour loads does not); W: one column per wavefront
+// (L = 64, column index scalar), as in the fused kernels.
 #include "column.h"
 
 namespace pcg {
@@ -48,11 +51,11 @@ __device__ __forceinline__ void hcouple(const Geom& g, const Col& c, int k0,
 // r taken from b in the first iteration), as kernel B does.  Reads r from
 // a.in0 (FUSED: a.in1 / a.io1 and q = a.io4, r written to a.io1); writes
 // the red columns of z = a.io2.
-template <typename T, int M, bool V, bool G, bool FUSED>
+template <typename T, int M, bool V, bool G, bool FUSED, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_rb_first(ColArgs a)
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st ? a.st + rhs : nullptr;
@@ -81,25 +84,25 @@ __global__ __launch_bounds__(kBlock) void k_rb_first(ColArgs a)
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         const bool red = is_red(c);
         T rc[M];
         if constexpr (FUSED) {
-            ld<T, M, V>(src, c.idx, c.ok, p.k0, g.nz, rc);
+            ld<T, M, V, NT>(src, c.idx, c.ok, p.k0, g.nz, rc);
             if (!first) {
                 T qc[M];
-                ld<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, qc);
+                ld<T, M, V, NT>(q, c.idx, c.ok, p.k0, g.nz, qc);
 #pragma unroll
                 for (int i = 0; i < M; ++i) rc[i] = rc[i] - alpha * qc[i];
             }
-            if (!first || store_r) st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+            if (!first || store_r) st<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
         } else {
-            ld<T, M, V>(src, c.idx, c.ok && red, p.k0, g.nz, rc);
+            ld<T, M, V, NT>(src, c.idx, c.ok && red, p.k0, g.nz, rc);
         }
         if (red) {   // the same for every lane of the column's segment
             T zc[M];
             line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, rc, zc);
-            st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
+            st<T, M, V, NT>(z, c.idx, c.ok, p.k0, g.nz, zc);
         }
     }
 }
@@ -107,11 +110,11 @@ __global__ __launch_bounds__(kBlock) void k_rb_first(ColArgs a)
 // One later half-sweep over the columns of colour RED (reads r = a.in0 and
 // the other colour of z = a.io2, writes this colour of z).  FINAL (red):
 // R = <r,r>, kappa = <r,z> over all columns, exit test, beta.
-template <typename T, int M, bool V, bool G, bool RED, bool FINAL>
+template <typename T, int M, bool V, bool G, bool RED, bool FINAL, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_rb_sweep(ColArgs a)
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st ? a.st + rhs : nullptr;
@@ -127,18 +130,18 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(ColArgs a)
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         const bool mine = is_red(c) == RED;
         if (!mine && !FINAL) continue;   // the same for every lane of the segment
         T rc[M], zc[M];
-        ld<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+        ld<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
         if (mine) {
             T h[M];
             hcouple<T, M, V, G>(g, c, p.k0, z, vc, h);
 #pragma unroll
             for (int i = 0; i < M; ++i) h[i] = rc[i] - h[i];
             line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, h, zc);
-            st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
+            st<T, M, V, NT>(z, c.idx, c.ok, p.k0, g.nz, zc);
         } else {
             ld<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
         }
@@ -159,49 +162,67 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(ColArgs a)
     }
 }
 
-template <typename T, int M, bool V, bool G>
+template <typename T, int M, bool V, bool G, bool NT, bool W>
 const void* rb_func_m(Kind kind)
 {
     switch (kind) {
-    case Kind::RbFirst: return reinterpret_cast<const void*>(&k_rb_first<T, M, V, G, false>);
-    case Kind::RbFirstFused: return reinterpret_cast<const void*>(&k_rb_first<T, M, V, G, true>);
+    case Kind::RbFirst:
+        return reinterpret_cast<const void*>(&k_rb_first<T, M, V, G, false, NT, W>);
+    case Kind::RbFirstFused:
+        return reinterpret_cast<const void*>(&k_rb_first<T, M, V, G, true, NT, W>);
     case Kind::RbBlack:
-        return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, false, false>);
-    case Kind::RbRed: return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, true, false>);
+        return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, false, false, NT, W>);
+    case Kind::RbRed:
+        return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, true, false, NT, W>);
     case Kind::RbRedFinal:
-        return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, true, true>);
+        return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, true, true, NT, W>);
     default: return nullptr;
     }
 }
 
+template <typename T, int M, bool V, bool G>
+const void* rb_func_n(Kind kind, bool nt, bool w)
+{
+    // the nontemporal variants exist only where the hint is used: one
+    // 16-byte chunk per lane and vector
+    if constexpr (M * sizeof(T) == 16) {
+        if (w) return nt ? rb_func_m<T, M, V, G, true, true>(kind) : rb_func_m<T, M, V, G, false, true>(kind);
+        return nt ? rb_func_m<T, M, V, G, true, false>(kind) : rb_func_m<T, M, V, G, false, false>(kind);
+    } else {
+        return w ? rb_func_m<T, M, V, G, false, true>(kind) : rb_func_m<T, M, V, G, false, false>(kind);
+    }
+}
+
 template <typename T, int M>
-const void* rb_func_v(Kind kind, const ColArgs& a)
+const void* rb_func_v(Kind kind, const ColArgs& a, bool nt)
 {
     const bool vec = (a.g.nz % M == 0) && ((M * sizeof(T)) % 16 == 0) &&
                      ((a.g.nz * sizeof(T)) % 16 == 0);
-    if (a.hgeo) return vec ? rb_func_m<T, M, true, true>(kind) : rb_func_m<T, M, false, true>(kind);
-    return vec ? rb_func_m<T, M, true, false>(kind) : rb_func_m<T, M, false, false>(kind);
+    const bool w = a.L == kWave;
+    if (a.hgeo) return vec ? rb_func_n<T, M, true, true>(kind, nt, w) : rb_func_n<T, M, false, true>(kind, nt, w);
+    return vec ? rb_func_n<T, M, true, false>(kind, nt, w) : rb_func_n<T, M, false, false>(kind, nt, w);
 }
 
 }  // namespace
 
 template <typename T>
-const void* rb_func(Kind kind, const ColArgs& a)
+const void* rb_func(Kind kind, const ColArgs& a, int64_t batch)
 {
     const int M = a.L > 0 ? (a.g.nz + a.L - 1) / a.L : 0;
     int Mp = 1;
     while (Mp < M) Mp <<= 1;
+    const bool nt = a.g.n * batch * (int64_t)sizeof(T) >= kStreamBytes && Mp * sizeof(T) == 16;
     switch (Mp) {
-    case 1: return rb_func_v<T, 1>(kind, a);
-    case 2: return rb_func_v<T, 2>(kind, a);
-    case 4: return rb_func_v<T, 4>(kind, a);
-    case 8: return rb_func_v<T, 8>(kind, a);
-    case 16: return rb_func_v<T, 16>(kind, a);
+    case 1: return rb_func_v<T, 1>(kind, a, nt);
+    case 2: return rb_func_v<T, 2>(kind, a, nt);
+    case 4: return rb_func_v<T, 4>(kind, a, nt);
+    case 8: return rb_func_v<T, 8>(kind, a, nt);
+    case 16: return rb_func_v<T, 16>(kind, a, nt);
     default: return nullptr;
     }
 }
 
-template const void* rb_func<double>(Kind, const ColArgs&);
-template const void* rb_func<float>(Kind, const ColArgs&);
+template const void* rb_func<double>(Kind, const ColArgs&, int64_t);
+template const void* rb_func<float>(Kind, const ColArgs&, int64_t);
 
 }  // namespace pcg
