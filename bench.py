@@ -144,6 +144,30 @@ def cuda_time(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def hbm_probe(pcg, torch, n=1 << 25, reps=10):
+    """The library's streaming kernel (pcg_stream_probe) with the access mixes
+    of kernel A (4 vectors in / 3 out), kernel B (2 / 2) and a copy (1 / 1),
+    on vectors of the main workload's size (n FP64 values): the best over
+    workgroup counts, with and without the nontemporal hint.  The practical
+    ceiling beside the 8 TB/s peak."""
+    vecs = [torch.full((n,), 1.0 + k, dtype=torch.float64, device="cuda") for k in range(7)]
+    out = {}
+    for name, nr, nw in (("copy", 1, 1), ("kernel_b_mix", 2, 2), ("kernel_a_mix", 4, 3)):
+        best = None
+        for nt in (False, True):
+            for blocks in (4096, 16384, 65536):
+                ms = cuda_time(torch, lambda: pcg.pcg_stream_probe(vecs[:nr], vecs[nr:nr + nw],
+                                                                   nt, blocks), reps)
+                gbps = (nr + nw) * n * 8 / (ms * 1e-3) / 1e9
+                if best is None or gbps > best["GBps"]:
+                    best = dict(GBps=gbps, nontemporal=nt, blocks=blocks, vectors_in=nr,
+                                vectors_out=nw, bytes_per_vector=n * 8)
+        out[name] = best
+        log("probe %s: %.0f GB/s" % (name, best["GBps"]))
+    del vecs
+    return out
+
+
 def timed_solves(pcg, torch, P, b, x, ws, opts, reps):
     st, r = pcg.pcg_solve(P, b, x, ws, opts)          # warm (graph capture, chunk length)
     torch.cuda.synchronize()
@@ -706,6 +730,11 @@ def main():
         "kernel_source_sha256_16": kernel_source_hash(),
     }
     if not args.main_only:
+        probe = hbm_probe(pcg, torch)
+        mix = probe["kernel_a_mix" if dom == "fused_apply" else "kernel_b_mix"]["GBps"]
+        line["roofline"]["probe_GBps"] = mix
+        line["roofline"]["frac_of_probe"] = kern[dom]["achieved_GBps"] / mix
+        line["hbm_probe"] = probe
         try:
             line["extras"] = extras(pcg, si, torch, m)
         except Exception as e:  # report, keep the main line

@@ -364,6 +364,22 @@ pcg_status pcg_server_query(pcg_server *s, pcg_server_stats *out);
 /* Cancels queued requests, waits for running ones, stops the workers. */
 void pcg_server_destroy(pcg_server *s);
 
+/* HBM bandwidth probe: the paper rates its memory-bound kernels by their
+ * global-memory bandwidth as a fraction of the quoted peak (Sec. 5); this
+ * measures what a kernel that only streams attains, the practical ceiling
+ * beside that peak.  One kernel streams n_read (1..4) vectors in and n_write
+ * (1..3) out, each `bytes` long (a positive multiple of 16), 16 bytes per
+ * lane and access, with the nontemporal hint on every access when
+ * nontemporal = 1.  vectors: host array of n_read + n_write device pointers
+ * (16-byte aligned, caller-owned), the read ones first; a written vector may
+ * not overlap any other.  Written vector k receives sum_i v_i * 2^-(i+k)
+ * elementwise.  blocks: workgroups (0: 16384), each streaming one contiguous
+ * range.  Asynchronous on `stream` (current device); the caller times it.
+ * The mixes of the solver's kernels: 4 in / 3 out (kernel A), 2 / 2
+ * (kernel B), 1 / 1 (copy).  PCG_E_INVALID for bad arguments. */
+pcg_status pcg_stream_probe(int32_t n_read, int32_t n_write, void *const *vectors, size_t bytes,
+                            int32_t nontemporal, int64_t blocks, void *stream);
+
 /* Thread-local message of the last failing call (NUL-terminated, truncated
  * to n bytes); returns the full length. */
 size_t pcg_last_error(char *buf, size_t n);

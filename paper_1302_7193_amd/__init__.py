@@ -117,6 +117,8 @@ _sig = {
     "pcg_csr_build": (_S, [_P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "pcg_csr_apply": (_S, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "pcg_last_error": (ctypes.c_size_t, [ctypes.c_char_p, ctypes.c_size_t]),
+    "pcg_stream_probe": (_S, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                              ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, _P]),
     "pcg_get_tuning": (_S, [_P, ctypes.c_int32, ctypes.POINTER(pcg_tuning)]),
     "pcg_set_tuning": (_S, [_P, ctypes.c_int32, ctypes.POINTER(pcg_tuning)]),
     "pcg_autotune": (_S, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(pcg_tuning)]),
@@ -335,6 +337,22 @@ def pcg_csr_build(p: Problem, dtype: int, buf, stream=None) -> int:
     return _check(_lib.pcg_csr_build(p.handle, dtype, _buf(buf, need, "csr buffer"),
                                      buf.numel() * buf.element_size(), _stream(stream)),
                   "pcg_csr_build")
+
+
+def pcg_stream_probe(reads, writes, nontemporal: bool = True, blocks: int = 0, stream=None) -> int:
+    """HBM probe: stream the CUDA tensors `reads` in and `writes` out (all of
+    one byte size); written tensor k receives sum_i reads[i] * 2^-(i+k)
+    (as FP64 pairs).  Asynchronous on `stream`."""
+    vecs = list(reads) + list(writes)
+    if not vecs:
+        raise ValueError("no vectors")
+    nbytes = vecs[0].numel() * vecs[0].element_size()
+    for t in vecs:
+        if _buf(t, nbytes, "probe vector") and t.numel() * t.element_size() != nbytes:
+            raise ValueError("probe vectors must have one byte size")
+    arr = (ctypes.c_void_p * len(vecs))(*[t.data_ptr() for t in vecs])
+    return _check(_lib.pcg_stream_probe(len(reads), len(writes), arr, nbytes, int(bool(nontemporal)),
+                                        blocks, _stream(stream)), "pcg_stream_probe")
 
 
 def pcg_csr_apply(p: Problem, dtype: int, buf, x, y, stream=None) -> int:

@@ -636,6 +636,40 @@ pcg_status pcg_csr_apply(pcg_problem* P, int32_t dtype, const void* buf, const v
     });
 }
 
+pcg_status pcg_stream_probe(int32_t n_read, int32_t n_write, void* const* vectors, size_t bytes,
+                            int32_t nontemporal, int64_t blocks, void* stream)
+{
+    if (n_read < 1 || n_read > 4 || n_write < 1 || n_write > 3 || !vectors || bytes == 0 ||
+        bytes % 16 != 0 || (nontemporal != 0 && nontemporal != 1) || blocks < 0) {
+        set_error("pcg_stream_probe: 1..4 read and 1..3 written vectors, bytes a positive "
+                  "multiple of 16, nontemporal 0 or 1, blocks >= 0");
+        return PCG_E_INVALID;
+    }
+    const int nv = n_read + n_write;
+    for (int i = 0; i < nv; ++i) {
+        const char* v = static_cast<const char*>(vectors[i]);
+        if (!v || !aligned16(v)) {
+            set_error("pcg_stream_probe: vectors must be non-NULL and 16-byte aligned");
+            return PCG_E_INVALID;
+        }
+        for (int k = 0; k < i; ++k) {
+            const char* u = static_cast<const char*>(vectors[k]);
+            if (v < u + bytes && u < v + bytes && (i >= n_read || k >= n_read)) {
+                set_error("pcg_stream_probe: a written vector overlaps another vector");
+                return PCG_E_INVALID;
+            }
+        }
+    }
+    const hipError_t e = stream_probe(n_read, n_write, vectors, bytes, nontemporal != 0,
+                                      blocks > 0 ? blocks : kDefaultCap,
+                                      static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        set_error(hip_msg(e, "pcg_stream_probe launch"));
+        return PCG_E_DEVICE;
+    }
+    return PCG_OK;
+}
+
 size_t pcg_last_error(char* buf, size_t n)
 {
     const std::string& m = g_last_error;

@@ -1,0 +1,126 @@
+// HBM bandwidth probe (gfx950): the practical ceiling of a kernel that only
+// streams vectors, with the access mixes of the fused kernels.
+//
+// Kernel A of the fused iteration reads four vectors and writes three, kernel
+// B reads two and writes two; a plain copy reads one and writes one.  The
+// probe streams n_read vectors in and n_write out, 16 bytes per lane and
+// access, with the workgroup-contiguous ranges the column kernels use, two
+// 256-thread strips in flight per vector, and (optionally) the nontemporal
+// hint on every access.  It does no other arithmetic than the combination
+// that keeps the loads alive: w_k = sum_i c_ik v_i with fixed coefficients.
+#include <hip/hip_runtime.h>
+
+#include "problem.h"
+
+namespace pcg {
+namespace {
+
+struct ProbeArgs {
+    const double2* in[4];
+    double2* out[3];
+    int64_t n16;     // 16-byte elements per vector
+};
+
+template <bool NT>
+__device__ __forceinline__ double2 pld(const double2* p)
+{
+    if constexpr (NT) {
+        double2 v;
+        v.x = __builtin_nontemporal_load(&p->x);
+        v.y = __builtin_nontemporal_load(&p->y);
+        return v;
+    }
+    return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void pst(double2* p, double2 v)
+{
+    if constexpr (NT) {
+        __builtin_nontemporal_store(v.x, &p->x);
+        __builtin_nontemporal_store(v.y, &p->y);
+    } else {
+        *p = v;
+    }
+}
+
+constexpr int kProbeStrips = 2;   // 256-thread strips in flight per vector
+
+// Output k is sum_i v_i * 2^-(i + k): a fixed linear map the tests rebuild.
+template <int NR, int NW, bool NT>
+__global__ __launch_bounds__(kBlock) void k_stream_probe(ProbeArgs a)
+{
+    const int64_t per = (a.n16 + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * per;
+    const int64_t i1 = i0 + per < a.n16 ? i0 + per : a.n16;
+    for (int64_t base = i0; base < i1; base += (int64_t)kBlock * kProbeStrips) {
+        double2 v[kProbeStrips][NR];
+#pragma unroll
+        for (int u = 0; u < kProbeStrips; ++u) {
+            const int64_t i = base + u * kBlock + threadIdx.x;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) v[u][r] = i < i1 ? pld<NT>(a.in[r] + i) : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < kProbeStrips; ++u) {
+            const int64_t i = base + u * kBlock + threadIdx.x;
+            if (i >= i1) continue;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                double2 s{0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const double c = ldexp(1.0, -(r + w));
+                    s.x += c * v[u][r].x;
+                    s.y += c * v[u][r].y;
+                }
+                pst<NT>(a.out[w] + i, s);
+            }
+        }
+    }
+}
+
+template <int NR, int NW>
+const void* probe_func(bool nt)
+{
+    return nt ? reinterpret_cast<const void*>(&k_stream_probe<NR, NW, true>)
+              : reinterpret_cast<const void*>(&k_stream_probe<NR, NW, false>);
+}
+
+template <int NR>
+const void* probe_func_r(int nw, bool nt)
+{
+    switch (nw) {
+    case 1: return probe_func<NR, 1>(nt);
+    case 2: return probe_func<NR, 2>(nt);
+    case 3: return probe_func<NR, 3>(nt);
+    default: return nullptr;
+    }
+}
+
+}  // namespace
+
+hipError_t stream_probe(int n_read, int n_write, void* const* vectors, size_t bytes, bool nt,
+                        int64_t blocks, hipStream_t s)
+{
+    ProbeArgs a{};
+    for (int r = 0; r < n_read; ++r) a.in[r] = static_cast<const double2*>(vectors[r]);
+    for (int w = 0; w < n_write; ++w) a.out[w] = static_cast<double2*>(vectors[n_read + w]);
+    a.n16 = (int64_t)(bytes / 16);
+    const void* f = nullptr;
+    switch (n_read) {
+    case 1: f = probe_func_r<1>(n_write, nt); break;
+    case 2: f = probe_func_r<2>(n_write, nt); break;
+    case 3: f = probe_func_r<3>(n_write, nt); break;
+    case 4: f = probe_func_r<4>(n_write, nt); break;
+    default: break;
+    }
+    if (!f) return hipErrorInvalidValue;
+    const int64_t per_block = (int64_t)kBlock * kProbeStrips;
+    const int64_t most = (a.n16 + per_block - 1) / per_block;   // no block without work
+    const int64_t grid = blocks < most ? blocks : most;
+    void* params[] = {&a};
+    return hipLaunchKernel(f, dim3((unsigned)grid), dim3(kBlock), params, 0, s);
+}
+
+}  // namespace pcg

@@ -129,4 +129,8 @@ private:
     Tuning saved_[2];
 };
 
+// HBM probe (probe.hip): n_read vectors streamed in, n_write out.
+hipError_t stream_probe(int n_read, int n_write, void* const* vectors, size_t bytes, bool nt,
+                        int64_t blocks, hipStream_t s);
+
 }  // namespace pcg

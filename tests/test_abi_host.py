@@ -140,3 +140,19 @@ def test_stretched_create_rejects_bad_widths_before_touching_a_device(lib):
         assert not h.value
     assert f(ctypes.byref(d), None, good_y, ctypes.byref(h)) == pcg.PCG_E_INVALID
     assert f(ctypes.byref(d), good_x, None, ctypes.byref(h)) == pcg.PCG_E_INVALID
+
+
+def test_stream_probe_rejects_bad_arguments_before_touching_a_device(lib):
+    import paper_1302_7193_amd as pcg
+    f = pcg._lib.pcg_stream_probe
+    buf = (ctypes.c_void_p * 7)(*[0x10000 * (k + 1) for k in range(7)])
+    for nr, nw, nbytes, nt, blocks in ((0, 1, 1024, 1, 0), (5, 1, 1024, 1, 0), (1, 0, 1024, 1, 0),
+                                       (1, 4, 1024, 1, 0), (1, 1, 0, 1, 0), (1, 1, 1000, 1, 0),
+                                       (1, 1, 1024, 2, 0), (1, 1, 1024, 1, -1)):
+        assert f(nr, nw, buf, nbytes, nt, blocks, None) == pcg.PCG_E_INVALID, (nr, nw, nbytes)
+    assert f(1, 1, None, 1024, 1, 0, None) == pcg.PCG_E_INVALID
+    bad = (ctypes.c_void_p * 2)(0x10000, 0x20008)            # misaligned
+    assert f(1, 1, bad, 1024, 1, 0, None) == pcg.PCG_E_INVALID
+    overlap = (ctypes.c_void_p * 2)(0x10000, 0x10200)        # written overlaps read
+    assert f(1, 1, overlap, 1024, 1, 0, None) == pcg.PCG_E_INVALID
+    assert "overlaps" in pcg.pcg_last_error()
