@@ -18,8 +18,11 @@
 //   forward   w_k = r_k - l_k w_{k-1},
 //   backward  z_k = w_k / D_k - phi_k z_{k+1},
 // which each lane runs over its own levels and the segment completes with a
-// log2(L)-step scan of affine maps across lanes -- the sub-structuring of the
-// column system into L pieces plus an L-sized interface problem (Sec. 6.1).
+// scan of affine maps across lanes -- the sub-structuring of the column
+// system into L pieces plus an L-sized interface problem (Sec. 6.1).  The
+// scan runs in two levels: within each row of 16 lanes by DPP row shifts
+// (register moves, no LDS round trip), then across the rows of a 32- or
+// 64-lane segment from the rows' totals read into scalar registers.
 // L = 1 is the sequential Thomas algorithm of Sec. 4.2.
 //
 // Stretched horizontal grids (G = true).  |T| and the face weights
@@ -43,6 +46,67 @@
 
 namespace pcg {
 namespace {
+
+// One step of an inclusive scan of affine maps y -> Q + P y within rows of
+// 16 lanes: compose with the map D lanes below (UP) or above; lanes whose
+// partner lies outside their segment of L lanes (l: position in it) or row
+// keep their map.
+template <int D, bool UP, typename T>
+__device__ __forceinline__ void scan_step(T& P, T& Q, int l, int L)
+{
+    const T Pn = dpp_move<UP ? kRowShr + D : kRowShl + D>(P, T(1));
+    const T Qn = dpp_move<UP ? kRowShr + D : kRowShl + D>(Q, T(0));
+    if (UP ? l >= D : l + D < L) {
+        Q = P * Qn + Q;
+        P = P * Pn;
+    }
+}
+
+// Forward (UP) or backward carry of the recurrence y -> Q + P y run across a
+// segment of L lanes (L a power of two, 1..64, segments aligned to L): the
+// value entering this lane's levels from the lanes below (UP) or above it,
+// starting from zero at the segment's end.  (P, Q): this lane's map.
+template <bool UP, typename T>
+__device__ __forceinline__ T segment_carry(T P, T Q, int l, int L)
+{
+    if (L > 1) scan_step<1, UP>(P, Q, l, L);
+    if (L > 2) scan_step<2, UP>(P, Q, l, L);
+    if (L > 4) scan_step<4, UP>(P, Q, l, L);
+    if (L > 8) scan_step<8, UP>(P, Q, l, L);
+    // (P, Q) now composes the lanes from the row's (or segment's) edge to
+    // this lane; the neighbour's composition, identity at an edge
+    T Px = dpp_move<UP ? kRowShr + 1 : kRowShl + 1>(P, T(1));
+    T Qx = dpp_move<UP ? kRowShr + 1 : kRowShl + 1>(Q, T(0));
+    if (UP ? l == 0 : l == L - 1) {
+        Px = T(1);
+        Qx = T(0);
+    }
+    if (L <= 16) return Qx;
+    // carry into this lane's row from the other rows of the segment, from
+    // the rows' totals (last lane of a row going up, first going down)
+    const int row = (threadIdx.x & (kWave - 1)) >> 4;
+    T cr;
+    if constexpr (UP) {
+        const T q0 = read_lane(Q, 15), q1 = read_lane(Q, 31), q2 = read_lane(Q, 47);
+        if (L == 32) {
+            cr = row == 1 ? q0 : row == 3 ? q2 : T(0);
+        } else {
+            const T p1 = read_lane(P, 31), p2 = read_lane(P, 47);
+            const T c2 = q1 + p1 * q0;
+            cr = row == 0 ? T(0) : row == 1 ? q0 : row == 2 ? c2 : q2 + p2 * c2;
+        }
+    } else {
+        const T q1 = read_lane(Q, 16), q2 = read_lane(Q, 32), q3 = read_lane(Q, 48);
+        if (L == 32) {
+            cr = row == 0 ? q1 : row == 2 ? q3 : T(0);
+        } else {
+            const T p1 = read_lane(P, 16), p2 = read_lane(P, 32);
+            const T c1 = q2 + p2 * q3;
+            cr = row == 3 ? T(0) : row == 2 ? q3 : row == 1 ? c1 : q1 + p1 * c1;
+        }
+    }
+    return Qx + Px * cr;
+}
 
 struct Col {
     int64_t idx;
@@ -226,8 +290,8 @@ __device__ __forceinline__ void stencil_nb(const Geom& g, const Col& c, int l, i
                                            const T (&xc)[M], const VertCoef<T, M>& vc,
                                            NbLoad&& nb, T (&y)[M])
 {
-    T below = __shfl_up(xc[M - 1], 1, L);
-    T above = __shfl_down(xc[0], 1, L);
+    T below = dpp_move<kWaveShr1>(xc[M - 1], T(0));
+    T above = dpp_move<kWaveShl1>(xc[0], T(0));
     if (l == 0) below = T(0);
     if (l == L - 1) above = T(0);
 
@@ -436,16 +500,7 @@ __device__ __forceinline__ void line_solve(const Geom& g, const Col& c, int l, i
         z[t] = Q;
         pi[t] = P;
     }
-    for (int d = 1; d < L; d <<= 1) {   // inclusive scan of (P, Q) across the segment
-        const T Pp = __shfl_up(P, d, L);
-        const T Qp = __shfl_up(Q, d, L);
-        if (l >= d) {
-            Q = P * Qp + Q;
-            P = P * Pp;
-        }
-    }
-    T carry = __shfl_up(Q, 1, L);
-    if (l == 0) carry = T(0);
+    T carry = segment_carry<true>(P, Q, l, L);
 #pragma unroll
     for (int t = 0; t < M; ++t) z[t] += pi[t] * carry;
 
@@ -459,16 +514,7 @@ __device__ __forceinline__ void line_solve(const Geom& g, const Col& c, int l, i
         z[t] = Q;
         pi[t] = P;
     }
-    for (int d = 1; d < L; d <<= 1) {   // reverse scan across the segment
-        const T Pn = __shfl_down(P, d, L);
-        const T Qn = __shfl_down(Q, d, L);
-        if (l + d < L) {
-            Q = P * Qn + Q;
-            P = P * Pn;
-        }
-    }
-    carry = __shfl_down(Q, 1, L);
-    if (l == L - 1) carry = T(0);
+    carry = segment_carry<false>(P, Q, l, L);
 #pragma unroll
     for (int t = 0; t < M; ++t) z[t] += pi[t] * carry;
 }

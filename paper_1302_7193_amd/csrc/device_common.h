@@ -19,11 +19,58 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
     return x * q + (x < r ? x : r) + i;
 }
 
+// ------------------------------------------------------ cross-lane moves --
+// DPP controls (GFX9): row_shr:d / row_shl:d move within rows of 16 lanes,
+// wave_shr:1 / wave_shl:1 across the whole wavefront by one lane.  A lane
+// reads another lane's register directly, without the LDS round trip of a
+// permute.
+constexpr int kRowShr = 0x110, kRowShl = 0x100, kWaveShr1 = 0x138, kWaveShl1 = 0x130;
+// quad_perm [1,0,3,2] and [2,3,0,1]; row_ror:n rotates within a row by n.
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kRowRor = 0x120;
+
+// Lane i receives x from the lane CTRL names; lanes without a source lane
+// (past the row or wavefront edge) receive id.
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T x, T id)
+{
+    if constexpr (sizeof(T) == 8) {
+        const int64_t xb = __builtin_bit_cast(int64_t, x), ib = __builtin_bit_cast(int64_t, id);
+        const int lo = __builtin_amdgcn_update_dpp((int)ib, (int)xb, CTRL, 0xF, 0xF, false);
+        const int hi =
+            __builtin_amdgcn_update_dpp((int)(ib >> 32), (int)(xb >> 32), CTRL, 0xF, 0xF, false);
+        return __builtin_bit_cast(T, ((int64_t)hi << 32) | (int64_t)(uint32_t)lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, id),
+                                                                 __builtin_bit_cast(int, x), CTRL,
+                                                                 0xF, 0xF, false));
+    }
+}
+
+// The value of x in lane `lane` (a constant), as a wavefront-uniform value.
+template <typename T>
+__device__ __forceinline__ T read_lane(T x, int lane)
+{
+    if constexpr (sizeof(T) == 8) {
+        const int64_t xb = __builtin_bit_cast(int64_t, x);
+        const int lo = __builtin_amdgcn_readlane((int)xb, lane);
+        const int hi = __builtin_amdgcn_readlane((int)(xb >> 32), lane);
+        return __builtin_bit_cast(T, ((int64_t)hi << 32) | (int64_t)(uint32_t)lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
+    }
+}
+
+// Sum over the wavefront in a fixed order, the same bits in every lane:
+// within each row of 16 lanes a quad butterfly and rotations by 4 and 8
+// lanes (lane 0 of a row ends with ((q0 + q1) + (q2 + q3)) of its quads'
+// sums), then the four rows' sums from lanes 0, 16, 32, 48.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v += dpp_move<kQuadXor1>(v, 0.0);
+    v += dpp_move<kQuadXor2>(v, 0.0);
+    v += dpp_move<kRowRor + 4>(v, 0.0);
+    v += dpp_move<kRowRor + 8>(v, 0.0);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // Sum NV per-thread values over the workgroup in a fixed order; the totals
