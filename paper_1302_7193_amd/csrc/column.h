@@ -31,7 +31,8 @@
 // its coefficients per column): the scaled pivots delta_k obey the continued
 // fraction delta_k = g_k - pi_k / delta_{k-1}, a Moebius map of delta_{k-1}.
 // Each lane composes the maps of its levels as a 2x2 matrix, the segment
-// scans those matrices across lanes (rescaled by powers of two), and each
+// scans those matrices across lanes (rescaled by powers of two; within rows
+// of 16 lanes, then across rows from the rows' products), and each
 // lane then runs the recurrence over its own levels from the pivot entering
 // them.
 //
@@ -404,6 +405,35 @@ __device__ __forceinline__ void rescale(T& e00, T& e01, T& e10, T& e11)
     e11 = ldexp(e11, -ex);
 }
 
+// The same for a vector.
+__device__ __forceinline__ void rescale_vec(double& v0, double& v1)
+{
+    int ex;
+    (void)frexp(fmax(fabs(v0), fabs(v1)), &ex);
+    v0 = ldexp(v0, -ex);
+    v1 = ldexp(v1, -ex);
+}
+
+// One step of the within-row scan of 2x2 matrices (later lanes on the left):
+// compose with the product D lanes below; lanes whose partner lies below
+// their row (identity) or segment keep theirs.
+template <int D>
+__device__ __forceinline__ void mobius_step(double& e00, double& e01, double& e10, double& e11,
+                                            int l)
+{
+    const double f00 = dpp_move<kRowShr + D>(e00, 1.0), f01 = dpp_move<kRowShr + D>(e01, 0.0);
+    const double f10 = dpp_move<kRowShr + D>(e10, 0.0), f11 = dpp_move<kRowShr + D>(e11, 1.0);
+    if (l >= D) {
+        const double n00 = e00 * f00 + e01 * f10, n01 = e00 * f01 + e01 * f11;
+        const double n10 = e10 * f00 + e11 * f10, n11 = e10 * f01 + e11 * f11;
+        e00 = n00;
+        e01 = n01;
+        e10 = n10;
+        e11 = n11;
+        rescale(e00, e01, e10, e11);
+    }
+}
+
 // LU factors of one stretched-grid column on this lane's levels.  Scaled by
 // 1/|T| the block is tridiag(c, s - (alpha_T/|T|) d, b); its pivots are
 // D_k = s_k delta_k with delta_k = g_k - pi_k / delta_{k-1} (delta_{-1}
@@ -439,23 +469,51 @@ __device__ __forceinline__ void gen_factors(const Col& c, int l, int L, int k0, 
             rescale(e00, e01, e10, e11);
         }
     }
-    // inclusive scan across the segment: lane l ends with the product over
-    // lanes l, l-1, ..., 0
-    for (int d = 1; d < L; d <<= 1) {
-        const double f00 = __shfl_up(e00, d, L), f01 = __shfl_up(e01, d, L);
-        const double f10 = __shfl_up(e10, d, L), f11 = __shfl_up(e11, d, L);
-        if (l >= d) {
-            const double n00 = e00 * f00 + e01 * f10, n01 = e00 * f01 + e01 * f11;
-            const double n10 = e10 * f00 + e11 * f10, n11 = e10 * f01 + e11 * f11;
-            e00 = n00;
-            e01 = n01;
-            e10 = n10;
-            e11 = n11;
-            rescale(e00, e01, e10, e11);
+    // inclusive scan within rows of 16 lanes: lane l ends with the product
+    // over the lanes from its row's (or segment's) start up to l
+    if (L > 1) mobius_step<1>(e00, e01, e10, e11, l);
+    if (L > 2) mobius_step<2>(e00, e01, e10, e11, l);
+    if (L > 4) mobius_step<4>(e00, e01, e10, e11, l);
+    if (L > 8) mobius_step<8>(e00, e01, e10, e11, l);
+    // the lanes below this one within its row (identity at a row start) ...
+    const double x00 = dpp_move<kRowShr + 1>(e00, 1.0), x01 = dpp_move<kRowShr + 1>(e01, 0.0);
+    const double x10 = dpp_move<kRowShr + 1>(e10, 0.0), x11 = dpp_move<kRowShr + 1>(e11, 1.0);
+    // ... applied to what the rows below it in the segment make of
+    // delta_{-1} = (1, 0), from the rows' products
+    double v0 = 1.0, v1 = 0.0;
+    if (L > 16) {
+        const int row = (threadIdx.x & (kWave - 1)) >> 4;
+        const double a00 = read_lane(e00, 15), a10 = read_lane(e10, 15);
+        if (L == 32) {
+            const double c00 = read_lane(e00, 47), c10 = read_lane(e10, 47);
+            if (row == 1) {
+                v0 = a00;
+                v1 = a10;
+            } else if (row == 3) {
+                v0 = c00;
+                v1 = c10;
+            }
+        } else {
+            double w0 = read_lane(e00, 31) * a00 + read_lane(e01, 31) * a10;
+            double w1 = read_lane(e10, 31) * a00 + read_lane(e11, 31) * a10;
+            rescale_vec(w0, w1);
+            double y0 = read_lane(e00, 47) * w0 + read_lane(e01, 47) * w1;
+            double y1 = read_lane(e10, 47) * w0 + read_lane(e11, 47) * w1;
+            rescale_vec(y0, y1);
+            if (row == 1) {
+                v0 = a00;
+                v1 = a10;
+            } else if (row == 2) {
+                v0 = w0;
+                v1 = w1;
+            } else if (row == 3) {
+                v0 = y0;
+                v1 = y1;
+            }
         }
     }
     // pivot entering this lane: the lanes below applied to delta_{-1} = (1, 0)
-    const double b00 = __shfl_up(e00, 1, L), b10 = __shfl_up(e10, 1, L);
+    const double b00 = x00 * v0 + x01 * v1, b10 = x10 * v0 + x11 * v1;
     double inv_prev = l == 0 ? 0.0 : b10 / b00;
 #pragma unroll
     for (int t = 0; t < M; ++t) {
