@@ -117,7 +117,9 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(ColArgs a)
         T acc[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[i] = T(0);
-#pragma unroll
+        // two children at a time: all four at once held 137 VGPRs (3 waves
+        // per SIMD) and ran 1 % slower over the V-cycle
+#pragma unroll 2
         for (int child = 0; child < 4; ++child) {
             const Col c = make_col_ij<G>(gf, 2 * cp.i + (child >> 1), 2 * cp.j + (child & 1),
                                          cp.ok, a.hgeo2);
