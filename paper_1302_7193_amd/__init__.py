@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 import torch  # loads the HIP runtime libpcg.so links against
 
@@ -235,9 +236,11 @@ class Problem:
                    "pcg_problem_create_stretched")
         self.handle = h
 
-    def __del__(self):
+    def __del__(self, _sys=sys):
+        # at interpreter exit the module's globals may already be gone and
+        # the process releases the device memory anyway
         h = getattr(self, "handle", None)
-        if h:
+        if h and not _sys.is_finalizing():
             _lib.pcg_problem_destroy(h)
             self.handle = None
 
