@@ -22,7 +22,10 @@
  *   device that was current when the problem was created), owned by the
  *   caller, 16-byte aligned (PCG_E_INVALID otherwise), never retained after
  *   return.
- *   Host pointers are accepted only where the argument name ends in _host.
+ *   Host pointers are accepted only where the argument name ends in _host,
+ *   for descriptor, option, tuning and result structs, and where the
+ *   description says host array (the widths of
+ *   pcg_problem_create_stretched, the pointer array of pcg_stream_probe).
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
  *   stream).  pcg_apply/pcg_precond/pcg_csr_* are asynchronous on it;
  *   pcg_solve and pcg_solve_batched block until the solve has finished.
