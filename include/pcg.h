@@ -151,7 +151,7 @@ typedef struct pcg_server pcg_server;   /* opaque */
 
 /* Default options: rtol 1e-8, atol 0, max_iter 10000, FP64, inner_rtol 3e-5,
  * max_outer 20, fused, graph_chunk -1, no profiling, no true residual, x0
- * read from x. */
+ * read from x, the line preconditioner (mg_levels 0). */
 void pcg_default_opts(pcg_solve_opts *opts);
 
 /* Fill a descriptor for the unit square (dx = 1/n_x, dy = 1/n_y), height 1,
@@ -207,16 +207,16 @@ pcg_status pcg_precond(pcg_problem *p, int32_t dtype, const void *r, void *z, vo
  * bytes of device memory (16-byte aligned) for the coarse levels and one
  * fine-level vector.  pcg_mg_levels: the number of levels the grid allows.
  * Asynchronous on stream. */
-/* Block Gauss-Seidel preconditioner alone: z = M^{-1} r for the symmetric
- * red-black block Gauss-Seidel M (see PCG_PRECOND_RBGS).  r and z: n values
- * of dtype, distinct.  Asynchronous on stream. */
-pcg_status pcg_rbgs_precond(pcg_problem *p, int32_t dtype, const void *r, void *z, void *stream);
-
 int32_t pcg_mg_levels(const pcg_problem *p);
 size_t pcg_mg_bytes(const pcg_problem *p, int32_t dtype, int32_t mg_levels);
 pcg_status pcg_mg_precond(pcg_problem *p, int32_t dtype, const void *r, void *z,
                           int32_t mg_levels, void *workspace, size_t workspace_bytes,
                           void *stream);
+
+/* Block Gauss-Seidel preconditioner alone: z = M^{-1} r for the symmetric
+ * red-black block Gauss-Seidel M (see PCG_PRECOND_RBGS).  r and z: n values
+ * of dtype, distinct.  Asynchronous on stream. */
+pcg_status pcg_rbgs_precond(pcg_problem *p, int32_t dtype, const void *r, void *z, void *stream);
 
 /* Solve A x = b.  b, x: n FP64 values; x holds x0 on entry and the solution
  * on return.  workspace: at least pcg_workspace_bytes(p, opts, 1) bytes of
@@ -243,8 +243,9 @@ pcg_status pcg_solve_batched(pcg_problem *p, int32_t nrhs, const double *b, doub
  *   lanes_per_column  L: a column is handled by L lanes of a 64-wide
  *                     wavefront, each owning ceil(n_z/L) (rounded up to a
  *                     power of two, at most 16) consecutive levels; the
- *                     line solve combines the L pieces with a log2(L)-step
- *                     in-wave scan (the sub-structuring of Sec. 6.1).
+ *                     line solve combines the L pieces with an in-wave
+ *                     scan (DPP moves within rows of 16 lanes, then across
+ *                     rows; the sub-structuring of Sec. 6.1).
  *                     Power of two, 1 <= L <= 64, 16*L >= n_z.
  *   block_cap         workgroups per right-hand side (>= 1, <= 65536; default
  *                     16384); each walks a contiguous range of column tiles.
@@ -272,8 +273,10 @@ pcg_status pcg_get_tuning(const pcg_problem *p, int32_t dtype, pcg_tuning *out);
 pcg_status pcg_set_tuning(pcg_problem *p, int32_t dtype, const pcg_tuning *t);
 
 /* Tuning cache: launch parameters keyed by (GPU architecture, uniform or
- * stretched horizontal grid, n_x, n_y, n_z, dtype, nrhs).  Loaded on first use from tuning_cache.txt next to
- * libpcg.so, or from the file named by the PCG_TUNING_CACHE environment
+ * stretched horizontal grid, n_x, n_y, n_z, dtype, nrhs).  Loaded on first
+ * use from tuning_cache.txt next to libpcg.so (regenerate it with
+ * python -m paper_1302_7193_amd.make_tuning_cache), or from the file
+ * named by the PCG_TUNING_CACHE environment
  * variable (empty: none).  A solve of nrhs right-hand sides uses the entry
  * for its shape unless the problem's tuning was set explicitly
  * (pcg_set_tuning, pcg_autotune); pcg_get_tuning reports the tuning a
@@ -283,14 +286,14 @@ pcg_status pcg_set_tuning(pcg_problem *p, int32_t dtype, const pcg_tuning *t);
 pcg_status pcg_tuning_cache_load(const char *path);
 pcg_status pcg_tuning_cache_save(const char *path);
 
-/* Autotuner: times fused iterations (kernels A and B over nrhs right-hand
- * sides, on synthetic vectors) for every supported lanes_per_column, a
- * ladder of block caps and both reduction modes, timing kernel A and kernel
- * B (each with its reduction) separately, keeps the fastest launch shape of
- * each and the reduction mode with the fastest pair for (p, dtype), records it in the tuning cache for (shape, dtype, nrhs) and
- * returns it in best (may be NULL).  A set-up utility: it
- * allocates (and frees) its own device scratch of about 5 vectors of
- * nrhs*n values of dtype.  Blocks. */
+/* Autotuner: times kernels A and B of the fused iteration (each with its
+ * reduction, over nrhs right-hand sides, on synthetic vectors) for every
+ * supported lanes_per_column, a ladder of block caps and both reduction
+ * modes; keeps the three fastest launch shapes of each kernel per mode,
+ * times the nine pairs together and takes the fastest pair for (p, dtype);
+ * records it in the tuning cache for (shape, dtype, nrhs) and returns it in
+ * best (may be NULL).  A set-up utility: it allocates (and frees) its own
+ * device scratch of about 5 vectors of nrhs*n values of dtype.  Blocks. */
 pcg_status pcg_autotune(pcg_problem *p, int32_t dtype, int32_t nrhs, void *stream,
                         pcg_tuning *best);
 
