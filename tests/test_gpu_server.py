@@ -1,5 +1,6 @@
 """Serving runtime on the GPU, through the C ABI: results identical alone and
-in a concurrent mix of different grids (and identical to a direct solve),
+in a concurrent mix of different grids (line, multigrid, block Gauss-Seidel
+and automatically chosen preconditioners; and identical to a direct solve),
 admission by HBM budget, rejection of requests that can never fit,
 cancellation of queued requests.  Accuracy of every served result is checked
 with the oracle's assembled matrix."""
@@ -22,13 +23,13 @@ SHAPES = [(32, 32, 32, 1e2), (48, 40, 64, 1e4), (16, 16, 128, 1e5), (64, 64, 32,
           (24, 20, 100, 1e3), (40, 40, 16, 1e2), (20, 36, 64, 5e4), (32, 32, 32, 1e2)]
 
 
-def requests(precision=pcg.PCG_PREC_MIXED):
+def requests(precision=pcg.PCG_PREC_MIXED, preconditioner=pcg.PCG_PRECOND_LINE):
     out = []
     for rid, (nx, ny, nz, g2) in enumerate(SHAPES):
         d = pcg.pcg_desc_from_ratio(nx, ny, nz, 1.05, g2, pcg.PCG_BC_DIRICHLET)
         b = si.rhs_uniform(nx, ny, nz, 1000 + rid)
         out.append((d, b))
-    return out, pcg.pcg_default_opts(precision=precision)
+    return out, pcg.pcg_default_opts(precision=precision, preconditioner=preconditioner)
 
 
 def serve(reqs, opts, max_active, budget=None, one_at_a_time=False):
@@ -66,9 +67,12 @@ def serve(reqs, opts, max_active, budget=None, one_at_a_time=False):
     return xs, res, stats, need
 
 
-@pytest.mark.parametrize("precision", [pcg.PCG_PREC_MIXED, pcg.PCG_PREC_FP64])
-def test_results_identical_alone_and_in_the_mix(precision):
-    reqs, opts = requests(precision)
+@pytest.mark.parametrize("precision,preconditioner", [
+    (pcg.PCG_PREC_MIXED, pcg.PCG_PRECOND_LINE), (pcg.PCG_PREC_FP64, pcg.PCG_PRECOND_LINE),
+    (pcg.PCG_PREC_FP64, pcg.PCG_PRECOND_MG), (pcg.PCG_PREC_MIXED, pcg.PCG_PRECOND_RBGS),
+    (pcg.PCG_PREC_FP64, pcg.PCG_PRECOND_AUTO)])
+def test_results_identical_alone_and_in_the_mix(precision, preconditioner):
+    reqs, opts = requests(precision, preconditioner)
     alone, ra, _, _ = serve(reqs, opts, max_active=1, one_at_a_time=True)
     mixed, rm, stats, _ = serve(reqs, opts, max_active=4)
     assert stats["completed"] == len(reqs) and stats["peak_bytes_in_use"] > 0
