@@ -493,7 +493,7 @@ def serving(pcg, si, torch, n_requests=512, max_active=4, preconditioner=0):
                 input="device-resident right-hand sides (pcg_submit_device)")
 
 
-def cpu_baseline(n_iter=2):
+def cpu_baseline(n_iter=10):
     """Oracle (plain C, FP64, one thread) on the same 512 x 512 x 128 problem:
     assembly, then a fixed number of PCG iterations."""
     import oracle
