@@ -171,8 +171,9 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
 
 // Kernel A (Alg. InterleavedApply): u += alpha p; p = z + beta p;
 // q = A z + beta q; sigma = <p,q> (FP64); scalar step: alpha.
-// FIRST: alpha = 0 and p = q = 0, so p = z, q = A z, and u keeps x0 (written
-// as zero for a zero start); u, p and q are not read.
+// FIRST: alpha = 0 and p = q = 0, so p = z, q = A z, and u keeps x0 (for a
+// zero start u stays unwritten until the next launch sets u = alpha p); u, p
+// and q are not read.
 template <typename T, int M, bool V, bool FIRST, bool G, bool NT, bool W>
 __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* s, int64_t rhs,
                                                  int64_t blk, double (&acc)[1])
@@ -186,7 +187,9 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
     T* q = static_cast<T*>(a.io4) + off;
     const T* vert = static_cast<const T*>(a.vert);
     const T alpha = T(s->alpha), beta = T(s->beta);
-    const bool zero_u = FIRST && s->zero_start;
+    // zero start: u is not written by the first launch (it would be zero)
+    // and the second sets u = alpha p instead of reading it
+    const bool u_unset = s->zero_start && s->iter == 1;
     const Lane p = lane_pos<M>(L);
     const VertCoef<T, M> vc = load_vert<T, M, V>(g, vert, p.k0);
     int64_t t0, t1;
@@ -203,15 +206,14 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
                 qc[i] = az[i];
                 acc[0] += double(pc[i]) * double(qc[i]);
             }
-            if (zero_u) {
-                T zero[M];
-#pragma unroll
-                for (int i = 0; i < M; ++i) zero[i] = T(0);
-                st<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, zero);
-            }
         } else {
             T uc[M];
-            ld<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, uc);
+            if (u_unset) {
+#pragma unroll
+                for (int i = 0; i < M; ++i) uc[i] = T(0);
+            } else {
+                ld<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, uc);
+            }
             ld<T, M, V, NT>(pp, c.idx, c.ok, p.k0, g.nz, pc);
             ld<T, M, V, NT>(q, c.idx, c.ok, p.k0, g.nz, qc);
 #pragma unroll
@@ -263,6 +265,8 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
                          (s->flag == kBreakdown && none);
     if (!stopped || s->fixed) return;
     if (none && !s->zero_start) return;
+    // zero start stopped after one iteration: kernel A has not written u yet
+    const bool u_unset = s->zero_start && s->iter == 1;
     const int64_t off = rhs * g.n;
     T* u = static_cast<T*>(a.io0) + off;
     const T* pp = static_cast<const T*>(a.io3) + off;
@@ -278,7 +282,12 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
             for (int i = 0; i < M; ++i) uc[i] = T(0);
         } else {
             T pc[M];
-            ld<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, uc);
+            if (u_unset) {
+#pragma unroll
+                for (int i = 0; i < M; ++i) uc[i] = T(0);
+            } else {
+                ld<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, uc);
+            }
             ld<T, M, V, NT>(pp, c.idx, c.ok, p.k0, g.nz, pc);
 #pragma unroll
             for (int i = 0; i < M; ++i) uc[i] += alpha * pc[i];
