@@ -35,16 +35,16 @@ PEAK_HBM_GBPS = 8000.0
 # The first kernel B of a zero-start solve reads b instead of r and q (24 B),
 # the first kernel A reads only z (32 B).
 BYTES = {"fused_apply": 56, "fused_prec": 32, "iteration": 88, "unfused_iteration": 160,
-         "apply": 16, "precond": 16, "fused_apply_first": 24, "fused_apply_second": 48,
+         "apply": 16, "precond": 16, "fused_apply_first": 16, "fused_apply_second": 48,
          "fused_prec_first": 24}
 
 
 def solve_kernel_bytes(kernel, iterations, n):
     """Algorithmic bytes of all launches of a fused kernel in one zero-start
     solve of `iterations` iterations (A runs k times, B k+1 times).  A's
-    first launch reads z and writes p and q (u, zero, is not written), its
-    second reads p, q, z and writes u, p, q (u is not read), later ones move
-    all seven vectors."""
+    first launch reads z and writes q (u, zero, is not written; p = z is
+    not stored: z's vector serves as p), its second reads p, q, z and
+    writes u, p, q (u is not read), later ones move all seven vectors."""
     if kernel == "fused_apply":
         if iterations <= 1:
             return n * BYTES["fused_apply_first"] * iterations

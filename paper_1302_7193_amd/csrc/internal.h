@@ -168,6 +168,11 @@ struct ColArgs {
     Geom g2;
     const double* hgeo2;
     double omega;
+    // fused iteration with the line preconditioner: kernel A's first launch
+    // does not store p = z (z stays in io2 and serves as that p); from the
+    // first iteration on kernel B writes z into io3 and kernel A keeps p in
+    // io2 (in place), so the two vectors swap roles
+    int zswap;
 };
 
 // Multigrid kernels (mg.hip): kernel for a Kind in MgPre..MgSmoothFinal, or

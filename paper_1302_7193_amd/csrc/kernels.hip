@@ -124,7 +124,7 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
     const T* src = static_cast<const T*>(from_b ? a.in1 : a.io1) + off;
     T* r = static_cast<T*>(a.io1) + off;
     const bool store_r = !(from_b && a.in1 == a.io1);
-    T* z = static_cast<T*>(a.io2) + off;
+    T* z = static_cast<T*>((a.zswap && !FIRST) ? a.io3 : a.io2) + off;
     const T* q = static_cast<const T*>(a.io4) + off;
     const T* lu = static_cast<const T*>(a.lu);
     const T alpha = T(s->alpha);
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
 // q = A z + beta q; sigma = <p,q> (FP64); scalar step: alpha.
 // FIRST: alpha = 0 and p = q = 0, so p = z, q = A z, and u keeps x0 (for a
 // zero start u stays unwritten until the next launch sets u = alpha p); u, p
-// and q are not read.
+// and q are not read, and with zswap p = z is not stored (ColArgs::zswap).
 template <typename T, int M, bool V, bool FIRST, bool G, bool NT, bool W>
 __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* s, int64_t rhs,
                                                  int64_t blk, double (&acc)[1])
@@ -182,8 +182,10 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
     const int L = W ? kWave : a.L;
     const int64_t off = rhs * g.n;
     T* u = static_cast<T*>(a.io0) + off;
-    const T* z = static_cast<const T*>(a.io2) + off;
-    T* pp = static_cast<T*>(a.io3) + off;
+    // z and p trade places after the first launch when zswap is set
+    const bool swapped = a.zswap && !FIRST;
+    const T* z = static_cast<const T*>(swapped ? a.io3 : a.io2) + off;
+    T* pp = static_cast<T*>(swapped ? a.io2 : a.io3) + off;
     T* q = static_cast<T*>(a.io4) + off;
     const T* vert = static_cast<const T*>(a.vert);
     const T alpha = T(s->alpha), beta = T(s->beta);
@@ -225,7 +227,7 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
             }
             st<T, M, V, NT>(u, c.idx, c.ok, p.k0, g.nz, uc);
         }
-        st<T, M, V, NT>(pp, c.idx, c.ok, p.k0, g.nz, pc);
+        if (!(FIRST && a.zswap)) st<T, M, V, NT>(pp, c.idx, c.ok, p.k0, g.nz, pc);
         st<T, M, V, NT>(q, c.idx, c.ok, p.k0, g.nz, qc);
     }
 }
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
     const bool u_unset = s->zero_start && s->iter == 1;
     const int64_t off = rhs * g.n;
     T* u = static_cast<T*>(a.io0) + off;
-    const T* pp = static_cast<const T*>(a.io3) + off;
+    const T* pp = static_cast<const T*>(a.zswap ? a.io2 : a.io3) + off;
     const T alpha = T(s->alpha);
     const Lane p = lane_pos<M>(L);
     int64_t t0, t1;

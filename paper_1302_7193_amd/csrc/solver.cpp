@@ -533,10 +533,15 @@ struct RunInfo {
 // at a.st must hold fresh_state() values with zero_start set as `zero_start`
 // (x0 = 0: x is not read and the first kernel B takes r from b = a.in1).
 template <typename T>
-pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a, int64_t nrhs,
+pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_in, int64_t nrhs,
                      bool zero_start, const pcg_solve_opts& o, char* ws, const Layout& w,
                      SolverState* host_states, RunInfo& info, hipStream_t s)
 {
+    // line preconditioner: z and p trade vectors after the first kernel A,
+    // which then need not store p = z (the other preconditioners' kernels
+    // write z into io2 throughout)
+    ColArgs a = a_in;
+    a.zswap = o.preconditioner == PCG_PRECOND_LINE ? 1 : 0;
     Phase bph;
     if (b_phase<T>(P, dtype, a, nrhs, o, ws, w, bph) != PCG_OK) return PCG_E_DEVICE;
     const int bkind = o.preconditioner == PCG_PRECOND_MG ? 100 + w.mg_levels : o.preconditioner;
