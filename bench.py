@@ -36,7 +36,7 @@ PEAK_HBM_GBPS = 8000.0
 # the first kernel A reads only z (32 B).
 BYTES = {"fused_apply": 56, "fused_prec": 32, "iteration": 88, "unfused_iteration": 160,
          "apply": 16, "precond": 16, "fused_apply_first": 16, "fused_apply_second": 48,
-         "fused_prec_first": 24}
+         "fused_prec_first": 16}
 
 
 def solve_kernel_bytes(kernel, iterations, n):

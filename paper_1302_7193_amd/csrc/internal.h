@@ -171,7 +171,8 @@ struct ColArgs {
     // fused iteration with the line preconditioner: kernel A's first launch
     // does not store p = z (z stays in io2 and serves as that p); from the
     // first iteration on kernel B writes z into io3 and kernel A keeps p in
-    // io2 (in place), so the two vectors swap roles
+    // io2 (in place), so the two vectors swap roles.  On a zero start kernel
+    // B's first launch does not copy b into r: its second reads b (in1)
     int zswap;
 };
 

@@ -110,8 +110,10 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
 // Kernel B (Alg. InterleavedPrec): r -= alpha q; z = M^{-1} r;
 // R = <r,r>, kappa = <r,z> (FP64 accumulation); scalar step: exit test, beta.
 // FIRST (no iteration done yet): alpha = 0 and q is unset, so q is not read;
-// with a zero start r is taken from b (no start-up kernel), and not stored
-// when b is r itself.
+// with a zero start r is taken from b (no start-up kernel).  The first launch
+// leaves r unchanged and does not store it: r is already in io1 (a start-up
+// kernel wrote it, or b is r itself), or, with the line preconditioner
+// (ColArgs::zswap), the second launch reads b again.
 // W: one column per wavefront (L = 64, column index scalar).
 template <typename T, int M, bool V, bool FIRST, bool G, bool NT, bool W>
 __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s, int64_t rhs,
@@ -120,10 +122,10 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     const int64_t off = rhs * g.n;
-    const bool from_b = FIRST && s->zero_start;
+    const bool from_b = s->zero_start && (FIRST || (a.zswap && s->iter == 1));
     const T* src = static_cast<const T*>(from_b ? a.in1 : a.io1) + off;
     T* r = static_cast<T*>(a.io1) + off;
-    const bool store_r = !(from_b && a.in1 == a.io1);
+    const bool store_r = !FIRST || (from_b && a.in1 != a.io1 && !a.zswap);
     T* z = static_cast<T*>((a.zswap && !FIRST) ? a.io3 : a.io2) + off;
     const T* q = static_cast<const T*>(a.io4) + off;
     const T* lu = static_cast<const T*>(a.lu);
@@ -144,7 +146,7 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
         }
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[0] += double(rc[i]) * double(rc[i]);
-        if (!FIRST || store_r) st<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
+        if (store_r) st<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
         line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, rc, zc);
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[1] += double(rc[i]) * double(zc[i]);
