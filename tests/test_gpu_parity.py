@@ -186,6 +186,34 @@ def test_fp64_solve_converges_like_oracle(name, fused):
     assert abs(res["rel_res_true"] - true) <= 1e-3 * true + 1e-13
 
 
+@pytest.mark.parametrize("name", SOLVE_GRIDS)
+@pytest.mark.parametrize("gc", [3, 0])
+def test_fp64_zero_start_equal_iterations(name, gc):
+    """x0 = 0 without reading x (x filled with NaN), the benchmark's path:
+    kernel A's first launch leaves u unwritten and does not store p = z,
+    kernel B's first launch does not copy b into r; stopped after one, two
+    and all iterations (the exit correction after one iteration sets
+    u = alpha p), graph chunks and direct launches, against the oracle."""
+    d = GRIDS[name]()
+    print("zero start", name, gc, flush=True)
+    b = si.rhs_uniform(d.nx, d.ny, d.nz, 5)
+    A = oracle.assemble(grid_of(d))
+    M = oracle.line_blocks(A, d.nz)
+    k = oracle.pcg(A, M, b, rtol=1e-8)["iterations"]
+    p = pcg.Problem(d)
+    bt = cuda(b)
+    for kk in sorted({1, min(2, k), k}):
+        ref = oracle.pcg(A, M, b, rtol=0.0, max_iter=kk)
+        o = pcg.pcg_default_opts(rtol=0.0, max_iter=kk, x0_zero=1, graph_chunk=gc)
+        x = torch.full_like(bt, float("nan"))
+        st, res = pcg.pcg_solve(p, bt, x, pcg.workspace(p, o), o)
+        assert res["iterations"] == ref["iterations"], (kk, res["iterations"])
+        xs = x.cpu().numpy()
+        err = np.linalg.norm(xs - ref["x"]) / max(np.linalg.norm(ref["x"]), 1e-300)
+        assert err <= 1e-10, (kk, err)
+        assert np.array_equal(b, bt.cpu().numpy())    # b is never written
+
+
 def test_fused_and_unfused_iterates_agree():
     d = GRIDS["64x64x32-dir"]()
     b = si.rhs_uniform(64, 64, 32, 5)
@@ -277,7 +305,8 @@ def test_mixed_precision_reaches_fp64_tolerance(name):
 
 
 @pytest.mark.parametrize("precision", [pcg.PCG_PREC_FP64, pcg.PCG_PREC_MIXED])
-def test_batched_equals_single_solves(precision):
+@pytest.mark.parametrize("x0z", [0, 1])
+def test_batched_equals_single_solves(precision, x0z):
     d = GRIDS["13x7x33-dir-ragged"]()
     p = pcg.Problem(d)
     n = p.n
@@ -285,7 +314,7 @@ def test_batched_equals_single_solves(precision):
     B = np.stack([si.rhs_uniform(d.nx, d.ny, d.nz, 100 + s) for s in range(nrhs)])
     B[2] *= 1e-3            # different scales and one zero right-hand side
     B[4] = 0.0
-    o = pcg.pcg_default_opts(precision=precision)
+    o = pcg.pcg_default_opts(precision=precision, x0_zero=x0z)
     bt = cuda(B.ravel())
     x = torch.zeros_like(bt)
     ws = pcg.workspace(p, o, nrhs)
@@ -294,7 +323,7 @@ def test_batched_equals_single_solves(precision):
     X = x.cpu().numpy().reshape(nrhs, n)
     A = oracle.assemble(grid_of(d))
     for s in range(nrhs):
-        xs, sts, rs = gpu_solve(d, B[s], precision=precision)
+        xs, sts, rs = gpu_solve(d, B[s], precision=precision, x0_zero=x0z)
         assert res[s]["status"] == sts == pcg.PCG_OK
         assert res[s]["iterations"] == rs["iterations"]
         np.testing.assert_array_equal(X[s], xs)
