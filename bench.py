@@ -549,7 +549,7 @@ def _working(values, frac=0.1):
     return [v for v in values if v >= frac * top]
 
 
-def summarize_rocprof(directory, kernel_filter="k_fused|k_init|k_fixup|k_finalize|k_mg|copy|elementwise"):
+def summarize_rocprof(directory, kernel_filter="k_fused|k_init|k_fixup|k_finalize|k_mg|k_rb|copy|elementwise"):
     """Condense rocprofv3 CSV output under `directory` into a few lines:
     the per-kernel stats table, per-dispatch durations from the kernel trace
     (all dispatches and the ones that did work), and counter means."""
@@ -641,6 +641,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--rbgs-only", action="store_true",
+                    help="only FP64 block-Gauss-Seidel-preconditioned solves of 512x512x128 "
+                         "Dirichlet with anisotropy 1e2 (for profiler runs of its kernels)")
     ap.add_argument("--mg-only", action="store_true",
                     help="only FP64 multigrid-preconditioned solves of 512x512x128 Dirichlet "
                          "with anisotropy 1e2 (for profiler runs of the V-cycle kernels)")
@@ -679,17 +682,19 @@ def main():
     import synth_inputs as si
     torch.cuda.set_device(0)
 
-    if args.mg_only:
+    if args.mg_only or args.rbgs_only:
         d = pcg.pcg_desc_from_ratio(512, 512, 128, 1.05, 1e2, pcg.PCG_BC_DIRICHLET)
         P = pcg.Problem(d)
         b = torch.from_numpy(si.rhs_uniform(512, 512, 128, 1)).cuda()
         x = torch.empty_like(b)
-        o = pcg.pcg_default_opts(x0_zero=1, preconditioner=pcg.PCG_PRECOND_MG, graph_chunk=-1)
+        prec = pcg.PCG_PRECOND_MG if args.mg_only else pcg.PCG_PRECOND_RBGS
+        o = pcg.pcg_default_opts(x0_zero=1, preconditioner=prec, graph_chunk=-1)
         ws = pcg.workspace(P, o)
         ms, its, st, r = timed_solves(pcg, torch, P, b, x, ws, o, args.steps)
-        print(json.dumps(dict(workload="512x512x128 Dirichlet anisotropy 1e2, FP64 MG-PCG",
+        name = "MG" if args.mg_only else "RBGS"
+        print(json.dumps(dict(workload="512x512x128 Dirichlet anisotropy 1e2, FP64 %s-PCG" % name,
                               ms_per_solve=ms, iterations=its, status=pcg.STATUS_NAMES[st],
-                              levels=pcg.pcg_mg_levels(P))))
+                              levels=pcg.pcg_mg_levels(P) if args.mg_only else 1)))
         return
 
     log("main loop: %d warm-up + %d timed solves of 512x512x128" % (args.warmup, args.steps))
