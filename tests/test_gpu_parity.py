@@ -362,6 +362,45 @@ def test_full_size_periodic_workload_sampled():
     assert true < 1.05e-8
 
 
+def test_full_size_mixed_precision_1024():
+    """1024 x 1024 x 128 Dirichlet, anisotropy 1e4, smooth field + 1 % noise:
+    mixed precision (FP32 inner solves, FP64 refinement) at full size; the
+    returned x's residual from the oracle's assembled matrix."""
+    d = make_desc(1024, 1024, 128, 1e4)
+    g = grid_of(d)
+    b = si.rhs_smooth_noise(1024, 1024, 128, 2)
+    print("1024x1024x128 mixed", flush=True)
+    xs, st, res = gpu_solve(d, b, precision=pcg.PCG_PREC_MIXED, x0_zero=1)
+    assert st == pcg.PCG_OK, res
+    A = oracle.assemble(g)
+    true = oracle.residual_norm(A, b, xs) / np.linalg.norm(b)
+    print("1024x1024x128 mixed: %d inner iterations, %d refinements, true residual %.3e"
+          % (res["iterations"], res["outer_iterations"], true))
+    assert true < 1e-8
+
+
+def test_full_size_batched_64_right_hand_sides():
+    """64 right-hand sides (seeds 100..163) on 256 x 256 x 64 Dirichlet,
+    anisotropy 1e3, in one batched mixed-precision solve: every one converged,
+    eight of them checked against the oracle's assembled matrix."""
+    d = make_desc(256, 256, 64, 1e3)
+    p = pcg.Problem(d)
+    n, nrhs = p.n, 64
+    B = np.concatenate([si.rhs_uniform(256, 256, 64, 100 + s) for s in range(nrhs)])
+    o = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED, x0_zero=1)
+    bt = cuda(B)
+    x = torch.empty_like(bt)
+    print("batched 64 x 256x256x64", flush=True)
+    st, res = pcg.pcg_solve_batched(p, nrhs, bt, x, pcg.workspace(p, o, nrhs), o)
+    assert all(r["status"] == pcg.PCG_OK for r in res)
+    X = x.cpu().numpy().reshape(nrhs, n)
+    A = oracle.assemble(grid_of(d))
+    for s in range(0, nrhs, 8):
+        bs = B[s * n:(s + 1) * n]
+        true = oracle.residual_norm(A, bs, X[s]) / np.linalg.norm(bs)
+        assert true < 1e-8, (s, true)
+
+
 # ------------------------------------------------------------ tunings --
 
 def _lane_counts(nz):
