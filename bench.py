@@ -738,7 +738,12 @@ def main():
                      "frac": kern[dom]["achieved_GBps"] / PEAK_HBM_GBPS,
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes_per_launch"],
-                     "avg_launch_ms": kern[dom]["avg_ms"]},
+                     "avg_launch_ms": kern[dom]["avg_ms"],
+                     # HBM bytes the counters measured, at this run's launch time
+                     "measured_GBps": (traffic / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+                                       if traffic else None),
+                     "traffic_over_algorithmic": (traffic / kern[dom]["algorithmic_bytes_per_launch"]
+                                                  if traffic else None)},
         "kernels": kern,
         "algorithmic_GBps_per_iteration": BYTES["iteration"] * n * iters / el / 1e9,
         "kernel_source_sha256_16": kernel_source_hash(),
