@@ -57,7 +57,10 @@ __device__ __forceinline__ void scan_step(T& P, T& Q, int l, int L)
 {
     const T Pn = dpp_move<UP ? kRowShr + D : kRowShl + D>(P, T(1));
     const T Qn = dpp_move<UP ? kRowShr + D : kRowShl + D>(Q, T(0));
-    if (UP ? l >= D : l + D < L) {
+    // segments of 16 lanes or more are whole rows: the lanes whose partner
+    // lies outside the segment are exactly those past the row edge, which
+    // already received the identity
+    if (L >= 16 || (UP ? l >= D : l + D < L)) {
         Q = P * Qn + Q;
         P = P * Pn;
     }
@@ -78,7 +81,7 @@ __device__ __forceinline__ T segment_carry(T P, T Q, int l, int L)
     // this lane; the neighbour's composition, identity at an edge
     T Px = dpp_move<UP ? kRowShr + 1 : kRowShl + 1>(P, T(1));
     T Qx = dpp_move<UP ? kRowShr + 1 : kRowShl + 1>(Q, T(0));
-    if (UP ? l == 0 : l == L - 1) {
+    if (L < 16 && (UP ? l == 0 : l == L - 1)) {   // (a row edge for L >= 16)
         Px = T(1);
         Qx = T(0);
     }
