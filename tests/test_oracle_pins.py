@@ -375,3 +375,63 @@ def test_torch_generator_equals_numpy_generator_on_cpu():
         a = si.uniform_pm1(seed, n, start)
         b = si.uniform_pm1_torch(seed, n, start, device="cpu").numpy()
         np.testing.assert_array_equal(a, b)
+
+
+# ------------------------------------------------------ true residual ---
+# orc_residual_norm is what every full-size GPU check leans on (the exit test
+# of Alg. InterleavedPCG is on the 2-norm of r = b - A x), so it is pinned by
+# facts that do not come from the oracle's own CSR loop.
+
+@pytest.mark.parametrize("per", [False, True])
+def test_residual_norm_closed_form_on_eigenvectors(per):
+    # b = v (a closed-form eigenvector, A v = mu v) and x = c v give
+    # ||b - A x|| = |1 - c mu| ||v|| exactly in exact arithmetic: this pins
+    # the square root, the sign of A x and every term of the sum
+    g = oracle.Grid(6, 5, 8, 0.3, 0.45, 2.0, 1.0, 1.7, 55.0, per, per)
+    A = oracle.assemble(g)
+    dzu = g.H / g.nz
+    V = g.dx * g.dy * dzu
+    for mx, my, mz in [(1, 1, 1), (2, 3, 5), (5, 4, 8)]:
+        vx, lx = _mode(g.nx, mx, per)
+        vy, ly = _mode(g.ny, my, per)
+        vz, lz = _mode(g.nz, mz, False)
+        v = (vx[:, None, None] * vy[None, :, None] * vz[None, None, :]).ravel()
+        mu = V * (1 + g.kh * lx / g.dx**2 + g.kh * ly / g.dy**2 + g.kv * lz / dzu**2)
+        nv = np.sqrt(np.sum(v * v))
+        for c in (0.0, 0.25 / mu, 1.0 / mu, 3.0 / mu):
+            expect = abs(1.0 - c * mu) * nv
+            got = oracle.residual_norm(A, v, c * v)
+            assert abs(got - expect) <= 1e-12 * nv, (c * mu, got, expect)
+
+
+@pytest.mark.parametrize("g", small_grids(), ids=lambda g: f"{g.nx}x{g.ny}x{g.nz}")
+def test_residual_norm_equals_dense_product_and_is_homogeneous(g):
+    A = oracle.assemble(g)
+    D = dense(A)
+    rng = np.random.default_rng(17)
+    for _ in range(3):
+        b, x = rng.standard_normal(g.n), rng.standard_normal(g.n)
+        ref = np.linalg.norm(b - D @ x)
+        got = oracle.residual_norm(A, b, x)
+        assert abs(got - ref) <= 1e-13 * ref
+        # degree-one homogeneity (a sum of squares would scale by 4, a sum of
+        # absolute values would not match the dense 2-norm above)
+        assert abs(oracle.residual_norm(A, 2 * b, 2 * x) - 2 * got) <= 1e-13 * got
+        # x = 0: the norm of b itself
+        assert abs(oracle.residual_norm(A, b, np.zeros(g.n)) - np.linalg.norm(b)) <= \
+            1e-14 * np.linalg.norm(b)
+        # x = A^{-1} b from a dense solve: zero up to rounding
+        xd = np.linalg.solve(D, b)
+        assert oracle.residual_norm(A, b, xd) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_residual_norm_agrees_with_the_solvers_true_residual():
+    # orc_pcg reports ||b - A x|| / ||r0|| of its own iterate, computed in
+    # its own code; the stand-alone function must give the same number
+    for g in small_grids():
+        A = oracle.assemble(g)
+        b = si.rhs_uniform(g.nx, g.ny, g.nz, 6)
+        for k in (1, 2, 5):
+            res = oracle.pcg(A, oracle.line_blocks(A, g.nz), b, rtol=0.0, max_iter=k)
+            got = oracle.residual_norm(A, b, res["x"]) / res["r0"]
+            assert abs(got - res["rel_res_true"]) <= 1e-12 * res["rel_res_true"] + 1e-300
