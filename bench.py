@@ -23,6 +23,7 @@ import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -190,9 +191,38 @@ def timed_solves(pcg, torch, P, b, x, ws, opts, reps):
     return dt / reps * 1e3, its / reps, st, r
 
 
+class OracleSolve(threading.Thread):
+    """The oracle's FP64 solve of the 1024 x 1024 x 128 workload (smooth field
+    + 1 % noise, seed 2) to relative residual 1e-12, on a host thread while
+    the GPU extras run (the C oracle releases the interpreter lock): the
+    reference the mixed-precision and FP64 GPU solutions are compared with."""
+
+    def __init__(self):
+        super().__init__(daemon=True)
+        self.result, self.error, self.seconds = None, None, 0.0
+
+    def run(self):
+        try:
+            import oracle
+            import synth_inputs as si
+            t0 = time.perf_counter()
+            g = oracle.grid_from_ratio(1024, 1024, 128, 1e4, q=1.05)
+            b = si.rhs_smooth_noise(1024, 1024, 128, 2)
+            A = oracle.assemble(g)
+            ref = oracle.pcg(A, oracle.line_blocks(A, 128), b, rtol=1e-12)
+            del A
+            self.result = dict(x=ref["x"], iterations=ref["iterations"],
+                               rel_res_true=ref["rel_res_true"])
+            self.seconds = time.perf_counter() - t0
+        except Exception as e:  # reported in the extras
+            self.error = repr(e)
+
+
 def extras(pcg, si, torch, main):
     out = {}
     P, b, x, n = main["P"], main["b"], main["x"], main["n"]
+    ref3 = OracleSolve()
+    ref3.start()
 
     # production path: HIP graph chunks, no per-kernel events
     o = pcg.pcg_default_opts(x0_zero=1, graph_chunk=-1)
@@ -251,13 +281,14 @@ def extras(pcg, si, torch, main):
     P3 = pcg.Problem(d3)
     b3 = si.rhs_smooth_noise_torch(1024, 1024, 128, 2)
     x3 = torch.empty_like(b3)
-    res3 = {}
+    res3, sol3 = {}, {}
     for name, o in (("fp64", pcg.pcg_default_opts(x0_zero=1, true_residual=1)),
                     ("mixed", pcg.pcg_default_opts(x0_zero=1, precision=pcg.PCG_PREC_MIXED))):
         ws3 = pcg.workspace(P3, o)
         ms, its, st, r = timed_solves(pcg, torch, P3, b3, x3, ws3, o, 5)
         res3[name] = dict(ms_per_solve=ms, iterations=its, outer=r["outer_iterations"],
                           status=pcg.STATUS_NAMES[st], rel_res_true=r["rel_res_true"])
+        sol3[name] = x3.cpu().numpy()
         del ws3
         log("1024x1024x128 %s: %.3f ms/solve" % (name, ms))
     res3["mixed_speedup_over_fp64"] = res3["fp64"]["ms_per_solve"] / res3["mixed"]["ms_per_solve"]
@@ -272,6 +303,24 @@ def extras(pcg, si, torch, main):
     out["serving_512_requests"] = serving(pcg, si, torch)
     out["serving_512_requests_auto_preconditioner"] = serving(
         pcg, si, torch, preconditioner=pcg.PCG_PRECOND_AUTO)
+
+    # error of the 1024 x 1024 x 128 solutions against the oracle's FP64 solve
+    log("waiting for the oracle's 1024x1024x128 FP64 solve")
+    ref3.join()
+    if ref3.result is not None:
+        import numpy as np
+        xr = ref3.result["x"]
+        nr = np.linalg.norm(xr)
+        for name in ("fp64", "mixed"):
+            res3[name]["rel_error_vs_fp64_oracle"] = float(np.linalg.norm(sol3[name] - xr) / nr)
+        res3["fp64_oracle"] = dict(rtol=1e-12, iterations=ref3.result["iterations"],
+                                   rel_res_true=ref3.result["rel_res_true"],
+                                   host_seconds=ref3.seconds)
+        log("1024x1024x128 error vs FP64 oracle: fp64 %.2e, mixed %.2e"
+            % (res3["fp64"]["rel_error_vs_fp64_oracle"], res3["mixed"]["rel_error_vs_fp64_oracle"]))
+    else:
+        res3["fp64_oracle_error"] = ref3.error
+    del sol3, ref3
 
     # plain copy kernel: attainable HBM bandwidth
     a = torch.empty(1 << 29, dtype=torch.float64, device="cuda")   # 4 GiB

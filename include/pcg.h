@@ -197,15 +197,16 @@ pcg_status pcg_apply(pcg_problem *p, int32_t dtype, const void *x, void *y, void
 
 /* z = M^{-1} r where M is A without the couplings between vertical columns:
  * one tridiagonal solve per column (Sec. 4.1 and eq.
- * MatrixFreeTridiagonalSystem).  r and z: n values of dtype; may alias.
- * Asynchronous on stream. */
+ * MatrixFreeTridiagonalSystem).  r and z: n values of dtype; either the
+ * same vector (in place) or not overlapping at all (PCG_E_INVALID for a
+ * partial overlap).  Asynchronous on stream. */
 pcg_status pcg_precond(pcg_problem *p, int32_t dtype, const void *r, void *z, void *stream);
 
 /* Multigrid preconditioner alone: z = B r for one V-cycle B (see
  * PCG_PRECOND_MG) over at most mg_levels levels (0: all).  r and z: n values
- * of dtype, distinct.  workspace: at least pcg_mg_bytes(p, dtype, mg_levels)
- * bytes of device memory (16-byte aligned) for the coarse levels and one
- * fine-level vector.  pcg_mg_levels: the number of levels the grid allows.
+ * of dtype, not overlapping each other or the workspace.  workspace: at
+ * least pcg_mg_bytes(p, dtype, mg_levels) bytes of device memory (16-byte
+ * aligned) for the coarse levels and one fine-level vector.  pcg_mg_levels: the number of levels the grid allows.
  * Asynchronous on stream. */
 int32_t pcg_mg_levels(const pcg_problem *p);
 size_t pcg_mg_bytes(const pcg_problem *p, int32_t dtype, int32_t mg_levels);
@@ -215,12 +216,13 @@ pcg_status pcg_mg_precond(pcg_problem *p, int32_t dtype, const void *r, void *z,
 
 /* Block Gauss-Seidel preconditioner alone: z = M^{-1} r for the symmetric
  * red-black block Gauss-Seidel M (see PCG_PRECOND_RBGS).  r and z: n values
- * of dtype, distinct.  Asynchronous on stream. */
+ * of dtype, not overlapping.  Asynchronous on stream. */
 pcg_status pcg_rbgs_precond(pcg_problem *p, int32_t dtype, const void *r, void *z, void *stream);
 
 /* Solve A x = b.  b, x: n FP64 values; x holds x0 on entry and the solution
  * on return.  workspace: at least pcg_workspace_bytes(p, opts, 1) bytes of
- * device memory (contents destroyed).  FP64 precision runs the loop-fused
+ * device memory (contents destroyed).  b, x and the workspace must not
+ * overlap (PCG_E_INVALID).  FP64 precision runs the loop-fused
  * iteration of Alg. InterleavedPCG (or, with fused = 0, standard PCG);
  * MIXED runs FP32 inner solves inside FP64 iterative refinement, with the
  * residual b - A x and the update of x in FP64.  Blocks until done.
@@ -299,7 +301,8 @@ pcg_status pcg_autotune(pcg_problem *p, int32_t dtype, int32_t nrhs, void *strea
 
 /* Assembled-CSR comparator (Sec. 6.2): bytes for the CSR arrays of dtype
  * (values of dtype, int32 column indices, int32 row offsets), a device-side
- * assembly into buf, and y = A x from it.  Not used by the solver. */
+ * assembly into buf, and y = A x from it (y must not overlap x or buf).
+ * Not used by the solver. */
 size_t pcg_csr_bytes(const pcg_problem *p, int32_t dtype);
 pcg_status pcg_csr_build(pcg_problem *p, int32_t dtype, void *buf, size_t bytes, void *stream);
 pcg_status pcg_csr_apply(pcg_problem *p, int32_t dtype, const void *buf, const void *x,
@@ -328,6 +331,8 @@ typedef struct {
     uint64_t submitted, completed, cancelled, rejected;
     int32_t queued, active;
     size_t bytes_in_use, peak_bytes_in_use;
+    int32_t peak_active;     /* most requests running on the device at once */
+    int32_t reserved;
 } pcg_server_stats;
 
 /* Device bytes one request needs: b, x and its workspace (0 if invalid). */

@@ -72,7 +72,8 @@ class pcg_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("cancelled", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("queued", ctypes.c_int32), ("active", ctypes.c_int32),
-                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes_in_use", ctypes.c_size_t)]
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes_in_use", ctypes.c_size_t),
+                ("peak_active", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -80,6 +80,29 @@ pcg_status check_aligned(std::initializer_list<const void*> ptrs, const char* wh
     return PCG_OK;
 }
 
+// Two byte ranges [a, a + na) and [b, b + nb) share a byte.
+bool overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return na > 0 && nb > 0 && x < y + nb && y < x + na;
+}
+
+// Rejects an output range that shares bytes with an input range; with
+// exact_ok an output that is exactly the input (same start, in-place
+// kernels) is allowed.
+pcg_status check_disjoint(const void* in, const void* out, size_t bytes, bool exact_ok,
+                          const char* what)
+{
+    if (exact_ok && in == out) return PCG_OK;
+    if (overlap(in, bytes, out, bytes)) {
+        set_error(what);
+        return PCG_E_INVALID;
+    }
+    return PCG_OK;
+}
+
+size_t elem_bytes(int32_t dtype) { return dtype == PCG_F64 ? sizeof(double) : sizeof(float); }
+
 pcg_status check_opts(const pcg_solve_opts& o)
 {
     if (!(o.rtol >= 0.0) || !(o.atol >= 0.0) || !std::isfinite(o.rtol) || !std::isfinite(o.atol)) {
@@ -353,7 +376,7 @@ void pcg_problem_destroy(pcg_problem* P)
     int cur = -1;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(P->device);
-    for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second.exec);
     for (hipEvent_t e : P->events) (void)hipEventDestroy(e);
     for (hipEvent_t e : P->gevents) (void)hipEventDestroy(e);
     if (P->pinned_states) (void)hipHostFree(P->pinned_states);
@@ -378,10 +401,9 @@ pcg_status pcg_apply(pcg_problem* P, int32_t dtype, const void* x, void* y, void
         set_error("pcg_apply: NULL argument or bad dtype");
         return PCG_E_INVALID;
     }
-    if (x == y) {
-        set_error("pcg_apply: x and y must not overlap");
+    if (check_disjoint(x, y, (size_t)P->geom.n * elem_bytes(dtype), false,
+                       "pcg_apply: x and y must not overlap") != PCG_OK)
         return PCG_E_INVALID;
-    }
     if (check_aligned({x, y}, "pcg_apply") != PCG_OK) return PCG_E_INVALID;
     return on_device(P->device, [&]() -> pcg_status {
         TuneScope ts(P, 1);
@@ -408,6 +430,9 @@ pcg_status pcg_precond(pcg_problem* P, int32_t dtype, const void* r, void* z, vo
         set_error("pcg_precond: NULL argument or bad dtype");
         return PCG_E_INVALID;
     }
+    if (check_disjoint(r, z, (size_t)P->geom.n * elem_bytes(dtype), true,
+                       "pcg_precond: r and z must be the same vector or not overlap") != PCG_OK)
+        return PCG_E_INVALID;
     if (check_aligned({r, z}, "pcg_precond") != PCG_OK) return PCG_E_INVALID;
     return on_device(P->device, [&]() -> pcg_status {
         TuneScope ts(P, 1);
@@ -436,10 +461,9 @@ pcg_status pcg_rbgs_precond(pcg_problem* P, int32_t dtype, const void* r, void* 
         set_error("pcg_rbgs_precond: NULL argument or bad dtype");
         return PCG_E_INVALID;
     }
-    if (r == z) {
-        set_error("pcg_rbgs_precond: r and z must not overlap");
+    if (check_disjoint(r, z, (size_t)P->geom.n * elem_bytes(dtype), false,
+                       "pcg_rbgs_precond: r and z must not overlap") != PCG_OK)
         return PCG_E_INVALID;
-    }
     if (!rbgs_supported(P)) {
         set_error("pcg_rbgs_precond: red-black ordering needs an even size in periodic directions");
         return PCG_E_INVALID;
@@ -464,9 +488,14 @@ pcg_status pcg_mg_precond(pcg_problem* P, int32_t dtype, const void* r, void* z,
         set_error("pcg_mg_precond: NULL argument, bad dtype or mg_levels < 0");
         return PCG_E_INVALID;
     }
-    if (r == z) {
-        set_error("pcg_mg_precond: r and z must not overlap");
-        return PCG_E_INVALID;
+    {
+        const size_t vb = (size_t)P->geom.n * elem_bytes(dtype);
+        if (check_disjoint(r, z, vb, false, "pcg_mg_precond: r and z must not overlap") != PCG_OK)
+            return PCG_E_INVALID;
+        if (overlap(workspace, workspace_bytes, r, vb) || overlap(workspace, workspace_bytes, z, vb)) {
+            set_error("pcg_mg_precond: the workspace must not overlap r or z");
+            return PCG_E_INVALID;
+        }
     }
     if (check_aligned({r, z, workspace}, "pcg_mg_precond") != PCG_OK) return PCG_E_INVALID;
     return on_device(P->device, [&]() -> pcg_status {
@@ -492,9 +521,16 @@ static pcg_status solve_common(pcg_problem* P, int32_t nrhs, const double* b, do
         set_error("pcg_solve_batched runs the fused iteration only");
         return PCG_E_INVALID;
     }
-    if (static_cast<const void*>(b) == static_cast<const void*>(x)) {
-        set_error("pcg_solve: b and x must not overlap");
-        return PCG_E_INVALID;
+    {
+        const size_t vb = (size_t)P->geom.n * (size_t)nrhs * sizeof(double);
+        if (overlap(b, vb, x, vb)) {
+            set_error("pcg_solve: b and x must not overlap");
+            return PCG_E_INVALID;
+        }
+        if (overlap(workspace, workspace_bytes, b, vb) || overlap(workspace, workspace_bytes, x, vb)) {
+            set_error("pcg_solve: the workspace must not overlap b or x");
+            return PCG_E_INVALID;
+        }
     }
     if (check_aligned({b, x, workspace}, "pcg_solve") != PCG_OK) return PCG_E_INVALID;
     for (int32_t i = 0; i < nrhs; ++i) std::memset(&results[i], 0, sizeof(pcg_result));
@@ -621,9 +657,18 @@ pcg_status pcg_csr_build(pcg_problem* P, int32_t dtype, void* buf, size_t bytes,
 pcg_status pcg_csr_apply(pcg_problem* P, int32_t dtype, const void* buf, const void* x, void* y,
                          void* stream)
 {
-    if (!P || !buf || !x || !y || !valid_dtype(dtype) || x == y) {
-        set_error("pcg_csr_apply: NULL/overlapping argument or bad dtype");
+    if (!P || !buf || !x || !y || !valid_dtype(dtype)) {
+        set_error("pcg_csr_apply: NULL argument or bad dtype");
         return PCG_E_INVALID;
+    }
+    {
+        const size_t vb = (size_t)P->geom.n * elem_bytes(dtype);
+        if (check_disjoint(x, y, vb, false, "pcg_csr_apply: x and y must not overlap") != PCG_OK)
+            return PCG_E_INVALID;
+        if (overlap(buf, csr_bytes(P->geom, dtype), y, vb)) {
+            set_error("pcg_csr_apply: y must not overlap the CSR buffer");
+            return PCG_E_INVALID;
+        }
     }
     if (check_aligned({buf, x, y}, "pcg_csr_apply") != PCG_OK) return PCG_E_INVALID;
     return on_device(P->device, [&]() -> pcg_status {

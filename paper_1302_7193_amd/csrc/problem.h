@@ -11,27 +11,20 @@
 
 namespace pcg {
 
-// Key of a graph of iteration chunks: every pointer and size baked into it.
-struct GraphKey {
-    int dtype;
-    int kind;             // 0: fused iteration chunk, 1: unfused iteration chunk
-    int iters;
-    int L;
-    int red_mode;
-    int64_t bpr;
-    int L_b;
-    int64_t bpr_b;
-    int64_t nrhs;
-    const void* ptrs[8];
-    bool operator<(const GraphKey& o) const
-    {
-        return std::tie(dtype, kind, iters, L, red_mode, bpr, L_b, bpr_b, nrhs, ptrs[0], ptrs[1],
-                        ptrs[2], ptrs[3], ptrs[4], ptrs[5], ptrs[6], ptrs[7]) <
-               std::tie(o.dtype, o.kind, o.iters, o.L, o.red_mode, o.bpr, o.L_b, o.bpr_b, o.nrhs,
-                        o.ptrs[0], o.ptrs[1], o.ptrs[2], o.ptrs[3], o.ptrs[4], o.ptrs[5],
-                        o.ptrs[6], o.ptrs[7]);
-    }
+// Key of a graph of iteration chunks: the profiled flag, then for every
+// kernel node its function, launch dimensions and every field of its
+// argument block (pointers, sizes, flags), so a replay never runs a graph
+// built for other vectors or launch parameters.
+using GraphKey = std::vector<uint64_t>;
+
+// A cached executable graph and when it was last replayed (the problem's
+// graph clock); the cache keeps at most kMaxGraphs, evicting the least
+// recently used.
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
 };
+constexpr size_t kMaxGraphs = 16;
 
 }  // namespace pcg
 
@@ -77,7 +70,8 @@ struct pcg_problem {
     int last_iters[2] = {0, 0};            // adaptive chunk length per precision
     pcg::SolverState* pinned_states = nullptr;  // host-pinned staging of solver states
     int64_t pinned_cap = 0;
-    std::map<pcg::GraphKey, hipGraphExec_t> graphs;
+    std::map<pcg::GraphKey, pcg::GraphEntry> graphs;
+    uint64_t graph_clock = 0;
     std::vector<hipEvent_t> events;
     std::vector<hipEvent_t> gevents;       // event nodes of profiled graph chunks
 };

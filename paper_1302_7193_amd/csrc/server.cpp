@@ -86,7 +86,7 @@ struct pcg_server {
     char* arena_base = nullptr;
     pcg::Arena arena;
     size_t admitted_bytes = 0, peak_bytes = 0;
-    int active = 0;
+    int active = 0, peak_active = 0;
     bool stop = false;
     uint64_t next_ticket = 1;
     uint64_t n_submitted = 0, n_completed = 0, n_cancelled = 0, n_rejected = 0;
@@ -114,6 +114,7 @@ struct pcg_server {
         admitted_bytes += req->need;
         peak_bytes = std::max(peak_bytes, admitted_bytes);
         ++active;
+        peak_active = std::max(peak_active, active);
         return req;
     }
 
@@ -429,6 +430,8 @@ pcg_status pcg_server_query(pcg_server* S, pcg_server_stats* out)
     out->active = S->active;
     out->bytes_in_use = S->admitted_bytes;
     out->peak_bytes_in_use = S->peak_bytes;
+    out->peak_active = S->peak_active;
+    out->reserved = 0;
     return PCG_OK;
 }
 

@@ -414,32 +414,47 @@ pcg_status issue_chunk(const ColArgs& a, const Phase& bph, int64_t nrhs, int K, 
     return launch<T>(Kind::Fixup, a, nrhs, s, count);
 }
 
+uint64_t bits(double v)
+{
+    uint64_t u;
+    std::memcpy(&u, &v, sizeof(u));
+    return u;
+}
+
+uint64_t bits(const void* p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); }
+
+void key_geom(GraphKey& k, const Geom& g)
+{
+    k.insert(k.end(), {uint64_t(uint32_t(g.nx)), uint64_t(uint32_t(g.ny)), uint64_t(uint32_t(g.nz)),
+                       uint64_t(uint32_t(g.nzp)), uint64_t(uint32_t(g.per_x)),
+                       uint64_t(uint32_t(g.per_y)), uint64_t(g.nh), uint64_t(g.n), bits(g.area),
+                       bits(g.ax), bits(g.ay)});
+}
+
+// Every field of one kernel node of a graph chunk, for its cache key.
+void key_launch(GraphKey& k, const KernelLaunch& l)
+{
+    const ColArgs& a = l.args;
+    k.insert(k.end(), {bits(l.func), l.grid.x, l.grid.y, l.grid.z, l.block.x, l.block.y, l.block.z});
+    key_geom(k, a.g);
+    key_geom(k, a.g2);
+    k.insert(k.end(), {uint64_t(uint32_t(a.L)), uint64_t(a.blocks_per_rhs), uint64_t(uint32_t(a.L_b)),
+                       uint64_t(a.bpr_b), bits(a.vert), bits(a.lu), bits(a.in0), bits(a.in1),
+                       bits(a.io0), bits(a.io1), bits(a.io2), bits(a.io3), bits(a.io4),
+                       bits(a.out32), bits(a.st), bits(a.part), uint64_t(uint32_t(a.red_mode)),
+                       uint64_t(uint32_t(a.x0_zero)), bits(a.hgeo), bits(a.hgeo2), bits(a.omega),
+                       uint64_t(uint32_t(a.zswap))});
+}
+
 // The chunk as an explicitly built HIP graph (kernel nodes in sequence).  No
 // stream capture is involved, so building is independent of what other host
 // threads do with their streams.
 // profiled: event record nodes around every kernel A and kernel B's launches
 // up to its last main kernel, events P->gevents[4i .. 4i+3] for iteration i.
 template <typename T>
-pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, const Phase& bph,
-                       int bkind, int64_t nrhs, int K, bool profiled, hipGraphExec_t* out)
+pcg_status chunk_graph(pcg_problem* P, const ColArgs& a, const Phase& bph,
+                       int64_t nrhs, int K, bool profiled, hipGraphExec_t* out)
 {
-    GraphKey key{};
-    key.dtype = dtype;
-    key.kind = bkind + (profiled ? 1000 : 0);
-    key.iters = K;
-    key.L = a.L;
-    key.red_mode = a.red_mode;
-    key.bpr = a.blocks_per_rhs;
-    key.L_b = a.L_b;
-    key.bpr_b = a.bpr_b;
-    key.nrhs = nrhs;
-    const void* ptrs[8] = {a.io0, a.io1, a.io2, a.io3, a.io4, a.st, a.part, a.lu};
-    std::memcpy(key.ptrs, ptrs, sizeof(ptrs));
-    auto it = P->graphs.find(key);
-    if (it != P->graphs.end()) {
-        *out = it->second;
-        return PCG_OK;
-    }
     if (profiled) {
         while (P->gevents.size() < 4 * (size_t)K) {
             hipEvent_t e;
@@ -473,6 +488,26 @@ pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, const Phase&
     if (!add(Kind::Fixup)) {
         set_error("graph: no kernel for this shape (internal)");
         return PCG_E_DEVICE;
+    }
+    GraphKey key;
+    key.reserve(1 + seq.size() * 48);
+    key.push_back(profiled ? 1 : 0);
+    for (const KernelLaunch& l : seq) key_launch(key, l);
+    const uint64_t now = ++P->graph_clock;
+    auto it = P->graphs.find(key);
+    if (it != P->graphs.end()) {
+        it->second.last_use = now;
+        *out = it->second.exec;
+        return PCG_OK;
+    }
+    // bounded cache: drop the least recently replayed graph (every replay of
+    // this problem has completed: solves end with a stream synchronisation)
+    if (P->graphs.size() >= kMaxGraphs) {
+        auto lru = P->graphs.begin();
+        for (auto j = P->graphs.begin(); j != P->graphs.end(); ++j)
+            if (j->second.last_use < lru->second.last_use) lru = j;
+        (void)hipGraphExecDestroy(lru->second.exec);
+        P->graphs.erase(lru);
     }
     hipGraph_t graph = nullptr;
     PCG_HIP(hipGraphCreate(&graph, 0), "hipGraphCreate");
@@ -518,7 +553,7 @@ pcg_status chunk_graph(pcg_problem* P, int dtype, const ColArgs& a, const Phase&
     const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     PCG_HIP(e, "hipGraphInstantiate");
-    P->graphs[key] = exec;
+    P->graphs[key] = GraphEntry{exec, now};
     *out = exec;
     return PCG_OK;
 }
@@ -544,7 +579,6 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_
     a.zswap = o.preconditioner == PCG_PRECOND_LINE ? 1 : 0;
     Phase bph;
     if (b_phase<T>(P, dtype, a, nrhs, o, ws, w, bph) != PCG_OK) return PCG_E_DEVICE;
-    const int bkind = o.preconditioner == PCG_PRECOND_MG ? 100 + w.mg_levels : o.preconditioner;
     const bool profile = o.profile != 0 && nrhs == 1;
     int K = o.graph_chunk > 0 ? o.graph_chunk : P->last_iters[prec_slot];
     if (K <= 0) K = 8;
@@ -601,7 +635,7 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_
             if (launch<T>(Kind::Fixup, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
         } else if (use_graph) {
             hipGraphExec_t exec;
-            if (chunk_graph<T>(P, dtype, a, bph, bkind, nrhs, K, profile, &exec) != PCG_OK)
+            if (chunk_graph<T>(P, a, bph, nrhs, K, profile, &exec) != PCG_OK)
                 return PCG_E_DEVICE;
             PCG_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
             info.launches += (1 + bph.mains) * K + 1;
@@ -881,7 +915,17 @@ pcg_status solve_mixed(pcg_problem* P, const double* b, double* x, char* ws, con
             }
             all_done &= done[i] != 0;
         }
-        if (all_done) break;
+        // a zero start that stops at its first residual (b = 0, ||b|| <= atol,
+        // a non-finite b) has written nothing to x yet: x = x0 = 0
+        if (k == 0 && o.x0_zero)
+            for (int64_t i = 0; i < nrhs; ++i)
+                if (done[i])
+                    PCG_HIP(hipMemsetAsync(x + i * P->geom.n, 0, sizeof(double) * (size_t)P->geom.n, s),
+                            "hipMemsetAsync(x = 0)");
+        if (all_done) {
+            PCG_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");   // the call blocks
+            break;
+        }
         // first step: rescale if the residual left the comfortable FP32 range
         if (k == 0) {
             bool redo = false;

@@ -43,16 +43,20 @@ def test_struct_layouts_match_header(tmp_path):
     import paper_1302_7193_amd as pcg
     prog = tmp_path / "sizes.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pcg.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(pcg_problem_desc),'
-                    ' sizeof(pcg_solve_opts), sizeof(pcg_result),'
-                    ' offsetof(pcg_result, ms_apply_kernel), offsetof(pcg_solve_opts, inner_rtol));'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                    ' sizeof(pcg_problem_desc), sizeof(pcg_solve_opts), sizeof(pcg_result),'
+                    ' offsetof(pcg_result, ms_apply_kernel), offsetof(pcg_solve_opts, inner_rtol),'
+                    ' sizeof(pcg_tuning), sizeof(pcg_server_opts), sizeof(pcg_server_stats),'
+                    ' offsetof(pcg_server_stats, peak_active));'
                     'return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(pcg.pcg_problem_desc), ctypes.sizeof(pcg.pcg_solve_opts),
             ctypes.sizeof(pcg.pcg_result), pcg.pcg_result.ms_apply_kernel.offset,
-            pcg.pcg_solve_opts.inner_rtol.offset]
+            pcg.pcg_solve_opts.inner_rtol.offset, ctypes.sizeof(pcg.pcg_tuning),
+            ctypes.sizeof(pcg.pcg_server_opts), ctypes.sizeof(pcg.pcg_server_stats),
+            pcg.pcg_server_stats.peak_active.offset]
     assert got == want
 
 

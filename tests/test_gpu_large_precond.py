@@ -7,8 +7,8 @@ kernel), against the oracle, through the C ABI.
   (the V-cycle's coarser levels take the plain loads: the test covers both);
 * three FP64 iterations of MG-PCG and of RBGS-PCG equal the oracle's
   iterates (the fused first and last kernels of each preconditioner phase).
-Tolerances as for the small grids: the same linear maps computed in another
-order."""
+Tolerances as for the small grids (per column: no column's error may
+exceed them): the same linear maps computed in another order."""
 import numpy as np
 import pytest
 
@@ -23,6 +23,7 @@ import oracle.mg as omg  # noqa: E402
 import oracle.rbgs as rb  # noqa: E402
 import paper_1302_7193_amd as pcg  # noqa: E402
 import synth_inputs as si  # noqa: E402
+from _checks import column_rel_errors  # noqa: E402
 
 NX, NY, NZ = 256, 256, 128
 
@@ -56,13 +57,15 @@ def test_vcycle_and_rbgs_match_oracle(case):
     pcg.pcg_mg_precond(p, pcg.PCG_F64, rt, z, ws, levels)
     torch.cuda.synchronize()
     want = omg.Hierarchy(g).vcycle(r)
-    err = np.linalg.norm(z.cpu().numpy() - want) / np.linalg.norm(want)
+    err = column_rel_errors(z.cpu().numpy(), want, NZ).max()
+    print("large vcycle: worst column error %.2e" % err)
     assert err <= 1e-11, err
     z.fill_(float("nan"))
     pcg.pcg_rbgs_precond(p, pcg.PCG_F64, rt, z)
     torch.cuda.synchronize()
     want = rb.RBGS(g, A).apply(r)
-    err = np.linalg.norm(z.cpu().numpy() - want) / np.linalg.norm(want)
+    err = column_rel_errors(z.cpu().numpy(), want, NZ).max()
+    print("large rbgs: worst column error %.2e" % err)
     assert err <= 1e-11, err
 
 

@@ -8,9 +8,11 @@ oracle's V-cycle and multigrid-preconditioned CG (oracle/mg.py).
   oracle's matrix, mixed precision reaches the FP64 tolerance;
 * batched, graph, direct and profiled launches bitwise equal; served
   requests with MG equal direct solves.
-Tolerances: the V-cycle is a fixed linear map, computed in a different
-order, so FP64 results agree to a few hundred ulps of its condition; FP32
-(mixed precision's inner solves) to 1e-4."""
+Tolerances, for every column separately (the error of each column relative
+to its own norm, or to the root-mean-square column norm where that is
+larger): the V-cycle is a fixed linear map, computed in a different order,
+so FP64 results agree to a few hundred ulps of its condition; FP32 (mixed
+precision's inner solves) to 1e-4."""
 import numpy as np
 import pytest
 
@@ -24,6 +26,7 @@ import oracle  # noqa: E402
 import oracle.mg as omg  # noqa: E402
 import paper_1302_7193_amd as pcg  # noqa: E402
 import synth_inputs as si  # noqa: E402
+from _checks import column_rel_errors  # noqa: E402
 
 MG = pcg.PCG_PRECOND_MG
 
@@ -76,7 +79,8 @@ def test_vcycle_matches_oracle(name, dtype):
         pcg.pcg_mg_precond(p, dtype, r, z, ws, ml)
         torch.cuda.synchronize()
         want = omg.Hierarchy(g, ml).vcycle(r.double().cpu().numpy())
-        err = np.linalg.norm(z.double().cpu().numpy() - want) / np.linalg.norm(want)
+        err = column_rel_errors(z.double().cpu().numpy(), want, d.nz).max()
+        print("vcycle %s dtype %d levels %d: worst column error %.2e" % (name, dtype, ml, err))
         assert err <= (1e-11 if dtype == pcg.PCG_F64 else 1e-4), (ml, err)
 
 

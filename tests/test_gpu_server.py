@@ -76,6 +76,7 @@ def test_results_identical_alone_and_in_the_mix(precision, preconditioner):
     alone, ra, _, _ = serve(reqs, opts, max_active=1, one_at_a_time=True)
     mixed, rm, stats, _ = serve(reqs, opts, max_active=4)
     assert stats["completed"] == len(reqs) and stats["peak_bytes_in_use"] > 0
+    print("peak requests on the device at once: %d" % stats["peak_active"])
     for i, (d, b) in enumerate(reqs):
         np.testing.assert_array_equal(alone[i], mixed[i])
         assert ra[i]["iterations"] == rm[i]["iterations"]
@@ -165,3 +166,40 @@ def test_device_generator_matches_host_generator():
     a = si.rhs_smooth_noise(17, 9, 33, 2)
     b = si.rhs_smooth_noise_torch(17, 9, 33, 2).cpu().numpy()
     np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+
+
+def test_requests_overlap_on_the_device():
+    """Requests submitted together run concurrently: the server's count of
+    requests running at once reaches the number of workers, and each result
+    is still the one the request gets alone."""
+    reqs = []
+    for rid in range(4):
+        d = pcg.pcg_desc_from_ratio(128, 128, 64, 1.05, 1e2, pcg.PCG_BC_DIRICHLET)
+        reqs.append((d, si.rhs_uniform(128, 128, 64, 1000 + rid)))
+    opts = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED)
+    mixed, rm, stats, _ = serve(reqs, opts, max_active=4)
+    print("peak requests on the device at once: %d" % stats["peak_active"])
+    assert stats["peak_active"] >= 2, stats
+    alone, ra, _, _ = serve(reqs[:1], opts, max_active=1, one_at_a_time=True)
+    np.testing.assert_array_equal(alone[0], mixed[0])
+
+
+def test_zero_right_hand_side_served_as_zero():
+    """A served request with b = 0 (done at its first residual) returns
+    x = 0, also when the host buffer held garbage."""
+    reqs, opts = requests()
+    d, b = reqs[0]
+    z = np.zeros_like(b)
+    arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    srv = pcg.Server(arena, arena.numel(), 2)
+    try:
+        x = np.full_like(b, np.nan)
+        st, r = pcg.pcg_wait(srv, pcg.pcg_submit(srv, d, z, x, opts))
+        assert st == pcg.PCG_OK and r["iterations"] == 0
+        assert np.array_equal(x, z)
+        bt = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+        xt = torch.full_like(bt, float("nan"))
+        st, r = pcg.pcg_wait(srv, pcg.pcg_submit_device(srv, d, bt, xt, opts))
+        assert st == pcg.PCG_OK and not xt.cpu().numpy().any()
+    finally:
+        srv.close()

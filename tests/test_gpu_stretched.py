@@ -21,6 +21,7 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 import paper_1302_7193_amd as pcg  # noqa: E402
 import synth_inputs as si  # noqa: E402
+from _checks import column_backward_errors, line_solve_bound  # noqa: E402
 
 U64, U32 = 2.0**-53, 2.0**-24
 DT = {pcg.PCG_F64: (torch.float64, U64), pcg.PCG_F32: (torch.float32, U32)}
@@ -77,15 +78,17 @@ def check_precond(p, d, xw, yw, dtype, seed=12):
     torch.cuda.synchronize()
     M = oracle.line_blocks(oracle.assemble(grid_of(d, xw, yw)), d.nz)
     rr, zz = r.double().cpu().numpy(), z.double().cpu().numpy()
-    Mz = M.di * zz
-    Mz[1:] += M.lo[1:] * zz[:-1]
-    Mz[:-1] += M.up[:-1] * zz[1:]
-    normM = np.abs(M.di).max() + np.abs(M.lo).max() + np.abs(M.up).max()
-    back = np.linalg.norm(Mz - rr) / (normM * np.linalg.norm(zz))
+    back = column_backward_errors(M, zz, rr, d.nz).max()
     assert back <= 64 * u * (4 if dtype == pcg.PCG_F32 else 1), back
+    # every element within the componentwise forward bound of the column
+    # solves; c = 256 rather than the 64 of the class-factor path: here the
+    # kernel also factorises every column, its pivots coming from a scan of
+    # rounded 2 x 2 products over up to 1024 levels, which adds their
+    # rounding to the backward error of the substitutions
     zo = oracle.line_solve(M, rr)
-    fwd = np.linalg.norm(zz - zo) / np.linalg.norm(zo)
-    assert fwd <= (1e-9 if dtype == pcg.PCG_F64 else 1e-3), fwd
+    ratio = (np.abs(zz - zo) / (line_solve_bound(M, zo, u, 256) + 1e-300)).max()
+    print("stretched line solve: max |z - z_ref| / bound = %.3f" % ratio)
+    assert ratio <= 1.0, ratio
 
 
 @pytest.mark.parametrize("name", list(CASES))
