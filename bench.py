@@ -52,6 +52,40 @@ def solve_kernel_bytes(kernel, iterations, n):
         return n * (BYTES["fused_apply_first"] + BYTES["fused_apply_second"] +
                     BYTES["fused_apply"] * (iterations - 2))
     return n * (BYTES["fused_prec_first"] + BYTES["fused_prec"] * iterations)
+
+
+def fp64_solve_bytes(k, n):
+    """Algorithmic bytes of a zero-start FP64 fused solve of k >= 1 iterations
+    with the line preconditioner: kernels A and B (solve_kernel_bytes) and
+    the exit correction u += alpha p (read u, p, write u: 24 bytes/unknown;
+    16 after a single iteration, when u is still unset and not read)."""
+    return (solve_kernel_bytes("fused_apply", k, n) + solve_kernel_bytes("fused_prec", k, n) +
+            n * (24 if k >= 2 else 16))
+
+
+def mixed_solve_bytes(inner, steps, n):
+    """Algorithmic bytes of a zero-start mixed-precision solve with `steps`
+    refinement steps and `inner` FP32 inner iterations in all (the counts a
+    pcg_result reports).  An inner solve of k iterations moves 44k - 4
+    bytes/unknown: kernel B 8 + 16k (its first launch reads b and writes z),
+    kernel A 8 + 24 + 28(k - 2) (first: read z, write q; second: u not
+    read), the exit correction 12 (8 after one iteration).  The FP64 steps:
+    steps + 1 residuals r32 = (b - A x) scale, 20 each (read x, b, write
+    r32; the first reads b only: 12), and `steps` updates x += u32 / scale,
+    20 each (read x, u32, write x; the first does not read x: 12)."""
+    if steps == 0:
+        return n * (12 + 8)   # one residual, then x = 0 written
+    return n * (44 * inner - 4 * steps + (12 + 20 * steps) + (12 + 20 * (steps - 1)))
+
+
+def solve_roofline(bytes_per_solve, ms_per_solve):
+    """Whole-solve bandwidth: algorithmic bytes over wall time per solve
+    (launch gaps, flag read-backs and finalize launches included)."""
+    gbps = bytes_per_solve / (ms_per_solve * 1e-3) / 1e9
+    return dict(bound="hbm", algorithmic_bytes_per_solve=bytes_per_solve, achieved=gbps,
+                peak=PEAK_HBM_GBPS, unit="GB/s", frac=gbps / PEAK_HBM_GBPS)
+
+
 KERNEL_PATTERN = {
     "fused_apply": r"k_fused_apply<double, \d+, (true|false), false, (true|false), (true|false)>",
     "fused_prec": r"k_fused_prec<double, \d+, (true|false), false, (true|false), (true|false)>"}
@@ -288,6 +322,9 @@ def extras(pcg, si, torch, main):
         ms, its, st, r = timed_solves(pcg, torch, P3, b3, x3, ws3, o, 5)
         res3[name] = dict(ms_per_solve=ms, iterations=its, outer=r["outer_iterations"],
                           status=pcg.STATUS_NAMES[st], rel_res_true=r["rel_res_true"])
+        nb = (fp64_solve_bytes(r["iterations"], P3.n) if name == "fp64" else
+              mixed_solve_bytes(r["iterations"], r["outer_iterations"], P3.n))
+        res3[name]["roofline"] = solve_roofline(nb, ms)
         sol3[name] = x3.cpu().numpy()
         del ws3
         log("1024x1024x128 %s: %.3f ms/solve" % (name, ms))
@@ -476,7 +513,10 @@ def batched(pcg, si, torch, nrhs=64):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / reps * 1e3
         its = [r["iterations"] for r in res]
+        nb = sum(mixed_solve_bytes(r["iterations"], r["outer_iterations"], n) if name == "mixed"
+                 else fp64_solve_bytes(r["iterations"], n) for r in res)
         out[name] = dict(ms_per_batched_solve=ms, status=pcg.STATUS_NAMES[st],
+                         roofline=solve_roofline(nb, ms),
                          all_ok=all(r["status"] == 0 for r in res),
                          iterations_mean=sum(its) / nrhs, iterations_max=max(its),
                          outer_max=max(r["outer_iterations"] for r in res),
@@ -547,6 +587,41 @@ def serving(pcg, si, torch, n_requests=512, max_active=4, preconditioner=0):
                 mean_unknowns=float(nunk.mean()), max_active=max_active,
                 peak_bytes_in_use=q["peak_bytes_in_use"], budget_bytes=200 * 10**9,
                 input="device-resident right-hand sides (pcg_submit_device)")
+
+
+def profile_run(pcg, si, torch, steps, mixed_1024):
+    """Timed solves of one configuration alone, for profiler runs: the
+    1024 x 1024 x 128 mixed-precision workload, or the 64 right-hand sides on
+    256 x 256 x 64 (mixed precision, launch parameters from the committed
+    tuning table, no autotuning)."""
+    if mixed_1024:
+        nx, ny, nz, g2, nrhs = 1024, 1024, 128, 1e4, 1
+    else:
+        nx, ny, nz, g2, nrhs = 256, 256, 64, 1e3, 64
+    d = pcg.pcg_desc_from_ratio(nx, ny, nz, 1.05, g2, pcg.PCG_BC_DIRICHLET)
+    P = pcg.Problem(d)
+    n = P.n
+    if mixed_1024:
+        B = si.rhs_smooth_noise_torch(nx, ny, nz, 2)
+    else:
+        B = torch.empty(nrhs * n, dtype=torch.float64, device="cuda")
+        for s_ in range(nrhs):
+            si.rhs_uniform_torch(nx, ny, nz, 100 + s_, out=B[s_ * n:(s_ + 1) * n])
+    X = torch.empty_like(B)
+    o = pcg.pcg_default_opts(x0_zero=1, precision=pcg.PCG_PREC_MIXED)
+    ws = pcg.workspace(P, o, nrhs)
+    pcg.pcg_solve_batched(P, nrhs, B, X, ws, o)     # warm: graph chunks, chunk length
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, res = pcg.pcg_solve_batched(P, nrhs, B, X, ws, o)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    nb = sum(mixed_solve_bytes(r["iterations"], r["outer_iterations"], n) for r in res)
+    return dict(workload="%dx%dx%d x %d right-hand sides, mixed precision" % (nx, ny, nz, nrhs),
+                ms_per_solve=ms, inner_iterations=[r["iterations"] for r in res][:4],
+                outer=[r["outer_iterations"] for r in res][:4], status=pcg.STATUS_NAMES[st],
+                roofline=solve_roofline(nb, ms))
 
 
 def cpu_baseline(n_iter=10):
@@ -696,6 +771,11 @@ def main():
     ap.add_argument("--mg-only", action="store_true",
                     help="only FP64 multigrid-preconditioned solves of 512x512x128 Dirichlet "
                          "with anisotropy 1e2 (for profiler runs of the V-cycle kernels)")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="only mixed-precision solves of 1024x1024x128 (for profiler runs)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only mixed-precision batched solves of 64 right-hand sides on "
+                         "256x256x64 with the committed tuning (for profiler runs)")
     ap.add_argument("--main-only", action="store_true",
                     help="only the timed loop (for profiler runs): no extras, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -730,6 +810,10 @@ def main():
     import paper_1302_7193_amd as pcg
     import synth_inputs as si
     torch.cuda.set_device(0)
+
+    if args.mixed_only or args.batched_only:
+        print(json.dumps(profile_run(pcg, si, torch, args.steps, args.mixed_only)))
+        return
 
     if args.mg_only or args.rbgs_only:
         d = pcg.pcg_desc_from_ratio(512, 512, 128, 1.05, 1e2, pcg.PCG_BC_DIRICHLET)

@@ -76,3 +76,24 @@ def test_rocprof_summary_of_a_synthetic_trace(tmp_path):
     # 3 dispatches averaging 205 us; the 5 us early-exit one is not working
     assert row[1] == "3" and abs(float(row[2]) - 205.0) < 1e-6
     assert row[3] == "2" and abs(float(row[4]) - 305.0) < 1e-6
+
+
+def test_whole_solve_bytes_by_enumeration():
+    """The whole-solve byte counts against a launch-by-launch enumeration
+    (bytes per unknown of each vector each launch reads or writes)."""
+    n = 1000
+
+    def inner(k, e):   # one zero-start inner solve of k iterations, e bytes per value
+        b = [2 * e] + [4 * e] * k                       # kernel B: b -> z, then r, q -> r, z
+        a = [2 * e] + ([6 * e] if k >= 2 else []) + [7 * e] * max(k - 2, 0)
+        fix = 3 * e if k >= 2 else 2 * e                # u += alpha p (u unset after one)
+        return sum(b) + sum(a) + fix
+
+    for k in (1, 2, 5, 9):
+        assert bench.fp64_solve_bytes(k, n) == n * inner(k, 8)
+    for ks in ((11,), (7, 4), (9, 1, 3)):
+        s = len(ks)
+        residuals = (8 + 4) + (8 + 8 + 4) * s           # b [, x] in, r32 out; s + 1 of them
+        updates = (4 + 8) + (8 + 4 + 8) * (s - 1)       # u32 [, x] in, x out
+        want = sum(inner(k, 4) for k in ks) + residuals + updates
+        assert bench.mixed_solve_bytes(sum(ks), s, n) == n * want, ks
