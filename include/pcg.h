@@ -232,6 +232,23 @@ pcg_status pcg_solve(pcg_problem *p, const double *b, double *x, void *workspace
                      size_t workspace_bytes, const pcg_solve_opts *opts,
                      pcg_result *result, void *stream);
 
+/* pcg_solve without a workspace argument and without any device memory
+ * allocation in the call, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The workspace is a fixed scratch array inside the library, 64 MiB per
+ * device, held for the life of the process: enough for an FP64 solve of
+ * about two million unknowns (less with the multigrid preconditioner's
+ * coarse levels); larger solves return PCG_E_NOMEM with a message giving
+ * the bytes needed.  Kernels, launch parameters and results are those of
+ * pcg_solve with the same options run with graph_chunk = 0 (direct
+ * launches, bitwise the same as graph chunks); graph_chunk and profile are
+ * ignored.  Every call on one device shares that device's scratch: calls
+ * that overlap in time on one device (from several host threads, or on
+ * several streams) race and must not be made.  b, x, opts, result and
+ * errors as pcg_solve.  Blocks until done. */
+pcg_status pcg_solve_noalloc(pcg_problem *p, const double *b, double *x,
+                             const pcg_solve_opts *opts, pcg_result *result, void *stream);
+
 /* Solve A x_s = b_s for nrhs right-hand sides sharing one operator, all
  * advanced together by single launches that cover every right-hand side
  * (each with its own scalars and exit test; finished ones drop out).

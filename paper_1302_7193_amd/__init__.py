@@ -113,6 +113,8 @@ _sig = {
     "pcg_mg_precond": (_S, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "pcg_solve": (_S, [_P, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(pcg_solve_opts),
                        ctypes.POINTER(pcg_result), _P]),
+    "pcg_solve_noalloc": (_S, [_P, _P, _P, ctypes.POINTER(pcg_solve_opts),
+                               ctypes.POINTER(pcg_result), _P]),
     "pcg_solve_batched": (_S, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t,
                                ctypes.POINTER(pcg_solve_opts), ctypes.POINTER(pcg_result), _P]),
     "pcg_csr_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
@@ -315,6 +317,17 @@ def pcg_solve(p: Problem, b, x, ws, opts: pcg_solve_opts | None = None, stream=N
                                _vec(x, p.n, torch.float64, "x"), _buf(ws, need, "workspace"),
                                ws.numel() * ws.element_size(), ctypes.byref(opts),
                                ctypes.byref(res), _stream(stream)), "pcg_solve")
+    return st, res.as_dict()
+
+
+def pcg_solve_noalloc(p: Problem, b, x, opts: pcg_solve_opts | None = None, stream=None):
+    """pcg_solve with the library's fixed device scratch as its workspace
+    (no allocation in the call).  Returns (status, result dict)."""
+    opts = opts or pcg_default_opts()
+    res = pcg_result()
+    st = _check(_lib.pcg_solve_noalloc(p.handle, _vec(b, p.n, torch.float64, "b"),
+                                       _vec(x, p.n, torch.float64, "x"), ctypes.byref(opts),
+                                       ctypes.byref(res), _stream(stream)), "pcg_solve_noalloc")
     return st, res.as_dict()
 
 

@@ -25,6 +25,8 @@ pcg_status mg_precond(pcg_problem* P, int dtype, const void* r, void* z, int lev
                       void* workspace, size_t ws_bytes, hipStream_t s);
 int64_t blocks_per_rhs(const pcg_problem* P, int dtype);
 pcg_status autotune(pcg_problem* P, int dtype, int64_t nrhs, hipStream_t s, Tuning* best);
+pcg_status solve_noalloc(pcg_problem* P, const double* b, double* x, const pcg_solve_opts& o,
+                         pcg_result* res, hipStream_t s);
 pcg_status solve(pcg_problem* P, const double* b, double* x, void* workspace, size_t ws_bytes,
                  const pcg_solve_opts& o, int64_t nrhs, pcg_result* res, hipStream_t s);
 
@@ -350,6 +352,15 @@ static pcg_status create_problem(const pcg_problem_desc* desc, const double* xw,
         pcg_problem_destroy(P);
         return mst;
     }
+    // pinned staging of one solver state: single-right-hand-side solves then
+    // allocate nothing per call
+    e = hipHostMalloc((void**)&P->pinned_states, sizeof(SolverState), 0);
+    if (e != hipSuccess) {
+        set_error(hip_msg(e, "hipHostMalloc(solver state)"));
+        pcg_problem_destroy(P);
+        return PCG_E_NOMEM;
+    }
+    P->pinned_cap = 1;
     *out = P;
     return PCG_OK;
 }
@@ -545,6 +556,29 @@ pcg_status pcg_solve(pcg_problem* P, const double* b, double* x, void* workspace
                      void* stream)
 {
     return solve_common(P, 1, b, x, workspace, workspace_bytes, opts, result, stream);
+}
+
+pcg_status pcg_solve_noalloc(pcg_problem* P, const double* b, double* x,
+                             const pcg_solve_opts* opts, pcg_result* result, void* stream)
+{
+    if (!P || !b || !x || !result) {
+        set_error("pcg_solve_noalloc: NULL argument");
+        return PCG_E_INVALID;
+    }
+    pcg_solve_opts o;
+    if (opts) o = *opts;
+    else pcg_default_opts(&o);
+    pcg_status c = check_opts(o);
+    if (c != PCG_OK) return c;
+    if (overlap(b, (size_t)P->geom.n * sizeof(double), x, (size_t)P->geom.n * sizeof(double))) {
+        set_error("pcg_solve_noalloc: b and x must not overlap");
+        return PCG_E_INVALID;
+    }
+    if (check_aligned({b, x}, "pcg_solve_noalloc") != PCG_OK) return PCG_E_INVALID;
+    std::memset(result, 0, sizeof(pcg_result));
+    return on_device(P->device, [&]() -> pcg_status {
+        return solve_noalloc(P, b, x, o, result, static_cast<hipStream_t>(stream));
+    });
 }
 
 pcg_status pcg_solve_batched(pcg_problem* P, int32_t nrhs, const double* b, double* x,

@@ -28,6 +28,9 @@ constexpr int kRedSlots = 2;       // doubles per workgroup in the partial-sum b
 constexpr int64_t kStreamBytes = int64_t(64) << 20;
 constexpr int64_t kMaxBlocks = 65536;   // largest workgroup cap per right-hand side
 constexpr int64_t kDefaultCap = 16384;  // default workgroup cap per right-hand side
+// Fixed device scratch of the allocation-free solve (per device, for the
+// life of the process): an FP64 solve of up to about 2 million unknowns.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 constexpr double kMgOmega = 0.8;   // multigrid: damping of the line-Jacobi smoother
 constexpr int kMgMinCells = 4;     // coarsen while both halves keep >= 4 cells
 constexpr int kMgCoarseSweeps = 4; // smoothing sweeps from zero on the coarsest level
