@@ -21,6 +21,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import threading
@@ -715,6 +716,79 @@ def summarize_rocprof(directory, kernel_filter="k_fused|k_init|k_fixup|k_finaliz
     print("\n".join(lines))
 
 
+BOUNDARY = re.compile(r"k_fixup|k_residual64|k_update64|k_init|k_true_residual")
+
+
+def launch_position(name):
+    """Position classes of a launch of a fused kernel within one (inner) solve."""
+    if "k_fused_apply" in name:
+        return ("first", "second", "steady")
+    if "k_fused_prec" in name:
+        return ("first", "steady")
+    return ("all",)
+
+
+def classify_launches(rows, value_key):
+    """rows: dicts with Kernel_Name, an order key and `value_key`, in dispatch
+    order.  Each launch of a fused kernel that did work (at least a tenth of
+    that kernel's largest value: the early-exit launches past convergence do
+    not) gets its position since the last start-up, exit-correction or
+    refinement kernel: kernel A's first, second and steady-state launches,
+    kernel B's first and steady-state ones."""
+    top = {}
+    for r in rows:
+        top[r["Kernel_Name"]] = max(top.get(r["Kernel_Name"], 0.0), r[value_key])
+    pos, out = {}, []
+    for r in rows:
+        name = r["Kernel_Name"]
+        if BOUNDARY.search(name):
+            pos = {}
+        if r[value_key] < 0.1 * top[name]:
+            continue
+        classes = launch_position(name)
+        i = pos.get(name, 0)
+        pos[name] = i + 1
+        out.append((name, classes[min(i, len(classes) - 1)], r[value_key]))
+    return out
+
+
+def summarize_launches(directory, kernel_filter=r"k_\w+|copy"):
+    """Per kernel and launch position (first / second / steady state within
+    each solve): dispatches that did work and their mean duration (kernel
+    trace) or mean counter value (counter runs)."""
+    lines = []
+    for path, rows in _csv_rows(directory, "kernel_trace.csv"):
+        rs = [dict(Kernel_Name=r["Kernel_Name"], t=float(r["Start_Timestamp"]),
+                   us=(float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e3)
+              for r in rows if re.search(kernel_filter, r["Kernel_Name"])]
+        rs.sort(key=lambda r: r["t"])
+        agg = {}
+        for name, cls, v in classify_launches(rs, "us"):
+            agg.setdefault((name, cls), []).append(v)
+        lines.append("# launches by position: %s" % os.path.relpath(path, directory))
+        lines.append("name | position | working_dispatches | avg_us | min_us | max_us")
+        for (name, cls), v in sorted(agg.items()):
+            lines.append("%s | %s | %d | %.2f | %.2f | %.2f" % (name, cls, len(v), sum(v) / len(v),
+                                                              min(v), max(v)))
+    for path, rows in _csv_rows(directory, "counter_collection.csv"):
+        per = {}
+        for r in rows:
+            if re.search(kernel_filter, r["Kernel_Name"]):
+                per.setdefault(r["Counter_Name"], []).append(
+                    dict(Kernel_Name=r["Kernel_Name"], t=int(r["Dispatch_Id"]),
+                         v=float(r["Counter_Value"])))
+        lines.append("# counters by position: %s" % os.path.relpath(path, directory))
+        lines.append("name | position | counter | working_dispatches | mean")
+        for cn, rs in sorted(per.items()):
+            rs.sort(key=lambda r: r["t"])
+            agg = {}
+            for name, cls, v in classify_launches(rs, "v"):
+                agg.setdefault((name, cls), []).append(v)
+            for (name, cls), v in sorted(agg.items()):
+                lines.append("%s | %s | %s | %d | %.1f" % (name, cls, cn, len(v), sum(v) / len(v)))
+    print("\n".join(lines))
+
+
 def traffic_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, kernel, command):
     """HBM bytes per working dispatch of `kernel` from FETCH_SIZE / WRITE_SIZE
     (KiB per dispatch), each scaled by the same counter's reading for a plain
@@ -776,6 +850,9 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="only mixed-precision batched solves of 64 right-hand sides on "
                          "256x256x64 with the committed tuning (for profiler runs)")
+    ap.add_argument("--ops-only", action="store_true",
+                    help="only the operator and the line preconditioner alone on 512x512x128 "
+                         "(FP64 and FP32), --steps launches each (for profiler runs)")
     ap.add_argument("--main-only", action="store_true",
                     help="only the timed loop (for profiler runs): no extras, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -783,6 +860,9 @@ def main():
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="print a text summary of rocprofv3 CSV output under DIR and exit")
+    ap.add_argument("--summarize-launches", metavar="DIR",
+                    help="print per-position (first / second / steady-state launch) kernel "
+                         "durations and counter means from rocprofv3 CSV output under DIR")
     ap.add_argument("--traffic-summary", nargs=5,
                     metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="print the HBM traffic summary of a fused kernel (fused_apply or "
@@ -792,6 +872,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(args.summarize_rocprof)
+        return
+    if args.summarize_launches:
+        summarize_launches(args.summarize_launches)
         return
     if args.traffic_summary:
         k, fd, wd, cfd, cwd = args.traffic_summary
@@ -810,6 +893,22 @@ def main():
     import paper_1302_7193_amd as pcg
     import synth_inputs as si
     torch.cuda.set_device(0)
+
+    if args.ops_only:
+        d = pcg.pcg_desc_from_ratio(512, 512, 128, 1.05, 1e5, pcg.PCG_BC_PERIODIC)
+        P = pcg.Problem(d)
+        out = {}
+        for dt, td in ((pcg.PCG_F64, torch.float64), (pcg.PCG_F32, torch.float32)):
+            xv = si.uniform_pm1_torch(21, P.n).to(td)
+            yv = torch.empty_like(xv)
+            ms_a = cuda_time(torch, lambda: pcg.pcg_apply(P, dt, xv, yv), args.steps)
+            ms_p = cuda_time(torch, lambda: pcg.pcg_precond(P, dt, xv, yv), args.steps)
+            e = xv.element_size()
+            out["fp64" if dt == pcg.PCG_F64 else "fp32"] = dict(
+                apply_us=ms_a * 1e3, apply_GBps=2 * e * P.n / (ms_a * 1e-3) / 1e9,
+                precond_us=ms_p * 1e3, precond_GBps=2 * e * P.n / (ms_p * 1e-3) / 1e9)
+        print(json.dumps(out))
+        return
 
     if args.mixed_only or args.batched_only:
         print(json.dumps(profile_run(pcg, si, torch, args.steps, args.mixed_only)))

@@ -97,3 +97,22 @@ def test_whole_solve_bytes_by_enumeration():
         updates = (4 + 8) + (8 + 4 + 8) * (s - 1)       # u32 [, x] in, x out
         want = sum(inner(k, 4) for k in ks) + residuals + updates
         assert bench.mixed_solve_bytes(sum(ks), s, n) == n * want, ks
+
+
+def test_launch_positions_of_a_synthetic_trace():
+    """Kernel A's and B's launches are labelled by their position within
+    each solve (reset at the exit correction and the refinement kernels);
+    early-exit launches are left out."""
+    A = "void pcg::k_fused_apply<float, 4, true, false, true, false>(pcg::ColArgs)"
+    B = "void pcg::k_fused_prec<float, 4, true, false, true, false>(pcg::ColArgs)"
+    F = "void pcg::k_fixup<float, 4, true, true>(pcg::ColArgs)"
+    R = "void pcg::k_residual64<4, true, false>(pcg::ColArgs)"
+    seq = [(R, 100), (B, 60), (A, 50), (B, 90), (A, 80), (B, 90), (A, 100), (B, 90),
+           (A, 2), (B, 1), (F, 40), (R, 100), (B, 61), (A, 51), (B, 91), (A, 2), (F, 30)]
+    rows = [dict(Kernel_Name=n, us=float(v)) for n, v in seq]
+    got = bench.classify_launches(rows, "us")
+    labels = [(n[:20], c, v) for n, c, v in got if n in (A, B)]
+    assert labels == [(B[:20], "first", 60), (A[:20], "first", 50), (B[:20], "steady", 90),
+                      (A[:20], "second", 80), (B[:20], "steady", 90), (A[:20], "steady", 100),
+                      (B[:20], "steady", 90), (B[:20], "first", 61), (A[:20], "first", 51),
+                      (B[:20], "steady", 91)]
