@@ -741,10 +741,10 @@ def classify_launches(rows, value_key):
     pos, out = {}, []
     for r in rows:
         name = r["Kernel_Name"]
+        if r[value_key] < 0.1 * top[name]:
+            continue              # returned at once (an exit correction included)
         if BOUNDARY.search(name):
             pos = {}
-        if r[value_key] < 0.1 * top[name]:
-            continue
         classes = launch_position(name)
         i = pos.get(name, 0)
         pos[name] = i + 1
@@ -752,7 +752,7 @@ def classify_launches(rows, value_key):
     return out
 
 
-def summarize_launches(directory, kernel_filter=r"k_\w+|copy"):
+def summarize_launches(directory, kernel_filter=r"pcg::.*k_\w+|copyBuffer"):
     """Per kernel and launch position (first / second / steady state within
     each solve): dispatches that did work and their mean duration (kernel
     trace) or mean counter value (counter runs)."""
@@ -786,6 +786,44 @@ def summarize_launches(directory, kernel_filter=r"k_\w+|copy"):
                 agg.setdefault((name, cls), []).append(v)
             for (name, cls), v in sorted(agg.items()):
                 lines.append("%s | %s | %s | %d | %.1f" % (name, cls, cn, len(v), sum(v) / len(v)))
+    print("\n".join(lines))
+
+
+def traffic_by_position(fetch_dir, write_dir, cfetch_dir, cwrite_dir,
+                        kernel_filter=r"pcg::.*k_\w+"):
+    """HBM bytes per working dispatch of every kernel by launch position, from
+    FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), each scaled by the
+    same counter's reading for a plain 1 GiB device copy (--copy-probe)."""
+    def means(directory, counter, pattern):
+        vals = []
+        for _, rows in _csv_rows(directory, "counter_collection.csv"):
+            vals += [float(r["Counter_Value"]) for r in rows
+                     if r["Counter_Name"] == counter and re.search(pattern, r["Kernel_Name"])]
+        w = _working(vals)
+        return sum(w) / len(w)
+
+    def by_pos(directory, counter):
+        rs = []
+        for _, rows in _csv_rows(directory, "counter_collection.csv"):
+            rs += [dict(Kernel_Name=r["Kernel_Name"], t=int(r["Dispatch_Id"]),
+                        v=float(r["Counter_Value"])) for r in rows
+                   if r["Counter_Name"] == counter and re.search(kernel_filter, r["Kernel_Name"])]
+        rs.sort(key=lambda r: r["t"])
+        agg = {}
+        for name, cls, v in classify_launches(rs, "v"):
+            agg.setdefault((name, cls), []).append(v)
+        return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
+
+    gib_kib = float(1 << 20)
+    ff = gib_kib / means(cfetch_dir, "FETCH_SIZE", "copyBuffer")
+    fw = gib_kib / means(cwrite_dir, "WRITE_SIZE", "copyBuffer")
+    f, w = by_pos(fetch_dir, "FETCH_SIZE"), by_pos(write_dir, "WRITE_SIZE")
+    lines = ["# scale factors from a 1 GiB copy: fetch x %.4f, write x %.4f" % (ff, fw),
+             "name | position | fetch_kib | write_kib | dispatches | hbm_bytes_per_launch"]
+    for key in sorted(set(f) & set(w)):
+        (fv, nf), (wv, nw) = f[key], w[key]
+        lines.append("%s | %s | %.1f | %.1f | %d | %.0f" % (key[0], key[1], fv, wv, min(nf, nw),
+                                                          (fv * ff + wv * fw) * 1024))
     print("\n".join(lines))
 
 
@@ -863,6 +901,10 @@ def main():
     ap.add_argument("--summarize-launches", metavar="DIR",
                     help="print per-position (first / second / steady-state launch) kernel "
                          "durations and counter means from rocprofv3 CSV output under DIR")
+    ap.add_argument("--traffic-by-position", nargs=4,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="print HBM bytes per launch of every kernel by launch position from "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE runs and exit")
     ap.add_argument("--traffic-summary", nargs=5,
                     metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="print the HBM traffic summary of a fused kernel (fused_apply or "
@@ -872,6 +914,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(args.summarize_rocprof)
+        return
+    if args.traffic_by_position:
+        traffic_by_position(*args.traffic_by_position)
         return
     if args.summarize_launches:
         summarize_launches(args.summarize_launches)
