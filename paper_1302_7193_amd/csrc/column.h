@@ -199,19 +199,22 @@ __device__ __forceinline__ void st1(T* p, T v)
     else *p = v;
 }
 
+// The vector path loads unconditionally (a chunk outside the grid or past
+// n_z reads the vector's first chunk instead) and zeroes the result by a
+// select: no branch around the load, so the compiler can issue the loads of
+// a column and of its neighbours together and wait for them once.
 template <typename T, int M, bool V, bool NT = false>
 __device__ __forceinline__ void ld(const T* __restrict__ v, int64_t col, bool ok, int k0,
                                    int nz, T (&o)[M])
 {
     if (V) {
-        if (ok && k0 < nz) {
-            const T* p = static_cast<const T*>(__builtin_assume_aligned(v + col * nz + k0, 16));
+        const bool in = ok && k0 < nz;
+        const T* p = static_cast<const T*>(
+            __builtin_assume_aligned(v + (in ? col * nz + k0 : int64_t(0)), 16));
 #pragma unroll
-            for (int t = 0; t < M; ++t) o[t] = ld1<NT>(p + t);
-        } else {
+        for (int t = 0; t < M; ++t) o[t] = ld1<NT>(p + t);
 #pragma unroll
-            for (int t = 0; t < M; ++t) o[t] = T(0);
-        }
+        for (int t = 0; t < M; ++t) o[t] = in ? o[t] : T(0);
     } else {
 #pragma unroll
         for (int t = 0; t < M; ++t) {
@@ -294,16 +297,16 @@ __device__ __forceinline__ void stencil_nb(const Geom& g, const Col& c, int l, i
                                            const T (&xc)[M], const VertCoef<T, M>& vc,
                                            NbLoad&& nb, T (&y)[M])
 {
-    T below = dpp_move<kWaveShr1>(xc[M - 1], T(0));
-    T above = dpp_move<kWaveShl1>(xc[0], T(0));
-    if (l == 0) below = T(0);
-    if (l == L - 1) above = T(0);
-
     T xim[M], xip[M], xjm[M], xjp[M];
     nb(0, c.im, c.ok && c.im >= 0, xim);
     nb(1, c.ip, c.ok && c.ip >= 0, xip);
     nb(2, c.jm, c.ok && c.jm >= 0, xjm);
     nb(3, c.jp, c.ok && c.jp >= 0, xjp);
+
+    T below = dpp_move<kWaveShr1>(xc[M - 1], T(0));
+    T above = dpp_move<kWaveShl1>(xc[0], T(0));
+    if (l == 0) below = T(0);
+    if (l == L - 1) above = T(0);
 
     const T at = T(c.alpha_t);
     if constexpr (G) {

@@ -11,11 +11,14 @@ namespace {
 
 // ---------------------------------------------------------------- kernels --
 
-template <typename T, int M, bool V, bool G>
+// W: one column per wavefront (L = 64, column index scalar); NT: the
+// vectors streamed once carry the nontemporal hint (x is not one of them:
+// its columns are re-read as the horizontal neighbours of others).
+template <typename T, int M, bool V, bool G, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     if (a.st && a.st[rhs].flag != kRunning) return;   // inside a solve: stop when done
@@ -27,19 +30,19 @@ __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         T xc[M], yc[M];
         ld<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
         stencil<T, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, yc);
-        st<T, M, V>(y, c.idx, c.ok, p.k0, g.nz, yc);
+        st<T, M, V, NT>(y, c.idx, c.ok, p.k0, g.nz, yc);
     }
 }
 
-template <typename T, int M, bool V, bool G>
+template <typename T, int M, bool V, bool G, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     if (a.st && a.st[rhs].flag != kRunning) return;
@@ -51,20 +54,20 @@ __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         T rc[M], zc[M];
-        ld<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+        ld<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
         line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, rc, zc);
-        st<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
+        st<T, M, V, NT>(z, c.idx, c.ok, p.k0, g.nz, zc);
     }
 }
 
 // r = b - A x; ZERO: x = 0, r = b (nothing to copy when b is r), p = q = 0.
-template <typename T, int M, bool V, bool ZERO, bool G>
+template <typename T, int M, bool V, bool ZERO, bool G, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     const int64_t off = rhs * g.n;
@@ -83,26 +86,26 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
 #pragma unroll
     for (int i = 0; i < M; ++i) zero[i] = T(0);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         if (ZERO) {
-            st<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, zero);
+            st<T, M, V, NT>(x, c.idx, c.ok, p.k0, g.nz, zero);
             if (!in_place) {
                 T bc[M];
-                ld<T, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
-                st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, bc);
+                ld<T, M, V, NT>(b, c.idx, c.ok, p.k0, g.nz, bc);
+                st<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, bc);
             }
         } else {
             T bc[M], rc[M], xc[M], ax[M];
-            ld<T, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
+            ld<T, M, V, NT>(b, c.idx, c.ok, p.k0, g.nz, bc);
             ld<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
             stencil<T, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, ax);
 #pragma unroll
             for (int i = 0; i < M; ++i) rc[i] = bc[i] - ax[i];
-            st<T, M, V>(r, c.idx, c.ok, p.k0, g.nz, rc);
+            st<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
         }
         if (ZERO) {   // the unfused iteration reads p and q; the fused one does not
-            st<T, M, V>(pp, c.idx, c.ok, p.k0, g.nz, zero);
-            st<T, M, V>(q, c.idx, c.ok, p.k0, g.nz, zero);
+            st<T, M, V, NT>(pp, c.idx, c.ok, p.k0, g.nz, zero);
+            st<T, M, V, NT>(q, c.idx, c.ok, p.k0, g.nz, zero);
         }
     }
 }
@@ -254,11 +257,11 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
 // Exit correction u += alpha p (the fused iteration leaves u one step
 // behind r).  Runs once: the last workgroup (or the finalize launch) marks
 // it done.
-template <typename T, int M, bool V, bool NT>
+template <typename T, int M, bool V, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col(g, tile_col(tile, p, L));
+        const Col c = make_col(g, W ? wave_col(tile, p) : tile_col(tile, p, L));
         T uc[M];
         if (none) {
 #pragma unroll
@@ -308,11 +311,11 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
 }
 
 // FP64 true residual: ||b - A x|| into state.aux (T = double only).
-template <int M, bool V, bool G>
+template <int M, bool V, bool G, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
@@ -325,10 +328,10 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     double acc[1] = {0.0};
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         double xc[M], ax[M], bc[M];
         ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
-        ld<double, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
+        ld<double, M, V, NT>(b, c.idx, c.ok, p.k0, g.nz, bc);
         stencil<double, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, ax);
 #pragma unroll
         for (int i = 0; i < M; ++i) {
@@ -346,11 +349,11 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
 // Refinement residual: r64 = b - A x in FP64 (r64 = b when a.x0_zero),
 // ||r64|| into state.rnorm (state.r0norm on the first call), FP32 copy
 // r32 = r64 * scale.
-template <int M, bool V, bool G>
+template <int M, bool V, bool G, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
@@ -366,10 +369,10 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     double acc[1] = {0.0};
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, tile_col(tile, p, L), a.hgeo);
+        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
         double xc[M], ax[M], bc[M];
         float rc[M];
-        ld<double, M, V>(b, c.idx, c.ok, p.k0, g.nz, bc);
+        ld<double, M, V, NT>(b, c.idx, c.ok, p.k0, g.nz, bc);
         if (a.x0_zero) {
 #pragma unroll
             for (int i = 0; i < M; ++i) ax[i] = 0.0;
@@ -384,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
             rc[i] = float(d * scale);
         }
         // FP32 rows are 16-byte aligned only when M*4 is a multiple of 16
-        st<float, M, (V && (M % 4 == 0))>(r32, c.idx, c.ok, p.k0, g.nz, rc);
+        st<float, M, (V && (M % 4 == 0)), NT>(r32, c.idx, c.ok, p.k0, g.nz, rc);
     }
     double tot[1];
     if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
@@ -399,11 +402,11 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
 
 // Refinement update: x64 += (1/scale) * u32, u32 being the inner solution
 // (x64 = u32 / scale when a.x0_zero: x is not read).
-template <int M, bool V>
+template <int M, bool V, bool NT, bool W>
 __global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
 {
     const Geom& g = a.g;
-    const int L = a.L;
+    const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
@@ -415,19 +418,19 @@ __global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col(g, tile_col(tile, p, L));
+        const Col c = make_col(g, W ? wave_col(tile, p) : tile_col(tile, p, L));
         double xc[M];
         float uc[M];
         if (a.x0_zero) {
 #pragma unroll
             for (int i = 0; i < M; ++i) xc[i] = 0.0;
         } else {
-            ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+            ld<double, M, V, NT>(x, c.idx, c.ok, p.k0, g.nz, xc);
         }
-        ld<float, M, (V && (M % 4 == 0))>(u32, c.idx, c.ok, p.k0, g.nz, uc);
+        ld<float, M, (V && (M % 4 == 0)), NT>(u32, c.idx, c.ok, p.k0, g.nz, uc);
 #pragma unroll
         for (int i = 0; i < M; ++i) xc[i] += inv_scale * double(uc[i]);
-        st<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+        st<double, M, V, NT>(x, c.idx, c.ok, p.k0, g.nz, xc);
     }
 }
 
@@ -490,40 +493,39 @@ template <typename T, int M, bool V, bool G, bool NT, bool W>
 const void* main_func_m(Kind kind)
 {
     switch (kind) {
-    case Kind::Apply: return reinterpret_cast<const void*>(&k_apply<T, M, V, G>);
-    case Kind::Precond: return reinterpret_cast<const void*>(&k_precond<T, M, V, G>);
-    case Kind::InitFull: return reinterpret_cast<const void*>(&k_init<T, M, V, false, G>);
-    case Kind::InitZero: return reinterpret_cast<const void*>(&k_init<T, M, V, true, false>);
+    case Kind::Apply: return reinterpret_cast<const void*>(&k_apply<T, M, V, G, NT, W>);
+    case Kind::Precond: return reinterpret_cast<const void*>(&k_precond<T, M, V, G, NT, W>);
+    case Kind::InitFull: return reinterpret_cast<const void*>(&k_init<T, M, V, false, G, NT, W>);
+    case Kind::InitZero: return reinterpret_cast<const void*>(&k_init<T, M, V, true, false, NT, W>);
     case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G, NT, W>);
     case Kind::FusedApply: return reinterpret_cast<const void*>(&k_fused_apply<T, M, V, G, NT, W>);
-    case Kind::Fixup: return reinterpret_cast<const void*>(&k_fixup<T, M, V, NT>);
+    case Kind::Fixup: return reinterpret_cast<const void*>(&k_fixup<T, M, V, NT, W>);
     case Kind::TrueResidual:
         if constexpr (sizeof(T) == 8)
-            return reinterpret_cast<const void*>(&k_true_residual<M, V, G>);
+            return reinterpret_cast<const void*>(&k_true_residual<M, V, G, NT, W>);
         return nullptr;
     case Kind::Residual64:
-        if constexpr (sizeof(T) == 8) return reinterpret_cast<const void*>(&k_residual64<M, V, G>);
+        if constexpr (sizeof(T) == 8)
+            return reinterpret_cast<const void*>(&k_residual64<M, V, G, NT, W>);
         return nullptr;
     case Kind::Update64:
-        if constexpr (sizeof(T) == 8) return reinterpret_cast<const void*>(&k_update64<M, V>);
+        if constexpr (sizeof(T) == 8)
+            return reinterpret_cast<const void*>(&k_update64<M, V, NT, W>);
         return nullptr;
+    default: return nullptr;
     }
-    return nullptr;
 }
 
 template <typename T, int M, bool V, bool G>
 const void* main_func_n(Kind kind, bool nt, bool w)
 {
-    // one column per wavefront: only the two fused kernels have that variant
     // the nontemporal variants exist only where the hint is used: one
-    // 16-byte chunk per lane and vector
+    // 16-byte chunk per lane and vector; one column per wavefront: L = 64
     if constexpr (M * sizeof(T) == 16) {
-        if (w && (kind == Kind::FusedApply || kind == Kind::FusedPrec))
-            return nt ? main_func_m<T, M, V, G, true, true>(kind) : main_func_m<T, M, V, G, false, true>(kind);
+        if (w) return nt ? main_func_m<T, M, V, G, true, true>(kind) : main_func_m<T, M, V, G, false, true>(kind);
         return nt ? main_func_m<T, M, V, G, true, false>(kind) : main_func_m<T, M, V, G, false, false>(kind);
     } else {
-        if (w && (kind == Kind::FusedApply || kind == Kind::FusedPrec))
-            return main_func_m<T, M, V, G, false, true>(kind);
+        if (w) return main_func_m<T, M, V, G, false, true>(kind);
         return main_func_m<T, M, V, G, false, false>(kind);
     }
 }
