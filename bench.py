@@ -117,7 +117,8 @@ def kernel_source_hash() -> str:
     """Hash of the sources the fused kernels A and B are built from: a traffic
     summary taken with other sources does not describe them."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "column.h", "device_common.h", "internal.h"):
+    for f in ("kernels.h", "kernels_f64.hip", "kernels_f32.hip", "column.h", "device_common.h",
+              "internal.h"):
         with open(os.path.join(ROOT, "paper_1302_7193_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -1,4 +1,4 @@
-// Device building blocks of the column kernels (included by kernels.hip and
+// Device building blocks of the column kernels (included by kernels.h and
 // mg.hip): per-column geometry, column loads and stores, the matrix-free
 // stencil and the vertical line solve.
 //
@@ -199,18 +199,27 @@ __device__ __forceinline__ void st1(T* p, T v)
     else *p = v;
 }
 
-// The vector path loads unconditionally (a chunk outside the grid or past
-// n_z reads the vector's first chunk instead) and zeroes the result by a
-// select: no branch around the load, so the compiler can issue the loads of
-// a column and of its neighbours together and wait for them once.
+// The vector path loads unconditionally (a chunk outside the grid reads
+// column 0, a lane past n_z the column's last chunk) and zeroes the result
+// by a select: no branch around the load, so the compiler can issue the
+// loads of a column and of its neighbours together and wait for them once.
+// The column part of the address stays uniform when the column is (one
+// column per wavefront), so the loads take a scalar base and a per-lane
+// offset.
+// Alignment of a lane's chunk of M values in the vector path (whole chunks,
+// rows a multiple of the chunk): its size, at most 16 bytes.
+template <typename T, int M>
+constexpr size_t kChunkAlign = M * sizeof(T) >= 16 ? 16 : M * sizeof(T);
+
 template <typename T, int M, bool V, bool NT = false>
 __device__ __forceinline__ void ld(const T* __restrict__ v, int64_t col, bool ok, int k0,
                                    int nz, T (&o)[M])
 {
     if (V) {
         const bool in = ok && k0 < nz;
-        const T* p = static_cast<const T*>(
-            __builtin_assume_aligned(v + (in ? col * nz + k0 : int64_t(0)), 16));
+        const uint32_t kk = uint32_t(k0 < nz ? k0 : nz - M);
+        const T* base = v + (ok ? col : int64_t(0)) * nz;
+        const T* p = static_cast<const T*>(__builtin_assume_aligned(base + kk, kChunkAlign<T, M>));
 #pragma unroll
         for (int t = 0; t < M; ++t) o[t] = ld1<NT>(p + t);
 #pragma unroll
@@ -230,7 +239,8 @@ __device__ __forceinline__ void st(T* __restrict__ v, int64_t col, bool ok, int 
 {
     if (V) {
         if (ok && k0 < nz) {
-            T* p = static_cast<T*>(__builtin_assume_aligned(v + col * nz + k0, 16));
+            T* base = v + col * nz;
+            T* p = static_cast<T*>(__builtin_assume_aligned(base + k0, kChunkAlign<T, M>));
 #pragma unroll
             for (int t = 0; t < M; ++t) st1<NT>(p + t, o[t]);
         }
@@ -241,6 +251,17 @@ __device__ __forceinline__ void st(T* __restrict__ v, int64_t col, bool ok, int 
             if (ok && k < nz) st1<NT>(v + col * nz + k, o[t]);
         }
     }
+}
+
+// Marks values as computed at this point (an empty statement that uses and
+// redefines their registers): a value used only by a store inside the
+// store's guard would otherwise be computed, and its load issued, inside
+// that guard -- after the tile's other loads had been waited for.
+template <typename T, int M>
+__device__ __forceinline__ void keep_here(T (&v)[M])
+{
+#pragma unroll
+    for (int i = 0; i < M; ++i) asm volatile("" : "+v"(v[i]));
 }
 
 // Level table row `comp` (length nzp, zero-padded), levels k0..k0+M-1.
@@ -333,6 +354,40 @@ __device__ __forceinline__ void stencil_nb(const Geom& g, const Col& c, int l, i
             y[t] = vertical + horizontal;
         }
     }
+}
+
+// A stencil's inputs loaded ahead of its arithmetic: the column's levels and
+// the same levels of its four horizontal neighbours (zeros across Dirichlet
+// faces).  Loading them first, together with a kernel's other loads, lets
+// all of a tile's memory accesses be in flight at once.
+template <typename T, int M>
+struct StencilIn {
+    T xc[M];
+    T nb[4][M];
+};
+
+template <typename T, int M, bool V>
+__device__ __forceinline__ void load_stencil(const Geom& g, const Col& c, int k0,
+                                             const T* __restrict__ x, StencilIn<T, M>& in)
+{
+    ld<T, M, V>(x, c.idx, c.ok, k0, g.nz, in.xc);
+    ld<T, M, V>(x, c.im, c.ok && c.im >= 0, k0, g.nz, in.nb[0]);
+    ld<T, M, V>(x, c.ip, c.ok && c.ip >= 0, k0, g.nz, in.nb[1]);
+    ld<T, M, V>(x, c.jm, c.ok && c.jm >= 0, k0, g.nz, in.nb[2]);
+    ld<T, M, V>(x, c.jp, c.ok && c.jp >= 0, k0, g.nz, in.nb[3]);
+}
+
+template <typename T, int M, bool G = false>
+__device__ __forceinline__ void stencil_in(const Geom& g, const Col& c, int l, int L,
+                                           const StencilIn<T, M>& in, const VertCoef<T, M>& vc,
+                                           T (&y)[M])
+{
+    stencil_nb<T, M, G>(g, c, l, L, in.xc, vc,
+                        [&](int d, int64_t, bool, T (&o)[M]) {
+#pragma unroll
+                            for (int t = 0; t < M; ++t) o[t] = in.nb[d][t];
+                        },
+                        y);
 }
 
 template <typename T, int M, bool V, bool G = false>

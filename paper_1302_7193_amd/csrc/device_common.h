@@ -120,13 +120,14 @@ __device__ __forceinline__ void sum_partials(const double* part, int64_t nblk, d
         for (int i = 0; i < NV; ++i) acc[r][i] = 0.0;
         const int64_t v = threadIdx.x + (int64_t)r * BS;
         auto load = [&](int64_t b, int i) {
-            const double* q = &part[b * kRedSlots + i];
+            const double* q = &part[b * NV + i];
             return COHERENT ? __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *q;
         };
         int64_t b = v;
-        // U loads in flight, added in slot order: the latency of reading
-        // partials written by other XCDs sets the finalize launch's time (32
-        // in flight); inside a main kernel (COHERENT) 8 keep its registers low
+        // U slots' loads in flight, added in slot order: the latency of
+        // reading partials written by other XCDs sets the finalize launch's
+        // time (32 in flight); inside a main kernel (COHERENT) 8 keep its
+        // registers low
         auto chunk = [&](auto U_) {
             constexpr int U = decltype(U_)::value;
             for (; b + (U - 1) * (int64_t)kFinalThreads < nblk; b += U * (int64_t)kFinalThreads) {
@@ -166,7 +167,9 @@ __device__ __forceinline__ void sum_partials(const double* part, int64_t nblk, d
     __syncthreads();
 }
 
-// Publish this workgroup's sums of v in slot blk of part.
+// Publish this workgroup's sums of v in slot blk of part (component i of
+// slot b at part[b * NV + i]: the slots of a reduction of one value are
+// dense, those of two values one 16-byte pair each).
 //   mode 0: the workgroup that finishes last (atomic ticket) totals all slots
 //           and returns true with the totals in tot -- the scalar step then
 //           runs inside this kernel, at the price of device-scope fences in
@@ -182,7 +185,7 @@ __device__ __forceinline__ bool publish(double (&v)[NV], double* part, int64_t b
     if (mode != 0) {
         if (threadIdx.x == 0) {
 #pragma unroll
-            for (int i = 0; i < NV; ++i) part[blk * kRedSlots + i] = bs[i];
+            for (int i = 0; i < NV; ++i) part[blk * NV + i] = bs[i];
         }
         return false;
     }
@@ -190,7 +193,7 @@ __device__ __forceinline__ bool publish(double (&v)[NV], double* part, int64_t b
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            __hip_atomic_store(&part[blk * kRedSlots + i], bs[i], __ATOMIC_RELAXED,
+            __hip_atomic_store(&part[blk * NV + i], bs[i], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         const uint32_t t = atomicAdd(ticket, 1u);

@@ -123,6 +123,8 @@ enum class Kind : int {
     Residual64,   // FP64 r = b - A x, ||r||; FP32 copy r * scale  (refinement)
     Update64,     // FP64 x += u32 / scale                         (refinement)
     TrueResidual, // FP64 ||b - A x||
+    FusedPrecFirst,  // kernel B's first launch in a solve (alpha = 0, q unset)
+    FusedApplyFirst, // kernel A's first launch in a solve (p = z, q = A z)
     // tensor-product multigrid preconditioner (mg.hip), on one level each:
     MgPre,        // z = omega M^{-1} r                      (pre-smoothing from zero)
     MgPreFused,   // the same, first: r -= alpha q, as kernel B does
@@ -160,9 +162,10 @@ struct ColArgs {
     void* io4;          // q
     void* out32;        // FP32 vector of the refinement kernels
     SolverState* st;    // per right-hand side
-    double* part;       // [batch][blocks_per_rhs][kRedSlots]
+    double* part;       // [batch][blocks_per_rhs][values reduced (1 or 2)]
     int red_mode;       // 0: last workgroup finishes reductions; 1: finalize launch
-    int x0_zero;        // refinement kernels: x is zero (not read)
+    int x0_zero;        // x is zero (not read): refinement kernels, and kernel B's first
+                        // launch, which then takes r from b
     const double* hgeo; // stretched grids: per-index widths and face weights
                         // [w_x m_x p_x](n_x) [w_y m_y p_y](n_y); null when uniform
     // multigrid kernels: the other level of an intergrid transfer (the fine
@@ -186,7 +189,7 @@ const void* mg_func(Kind kind, const ColArgs& a, int64_t batch);
 template <typename T>
 const void* rb_func(Kind kind, const ColArgs& a, int64_t batch);
 
-// Host launchers (kernels.hip): T = double or float.  column_launches
+// Host launchers (kernels.h): T = double or float.  column_launches
 // returns the kernel (and, for mode-1 reductions, its finalize kernel) with
 // launch dimensions, for direct launches or graph nodes; launch_column
 // issues both; launch_column_main / launch_column_finalize issue them

@@ -3,18 +3,54 @@
 // Alg. InterleavedPCG, the exit correction, the refinement kernels of the
 // mixed-precision form, their finalize launches, and the host-side
 // dispatch.  The building blocks (work decomposition, stencil, line solve)
-// are in column.h.
+// are in column.h.  kernels_f64.hip and kernels_f32.hip instantiate the
+// launchers for one precision each (two translation units that compile in
+// parallel).
+#pragma once
+
+#include <algorithm>
+
 #include "column.h"
 
 namespace pcg {
 namespace {
 
+// Tiles a wavefront takes at a time in the kernels with a single input
+// stream (the operator and the preconditioner alone, the first launches of
+// kernels A and B): their loads are issued together before any arithmetic.
+constexpr int kStepApply = 4, kStepPrecond = 2, kStepFirstA = 4, kStepFirstB = 2;
+
+int step_of(Kind k)
+{
+    switch (k) {
+    case Kind::Apply: return kStepApply;
+    case Kind::Precond: return kStepPrecond;
+    case Kind::FusedApplyFirst: return kStepFirstA;
+    case Kind::FusedPrecFirst: return kStepFirstB;
+    default: return 1;
+    }
+}
+
 // ---------------------------------------------------------------- kernels --
+
+// Column c of wavefront step `tile` (U tiles per step): the column index of
+// tile + u, or one past the grid (make_col then marks it absent) beyond t1.
+template <bool W>
+__device__ __forceinline__ int64_t step_col(const Geom& g, int64_t tile, int u, int64_t t1,
+                                            const Lane& p, int L)
+{
+    const int64_t tu = tile + u;
+    if (tu >= t1) return g.nh;
+    return W ? wave_col(tu, p) : tile_col(tu, p, L);
+}
 
 // W: one column per wavefront (L = 64, column index scalar); NT: the
 // vectors streamed once carry the nontemporal hint (x is not one of them:
-// its columns are re-read as the horizontal neighbours of others).
-template <typename T, int M, bool V, bool G, bool NT, bool W>
+// its columns are re-read as the horizontal neighbours of others).  U: each
+// wavefront takes U tiles at a time and issues the loads of all of them
+// before computing any: a kernel with one input stream otherwise keeps too
+// few bytes in flight to cover the memory latency.
+template <typename T, int M, bool V, bool G, bool NT, bool W, int U>
 __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
 {
     const Geom& g = a.g;
@@ -29,16 +65,22 @@ __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
     const VertCoef<T, M> vc = load_vert<T, M, V>(g, vert, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
-        T xc[M], yc[M];
-        ld<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
-        stencil<T, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, yc);
-        st<T, M, V, NT>(y, c.idx, c.ok, p.k0, g.nz, yc);
+    for (int64_t tile = t0; tile < t1; tile += U) {
+        Col c[U];
+        StencilIn<T, M> in[U];
+        T yc[U][M];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = make_col<G>(g, step_col<W>(g, tile, u, t1, p, L), a.hgeo);
+#pragma unroll
+        for (int u = 0; u < U; ++u) load_stencil<T, M, V>(g, c[u], p.k0, x, in[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) stencil_in<T, M, G>(g, c[u], p.l, L, in[u], vc, yc[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) st<T, M, V, NT>(y, c[u].idx, c[u].ok, p.k0, g.nz, yc[u]);
     }
 }
 
-template <typename T, int M, bool V, bool G, bool NT, bool W>
+template <typename T, int M, bool V, bool G, bool NT, bool W, int U>
 __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
 {
     const Geom& g = a.g;
@@ -53,12 +95,17 @@ __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
     const SolveCoef<T, M, G> sc = load_solve<T, M, V, G>(g, a, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
-        T rc[M], zc[M];
-        ld<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
-        line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, rc, zc);
-        st<T, M, V, NT>(z, c.idx, c.ok, p.k0, g.nz, zc);
+    for (int64_t tile = t0; tile < t1; tile += U) {
+        Col c[U];
+        T rc[U][M], zc[U][M];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = make_col<G>(g, step_col<W>(g, tile, u, t1, p, L), a.hgeo);
+#pragma unroll
+        for (int u = 0; u < U; ++u) ld<T, M, V, NT>(r, c[u].idx, c[u].ok, p.k0, g.nz, rc[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) line_solve<T, M, V, G>(g, c[u], p.l, L, p.k0, lu, sc, rc[u], zc[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) st<T, M, V, NT>(z, c[u].idx, c[u].ok, p.k0, g.nz, zc[u]);
     }
 }
 
@@ -95,10 +142,11 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
                 st<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, bc);
             }
         } else {
-            T bc[M], rc[M], xc[M], ax[M];
+            T bc[M], rc[M], ax[M];
+            StencilIn<T, M> in;
             ld<T, M, V, NT>(b, c.idx, c.ok, p.k0, g.nz, bc);
-            ld<T, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
-            stencil<T, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, ax);
+            load_stencil<T, M, V>(g, c, p.k0, x, in);
+            stencil_in<T, M, G>(g, c, p.l, L, in, vc, ax);
 #pragma unroll
             for (int i = 0; i < M; ++i) rc[i] = bc[i] - ax[i];
             st<T, M, V, NT>(r, c.idx, c.ok, p.k0, g.nz, rc);
@@ -254,6 +302,118 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
     }
 }
 
+// First launch of kernel B in a solve (iteration 0: alpha = 0, q unset),
+// compiled apart from the general kernel so that its wavefronts can take U
+// tiles at a time (its loads issued together, the line solves of the U
+// columns interleaved) without the general kernel's registers: r (or b on a
+// zero start, ColArgs::x0_zero) in, z out, R = <r,r>, kappa = <r,z>, scalar
+// step.  r is not stored (see fused_prec_body).  It runs once per solve, so
+// its loads need not wait for the solver flag: the flag (set only for a
+// right-hand side of a batch that is already done) is read alongside them
+// and checked before anything is stored.
+template <typename T, int M, bool V, bool G, bool NT, bool W, int U>
+__global__ __launch_bounds__(kBlock) void k_fused_prec_first(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = W ? kWave : a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    const int32_t flag = s->flag;
+    const int64_t off = rhs * g.n;
+    const T* src = static_cast<const T*>(a.x0_zero ? a.in1 : a.io1) + off;
+    T* r = static_cast<T*>(a.io1) + off;
+    const bool store_r = a.x0_zero && a.in1 != a.io1 && !a.zswap;
+    T* z = static_cast<T*>(a.io2) + off;
+    const T* lu = static_cast<const T*>(a.lu);
+    const Lane p = lane_pos<M>(L);
+    const SolveCoef<T, M, G> sc = load_solve<T, M, V, G>(g, a, p.k0);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    double acc[2] = {0.0, 0.0};
+    for (int64_t tile = t0; tile < t1; tile += U) {
+        Col c[U];
+        T rc[U][M], zc[U][M];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = make_col<G>(g, step_col<W>(g, tile, u, t1, p, L), a.hgeo);
+#pragma unroll
+        for (int u = 0; u < U; ++u) ld<T, M, V, NT>(src, c[u].idx, c[u].ok, p.k0, g.nz, rc[u]);
+        if (flag != kRunning) return;   // the same in every thread of the workgroup
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) acc[0] += double(rc[u][i]) * double(rc[u][i]);
+            if (store_r) st<T, M, V, NT>(r, c[u].idx, c[u].ok, p.k0, g.nz, rc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) line_solve<T, M, V, G>(g, c[u], p.l, L, p.k0, lu, sc, rc[u], zc[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) acc[1] += double(rc[u][i]) * double(zc[u][i]);
+            st<T, M, V, NT>(z, c[u].idx, c[u].ok, p.k0, g.nz, zc[u]);
+        }
+    }
+    if (flag != kRunning) return;
+    double tot[2];
+    if (publish<2>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                   &s->ticket, a.red_mode, tot)) {
+        if (threadIdx.x == 0) finish_prec(s, tot[0], tot[1]);
+    }
+}
+
+// First launch of kernel A in a solve (iteration 0: alpha = 0, p = q = 0):
+// p = z, q = A z, sigma = <z, A z>, scalar step; U tiles per wavefront
+// step and the solver flag checked before the stores, as in
+// k_fused_prec_first.  z stays in io2 and serves as p when ColArgs::zswap
+// is set; otherwise p = z is stored.  u keeps x0 (a zero start leaves it
+// unwritten until the next launch sets u = alpha p).
+template <typename T, int M, bool V, bool G, bool NT, bool W, int U>
+__global__ __launch_bounds__(kBlock) void k_fused_apply_first(ColArgs a)
+{
+    const Geom& g = a.g;
+    const int L = W ? kWave : a.L;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    const int32_t flag = s->flag;
+    const int64_t off = rhs * g.n;
+    const T* z = static_cast<const T*>(a.io2) + off;
+    T* pp = static_cast<T*>(a.io3) + off;
+    T* q = static_cast<T*>(a.io4) + off;
+    const T* vert = static_cast<const T*>(a.vert);
+    const Lane p = lane_pos<M>(L);
+    const VertCoef<T, M> vc = load_vert<T, M, V>(g, vert, p.k0);
+    int64_t t0, t1;
+    block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
+    double acc[1] = {0.0};
+    for (int64_t tile = t0; tile < t1; tile += U) {
+        Col c[U];
+        StencilIn<T, M> in[U];
+        T az[U][M];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = make_col<G>(g, step_col<W>(g, tile, u, t1, p, L), a.hgeo);
+#pragma unroll
+        for (int u = 0; u < U; ++u) load_stencil<T, M, V>(g, c[u], p.k0, z, in[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) stencil_in<T, M, G>(g, c[u], p.l, L, in[u], vc, az[u]);
+        if (flag != kRunning) return;   // the same in every thread of the workgroup
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) acc[0] += double(in[u].xc[i]) * double(az[u][i]);
+            if (!a.zswap) st<T, M, V, NT>(pp, c[u].idx, c[u].ok, p.k0, g.nz, in[u].xc);
+            st<T, M, V, NT>(q, c[u].idx, c[u].ok, p.k0, g.nz, az[u]);
+        }
+    }
+    if (flag != kRunning) return;
+    double tot[1];
+    if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
+                   &s->ticket, a.red_mode, tot)) {
+        if (threadIdx.x == 0) finish_apply(s, tot[0]);
+    }
+}
+
 // Exit correction u += alpha p (the fused iteration leaves u one step
 // behind r).  Runs once: the last workgroup (or the finalize launch) marks
 // it done.
@@ -329,10 +489,11 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
     double acc[1] = {0.0};
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
-        double xc[M], ax[M], bc[M];
-        ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
+        double ax[M], bc[M];
+        StencilIn<double, M> in;
         ld<double, M, V, NT>(b, c.idx, c.ok, p.k0, g.nz, bc);
-        stencil<double, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, ax);
+        load_stencil<double, M, V>(g, c, p.k0, x, in);
+        stencil_in<double, M, G>(g, c, p.l, L, in, vc, ax);
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             const double d = bc[i] - ax[i];
@@ -346,18 +507,16 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
     }
 }
 
-// Refinement residual: r64 = b - A x in FP64 (r64 = b when a.x0_zero),
-// ||r64|| into state.rnorm (state.r0norm on the first call), FP32 copy
-// r32 = r64 * scale.
-template <int M, bool V, bool G, bool NT, bool W>
-__global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
+// Refinement residual: r64 = b - A x in FP64 (r64 = b when ZERO: x = 0 is
+// not read), ||r64|| into state.rnorm (state.r0norm on the first call), FP32
+// copy r32 = r64 * scale.  The FP32 vectors take the FP64 launch shape:
+// chunks of M floats, aligned to their size whenever the FP64 ones are.
+template <int M, bool V, bool ZERO, bool G, bool NT, bool W>
+__device__ __forceinline__ void residual64_body(const ColArgs& a, SolverState* s, int64_t rhs,
+                                                int64_t blk, double (&acc)[1])
 {
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
-    SolverState* s = a.st + rhs;
-    if (s->flag != kRunning) return;
     const double* x = static_cast<const double*>(a.in0) + rhs * g.n;
     const double* b = static_cast<const double*>(a.in1) + rhs * g.n;
     float* r32 = static_cast<float*>(a.out32) + rhs * g.n;
@@ -367,18 +526,18 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
     const VertCoef<double, M> vc = load_vert<double, M, V>(g, vert, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
-    double acc[1] = {0.0};
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
-        double xc[M], ax[M], bc[M];
+        double ax[M], bc[M];
         float rc[M];
+        StencilIn<double, M> in;
         ld<double, M, V, NT>(b, c.idx, c.ok, p.k0, g.nz, bc);
-        if (a.x0_zero) {
+        if constexpr (ZERO) {
 #pragma unroll
             for (int i = 0; i < M; ++i) ax[i] = 0.0;
         } else {
-            ld<double, M, V>(x, c.idx, c.ok, p.k0, g.nz, xc);
-            stencil<double, M, V, G>(g, c, p.l, L, p.k0, x, xc, vc, ax);
+            load_stencil<double, M, V>(g, c, p.k0, x, in);
+            stencil_in<double, M, G>(g, c, p.l, L, in, vc, ax);
         }
 #pragma unroll
         for (int i = 0; i < M; ++i) {
@@ -386,9 +545,20 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
             acc[0] += d * d;
             rc[i] = float(d * scale);
         }
-        // FP32 rows are 16-byte aligned only when M*4 is a multiple of 16
-        st<float, M, (V && (M % 4 == 0)), NT>(r32, c.idx, c.ok, p.k0, g.nz, rc);
+        st<float, M, V, NT>(r32, c.idx, c.ok, p.k0, g.nz, rc);
     }
+}
+
+template <int M, bool V, bool G, bool NT, bool W>
+__global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
+{
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    if (s->flag != kRunning) return;
+    double acc[1] = {0.0};
+    if (a.x0_zero) residual64_body<M, V, true, G, NT, W>(a, s, rhs, blk, acc);
+    else residual64_body<M, V, false, G, NT, W>(a, s, rhs, blk, acc);
     double tot[1];
     if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
                        &s->ticket, a.red_mode, tot)) {
@@ -401,16 +571,13 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
 }
 
 // Refinement update: x64 += (1/scale) * u32, u32 being the inner solution
-// (x64 = u32 / scale when a.x0_zero: x is not read).
-template <int M, bool V, bool NT, bool W>
-__global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
+// (x64 = u32 / scale when ZERO: x is not read).
+template <int M, bool V, bool ZERO, bool NT, bool W>
+__device__ __forceinline__ void update64_body(const ColArgs& a, SolverState* s, int64_t rhs,
+                                              int64_t blk)
 {
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
-    SolverState* s = a.st + rhs;
-    if (s->flag != kRunning) return;
     double* x = static_cast<double*>(a.io0) + rhs * g.n;
     const float* u32 = static_cast<const float*>(a.out32) + rhs * g.n;
     const double inv_scale = 1.0 / s->aux;
@@ -421,17 +588,29 @@ __global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
         const Col c = make_col(g, W ? wave_col(tile, p) : tile_col(tile, p, L));
         double xc[M];
         float uc[M];
-        if (a.x0_zero) {
+        if constexpr (ZERO) {
 #pragma unroll
             for (int i = 0; i < M; ++i) xc[i] = 0.0;
         } else {
             ld<double, M, V, NT>(x, c.idx, c.ok, p.k0, g.nz, xc);
         }
-        ld<float, M, (V && (M % 4 == 0)), NT>(u32, c.idx, c.ok, p.k0, g.nz, uc);
+        ld<float, M, V, NT>(u32, c.idx, c.ok, p.k0, g.nz, uc);
 #pragma unroll
         for (int i = 0; i < M; ++i) xc[i] += inv_scale * double(uc[i]);
+        keep_here(xc);
         st<double, M, V, NT>(x, c.idx, c.ok, p.k0, g.nz, xc);
     }
+}
+
+template <int M, bool V, bool NT, bool W>
+__global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
+{
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    SolverState* s = a.st + rhs;
+    if (s->flag != kRunning) return;
+    if (a.x0_zero) update64_body<M, V, true, NT, W>(a, s, rhs, blk);
+    else update64_body<M, V, false, NT, W>(a, s, rhs, blk);
 }
 
 // Mode-1 reductions: one workgroup per right-hand side totals the published
@@ -469,7 +648,8 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(ColArgs a)
 
 bool has_finalize(Kind k)
 {
-    return k == Kind::FusedPrec || k == Kind::FusedApply || k == Kind::Fixup ||
+    return k == Kind::FusedPrec || k == Kind::FusedApply || k == Kind::FusedPrecFirst ||
+           k == Kind::FusedApplyFirst || k == Kind::Fixup ||
            k == Kind::TrueResidual || k == Kind::Residual64 || k == Kind::MgPostFinal ||
            k == Kind::MgSmoothFinal || k == Kind::RbRedFinal;
 }
@@ -478,10 +658,12 @@ const void* finalize_func(Kind kind)
 {
     switch (kind) {
     case Kind::FusedPrec:
+    case Kind::FusedPrecFirst:
     case Kind::MgPostFinal:
     case Kind::MgSmoothFinal:
     case Kind::RbRedFinal: return reinterpret_cast<const void*>(&k_finalize<Kind::FusedPrec>);
-    case Kind::FusedApply: return reinterpret_cast<const void*>(&k_finalize<Kind::FusedApply>);
+    case Kind::FusedApply:
+    case Kind::FusedApplyFirst: return reinterpret_cast<const void*>(&k_finalize<Kind::FusedApply>);
     case Kind::Fixup: return reinterpret_cast<const void*>(&k_finalize<Kind::Fixup>);
     case Kind::TrueResidual: return reinterpret_cast<const void*>(&k_finalize<Kind::TrueResidual>);
     case Kind::Residual64: return reinterpret_cast<const void*>(&k_finalize<Kind::Residual64>);
@@ -493,8 +675,13 @@ template <typename T, int M, bool V, bool G, bool NT, bool W>
 const void* main_func_m(Kind kind)
 {
     switch (kind) {
-    case Kind::Apply: return reinterpret_cast<const void*>(&k_apply<T, M, V, G, NT, W>);
-    case Kind::Precond: return reinterpret_cast<const void*>(&k_precond<T, M, V, G, NT, W>);
+    case Kind::Apply: return reinterpret_cast<const void*>(&k_apply<T, M, V, G, NT, W, kStepApply>);
+    case Kind::Precond:
+        return reinterpret_cast<const void*>(&k_precond<T, M, V, G, NT, W, kStepPrecond>);
+    case Kind::FusedPrecFirst:
+        return reinterpret_cast<const void*>(&k_fused_prec_first<T, M, V, G, NT, W, kStepFirstB>);
+    case Kind::FusedApplyFirst:
+        return reinterpret_cast<const void*>(&k_fused_apply_first<T, M, V, G, NT, W, kStepFirstA>);
     case Kind::InitFull: return reinterpret_cast<const void*>(&k_init<T, M, V, false, G, NT, W>);
     case Kind::InitZero: return reinterpret_cast<const void*>(&k_init<T, M, V, true, false, NT, W>);
     case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G, NT, W>);
@@ -566,7 +753,8 @@ const void* main_func(Kind kind, const ColArgs& a, int64_t batch)
 // Kernels dominated by the line solve run with their own launch shape.
 static bool line_solve_kind(Kind k)
 {
-    return k == Kind::FusedPrec || k == Kind::Precond || k == Kind::MgPre ||
+    return k == Kind::FusedPrec || k == Kind::FusedPrecFirst || k == Kind::Precond ||
+           k == Kind::MgPre ||
            k == Kind::MgPreFused || k == Kind::MgPost || k == Kind::MgPostFinal ||
            k == Kind::MgSmooth || k == Kind::MgSmoothFinal || k >= Kind::RbFirst;
 }
@@ -578,6 +766,13 @@ int column_launches(Kind kind, const ColArgs& a0, int64_t batch, KernelLaunch ou
     if (line_solve_kind(kind)) {
         a.L = a0.L_b;
         a.blocks_per_rhs = a0.bpr_b;
+    }
+    // kernels that take U tiles per wavefront step: at most one workgroup per
+    // U tiles (the partial sums follow the launch's own workgroup count)
+    if (const int U = step_of(kind); U > 1 && a.L > 0) {
+        const int64_t cols = (int64_t)(kWave / a.L) * (kBlock / kWave);
+        const int64_t tiles = (a.g.nh + cols - 1) / cols;
+        a.blocks_per_rhs = std::max<int64_t>(1, std::min(a.blocks_per_rhs, (tiles + U - 1) / U));
     }
     out[0].func = main_func<T>(kind, a, batch);
     if (!out[0].func) return 0;
@@ -592,11 +787,6 @@ int column_launches(Kind kind, const ColArgs& a0, int64_t batch, KernelLaunch ou
     return 2;
 }
 
-hipError_t issue(const KernelLaunch& k, hipStream_t s)
-{
-    void* args[] = {const_cast<ColArgs*>(&k.args)};
-    return hipLaunchKernel(k.func, k.grid, k.block, args, 0, s);
-}
 
 template <typename T>
 hipError_t launch_column_main(Kind kind, const ColArgs& a, int64_t batch, hipStream_t s)
@@ -626,14 +816,5 @@ hipError_t launch_column(Kind kind, const ColArgs& a, int64_t batch, hipStream_t
     }
     return hipSuccess;
 }
-
-template int column_launches<double>(Kind, const ColArgs&, int64_t, KernelLaunch*);
-template int column_launches<float>(Kind, const ColArgs&, int64_t, KernelLaunch*);
-template hipError_t launch_column<double>(Kind, const ColArgs&, int64_t, hipStream_t);
-template hipError_t launch_column<float>(Kind, const ColArgs&, int64_t, hipStream_t);
-template hipError_t launch_column_main<double>(Kind, const ColArgs&, int64_t, hipStream_t);
-template hipError_t launch_column_main<float>(Kind, const ColArgs&, int64_t, hipStream_t);
-template hipError_t launch_column_finalize<double>(Kind, const ColArgs&, int64_t, hipStream_t);
-template hipError_t launch_column_finalize<float>(Kind, const ColArgs&, int64_t, hipStream_t);
 
 }  // namespace pcg

@@ -402,13 +402,15 @@ pcg_status b_phase(const pcg_problem* P, int dtype, const ColArgs& a, int64_t nr
     return PCG_OK;
 }
 
-// One chunk of the fused iteration: K x (A, B) and the exit correction.
+// One chunk of the fused iteration: K x (A, B) and the exit correction.  In
+// the first chunk of a solve the first kernel A is its first-launch kernel.
 template <typename T>
-pcg_status issue_chunk(const ColArgs& a, const Phase& bph, int64_t nrhs, int K, hipStream_t s,
-                       int& count)
+pcg_status issue_chunk(const ColArgs& a, const Phase& bph, int64_t nrhs, int K, bool first,
+                       hipStream_t s, int& count)
 {
     for (int i = 0; i < K; ++i) {
-        if (launch<T>(Kind::FusedApply, a, nrhs, s, count) != PCG_OK) return PCG_E_DEVICE;
+        const Kind ka = (first && i == 0) ? Kind::FusedApplyFirst : Kind::FusedApply;
+        if (launch<T>(ka, a, nrhs, s, count) != PCG_OK) return PCG_E_DEVICE;
         if (issue_phase(bph, s, count) != PCG_OK) return PCG_E_DEVICE;
     }
     return launch<T>(Kind::Fixup, a, nrhs, s, count);
@@ -451,9 +453,11 @@ void key_launch(GraphKey& k, const KernelLaunch& l)
 // threads do with their streams.
 // profiled: event record nodes around every kernel A and kernel B's launches
 // up to its last main kernel, events P->gevents[4i .. 4i+3] for iteration i.
+// first: the chunk that starts a solve (its first kernel A is the
+// first-launch kernel).
 template <typename T>
 pcg_status chunk_graph(pcg_problem* P, const ColArgs& a, const Phase& bph,
-                       int64_t nrhs, int K, bool profiled, hipGraphExec_t* out)
+                       int64_t nrhs, int K, bool first, bool profiled, hipGraphExec_t* out)
 {
     if (profiled) {
         while (P->gevents.size() < 4 * (size_t)K) {
@@ -475,7 +479,7 @@ pcg_status chunk_graph(pcg_problem* P, const ColArgs& a, const Phase& bph,
     for (int i = 0; i < K; ++i) {
         const size_t a_main = seq.size();
         if (profiled) marks.emplace_back(a_main, P->gevents[4 * i]);
-        if (!add(Kind::FusedApply)) {
+        if (!add((first && i == 0) ? Kind::FusedApplyFirst : Kind::FusedApply)) {
             set_error("graph: no kernel for this shape (internal)");
             return PCG_E_DEVICE;
         }
@@ -590,10 +594,24 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_
 
     // profile: phase i (kernel A, or kernel B's launches up to its last main
     // kernel) is bracketed by events 2i and 2i+1
-    Phase aph;
-    if (!add_kind<T>(aph, Kind::FusedApply, a, nrhs)) {
+    Phase aph, aph_first, bph_first;
+    if (!add_kind<T>(aph, Kind::FusedApply, a, nrhs) ||
+        !add_kind<T>(aph_first, Kind::FusedApplyFirst, a, nrhs)) {
         set_error("no kernel for this shape (internal)");
         return PCG_E_DEVICE;
+    }
+    // kernel B's first launch: the first-launch kernel with the line
+    // preconditioner (the other preconditioners' first kernels handle their
+    // first launch themselves)
+    if (o.preconditioner == PCG_PRECOND_LINE) {
+        ColArgs af = a;
+        af.x0_zero = zero_start ? 1 : 0;   // r from b (every right-hand side starts alike)
+        if (!add_kind<T>(bph_first, Kind::FusedPrecFirst, af, nrhs)) {
+            set_error("no kernel for this shape (internal)");
+            return PCG_E_DEVICE;
+        }
+    } else {
+        bph_first = bph;
     }
     // timings in launch order: kernel A or B, and either an event pair of
     // P->events (direct launches, each its own pair, read at the end; -1
@@ -619,28 +637,29 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_
         return PCG_OK;
     };
     if (profile) {
-        if (timed(bph, 0) != PCG_OK) return PCG_E_DEVICE;
-    } else if (issue_phase(bph, s, info.launches) != PCG_OK) {
+        if (timed(bph_first, 0) != PCG_OK) return PCG_E_DEVICE;
+    } else if (issue_phase(bph_first, s, info.launches) != PCG_OK) {
         return PCG_E_DEVICE;
     }
 
     const int max_chunks = o.max_iter / K + 3;
     int chunks = 0;
     for (;;) {
+        const bool first = chunks == 0;
         if (profile && !use_graph) {
             for (int i = 0; i < K; ++i) {
-                if (timed(aph, 1) != PCG_OK) return PCG_E_DEVICE;
+                if (timed((first && i == 0) ? aph_first : aph, 1) != PCG_OK) return PCG_E_DEVICE;
                 if (timed(bph, 0) != PCG_OK) return PCG_E_DEVICE;
             }
             if (launch<T>(Kind::Fixup, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
         } else if (use_graph) {
             hipGraphExec_t exec;
-            if (chunk_graph<T>(P, a, bph, nrhs, K, profile, &exec) != PCG_OK)
+            if (chunk_graph<T>(P, a, bph, nrhs, K, first, profile, &exec) != PCG_OK)
                 return PCG_E_DEVICE;
             PCG_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
             info.launches += (1 + bph.mains) * K + 1;
         } else {
-            if (issue_chunk<T>(a, bph, nrhs, K, s, info.launches)) return PCG_E_DEVICE;
+            if (issue_chunk<T>(a, bph, nrhs, K, first, s, info.launches)) return PCG_E_DEVICE;
         }
         ++chunks;
         if (read_states(P, a.st, host_states, nrhs, s) != PCG_OK) return PCG_E_DEVICE;
