@@ -67,16 +67,19 @@ def fp64_solve_bytes(k, n):
 def mixed_solve_bytes(inner, steps, n):
     """Algorithmic bytes of a zero-start mixed-precision solve with `steps`
     refinement steps and `inner` FP32 inner iterations in all (the counts a
-    pcg_result reports).  An inner solve of k iterations moves 44k - 4
+    pcg_result reports).  An inner solve of k iterations moves 44k - 16
     bytes/unknown: kernel B 8 + 16k (its first launch reads b and writes z),
     kernel A 8 + 24 + 28(k - 2) (first: read z, write q; second: u not
-    read), the exit correction 12 (8 after one iteration).  The FP64 steps:
+    read); its exit correction is folded into the update.  (Exact when every
+    inner solve runs at least two iterations; one of a single iteration
+    moves 4 bytes/unknown more.)  The FP64 steps:
     steps + 1 residuals r32 = (b - A x) scale, 20 each (read x, b, write
-    r32; the first reads b only: 12), and `steps` updates x += u32 / scale,
-    20 each (read x, u32, write x; the first does not read x: 12)."""
+    r32; the first reads b only: 12), and `steps` updates
+    x += (u32 + alpha p32) / scale, 24 each (read x, u32, p32, write x; the
+    first does not read x: 16)."""
     if steps == 0:
         return n * (12 + 8)   # one residual, then x = 0 written
-    return n * (44 * inner - 4 * steps + (12 + 20 * steps) + (12 + 20 * (steps - 1)))
+    return n * (44 * inner - 16 * steps + (12 + 20 * steps) + (16 + 24 * (steps - 1)))
 
 
 def solve_roofline(bytes_per_solve, ms_per_solve):

@@ -121,7 +121,7 @@ enum class Kind : int {
     FusedApply,   // kernel A: x += alpha p; p = z + beta p; q = A z + beta q; sigma; alpha
     Fixup,        // x += alpha p once, after the exit test fired
     Residual64,   // FP64 r = b - A x, ||r||; FP32 copy r * scale  (refinement)
-    Update64,     // FP64 x += u32 / scale                         (refinement)
+    Update64,     // FP64 x += (u32 + alpha p32) / scale           (refinement)
     TrueResidual, // FP64 ||b - A x||
     FusedPrecFirst,  // kernel B's first launch in a solve (alpha = 0, q unset)
     FusedApplyFirst, // kernel A's first launch in a solve (p = z, q = A z)
@@ -180,6 +180,9 @@ struct ColArgs {
     // io2 (in place), so the two vectors swap roles.  On a zero start kernel
     // B's first launch does not copy b into r: its second reads b (in1)
     int zswap;
+    // mixed-precision update: the states of the inner solves whose pending
+    // exit correction (u += alpha p) it folds in; null elsewhere
+    const SolverState* st_in;
 };
 
 // Multigrid kernels (mg.hip): kernel for a Kind in MgPre..MgSmoothFinal, or

@@ -570,24 +570,35 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
     }
 }
 
-// Refinement update: x64 += (1/scale) * u32, u32 being the inner solution
-// (x64 = u32 / scale when ZERO: x is not read).
+// Refinement update: x64 += (u32 + alpha p32) / scale, u32 being the inner
+// solution without its pending exit correction alpha p (the inner solve runs
+// no exit-correction kernel: the update folds it in, saving a pass over the
+// FP32 vectors).  From the inner solve's state (zero start): u is valid
+// after two or more iterations (unwritten before); alpha p is added when it
+// stopped by the exit test or the iteration limit after at least one
+// iteration (a breakdown leaves u as it is, like the exit correction).
+// Both vectors are always read and the unused values selected away, so no
+// branch separates the loads.  ZERO: x = 0 is not read.
 template <int M, bool V, bool ZERO, bool NT, bool W>
-__device__ __forceinline__ void update64_body(const ColArgs& a, SolverState* s, int64_t rhs,
-                                              int64_t blk)
+__device__ __forceinline__ void update64_body(const ColArgs& a, const SolverState* s,
+                                              const SolverState* si, int64_t rhs, int64_t blk)
 {
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     double* x = static_cast<double*>(a.io0) + rhs * g.n;
     const float* u32 = static_cast<const float*>(a.out32) + rhs * g.n;
+    const float* p32 = static_cast<const float*>(a.in0) + rhs * g.n;
     const double inv_scale = 1.0 / s->aux;
+    const bool u_valid = si->iter >= 2;
+    const bool add_p = (si->flag == kConverged || si->flag == kMaxIter) && si->iter >= 1;
+    const float alpha = add_p ? float(si->alpha) : 0.0f;
     const Lane p = lane_pos<M>(L);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
         const Col c = make_col(g, W ? wave_col(tile, p) : tile_col(tile, p, L));
         double xc[M];
-        float uc[M];
+        float uc[M], pc[M];
         if constexpr (ZERO) {
 #pragma unroll
             for (int i = 0; i < M; ++i) xc[i] = 0.0;
@@ -595,8 +606,13 @@ __device__ __forceinline__ void update64_body(const ColArgs& a, SolverState* s, 
             ld<double, M, V, NT>(x, c.idx, c.ok, p.k0, g.nz, xc);
         }
         ld<float, M, V, NT>(u32, c.idx, c.ok, p.k0, g.nz, uc);
+        ld<float, M, V, NT>(p32, c.idx, c.ok, p.k0, g.nz, pc);
 #pragma unroll
-        for (int i = 0; i < M; ++i) xc[i] += inv_scale * double(uc[i]);
+        for (int i = 0; i < M; ++i) {
+            const float ui = u_valid ? uc[i] : 0.0f;
+            const float pi = add_p ? pc[i] : 0.0f;
+            xc[i] += inv_scale * double(ui + alpha * pi);
+        }
         keep_here(xc);
         st<double, M, V, NT>(x, c.idx, c.ok, p.k0, g.nz, xc);
     }
@@ -609,8 +625,9 @@ __global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
-    if (a.x0_zero) update64_body<M, V, true, NT, W>(a, s, rhs, blk);
-    else update64_body<M, V, false, NT, W>(a, s, rhs, blk);
+    const SolverState* si = a.st_in + rhs;
+    if (a.x0_zero) update64_body<M, V, true, NT, W>(a, s, si, rhs, blk);
+    else update64_body<M, V, false, NT, W>(a, s, si, rhs, blk);
 }
 
 // Mode-1 reductions: one workgroup per right-hand side totals the published

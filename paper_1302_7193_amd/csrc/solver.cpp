@@ -11,7 +11,9 @@
 //
 // Mixed precision: FP64 residual r = b - A x (scaled to FP32), an FP32 inner
 // solve of A d = r to a relative tolerance, FP64 update x += d / scale,
-// repeated until the FP64 residual meets the tolerance.
+// repeated until the FP64 residual meets the tolerance.  The inner solve's
+// exit correction d = u + alpha p is folded into the update (no separate
+// pass over the FP32 vectors).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -402,18 +404,19 @@ pcg_status b_phase(const pcg_problem* P, int dtype, const ColArgs& a, int64_t nr
     return PCG_OK;
 }
 
-// One chunk of the fused iteration: K x (A, B) and the exit correction.  In
-// the first chunk of a solve the first kernel A is its first-launch kernel.
+// One chunk of the fused iteration: K x (A, B) and the exit correction
+// (unless the caller folds it into its own next kernel).  In the first chunk
+// of a solve the first kernel A is its first-launch kernel.
 template <typename T>
 pcg_status issue_chunk(const ColArgs& a, const Phase& bph, int64_t nrhs, int K, bool first,
-                       hipStream_t s, int& count)
+                       bool fixup, hipStream_t s, int& count)
 {
     for (int i = 0; i < K; ++i) {
         const Kind ka = (first && i == 0) ? Kind::FusedApplyFirst : Kind::FusedApply;
         if (launch<T>(ka, a, nrhs, s, count) != PCG_OK) return PCG_E_DEVICE;
         if (issue_phase(bph, s, count) != PCG_OK) return PCG_E_DEVICE;
     }
-    return launch<T>(Kind::Fixup, a, nrhs, s, count);
+    return fixup ? launch<T>(Kind::Fixup, a, nrhs, s, count) : PCG_OK;
 }
 
 uint64_t bits(double v)
@@ -445,7 +448,7 @@ void key_launch(GraphKey& k, const KernelLaunch& l)
                        bits(a.io0), bits(a.io1), bits(a.io2), bits(a.io3), bits(a.io4),
                        bits(a.out32), bits(a.st), bits(a.part), uint64_t(uint32_t(a.red_mode)),
                        uint64_t(uint32_t(a.x0_zero)), bits(a.hgeo), bits(a.hgeo2), bits(a.omega),
-                       uint64_t(uint32_t(a.zswap))});
+                       uint64_t(uint32_t(a.zswap)), bits(a.st_in)});
 }
 
 // The chunk as an explicitly built HIP graph (kernel nodes in sequence).  No
@@ -457,7 +460,8 @@ void key_launch(GraphKey& k, const KernelLaunch& l)
 // first-launch kernel).
 template <typename T>
 pcg_status chunk_graph(pcg_problem* P, const ColArgs& a, const Phase& bph,
-                       int64_t nrhs, int K, bool first, bool profiled, hipGraphExec_t* out)
+                       int64_t nrhs, int K, bool first, bool fixup, bool profiled,
+                       hipGraphExec_t* out)
 {
     if (profiled) {
         while (P->gevents.size() < 4 * (size_t)K) {
@@ -489,7 +493,7 @@ pcg_status chunk_graph(pcg_problem* P, const ColArgs& a, const Phase& bph,
         seq.insert(seq.end(), bph.k.begin(), bph.k.end());
         if (profiled) marks.emplace_back(b0 + bph.last_main + 1, P->gevents[4 * i + 3]);
     }
-    if (!add(Kind::Fixup)) {
+    if (fixup && !add(Kind::Fixup)) {
         set_error("graph: no kernel for this shape (internal)");
         return PCG_E_DEVICE;
     }
@@ -571,10 +575,12 @@ struct RunInfo {
 // Fused Krylov engine for nrhs right-hand sides of precision T.  The states
 // at a.st must hold fresh_state() values with zero_start set as `zero_start`
 // (x0 = 0: x is not read and the first kernel B takes r from b = a.in1).
+// fixup = false: the exit correction u += alpha p is left to the caller
+// (the mixed-precision update folds it in).
 template <typename T>
 pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_in, int64_t nrhs,
                      bool zero_start, const pcg_solve_opts& o, char* ws, const Layout& w,
-                     SolverState* host_states, RunInfo& info, hipStream_t s)
+                     SolverState* host_states, RunInfo& info, hipStream_t s, bool fixup = true)
 {
     // line preconditioner: z and p trade vectors after the first kernel A,
     // which then need not store p = z (the other preconditioners' kernels
@@ -651,15 +657,15 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_
                 if (timed((first && i == 0) ? aph_first : aph, 1) != PCG_OK) return PCG_E_DEVICE;
                 if (timed(bph, 0) != PCG_OK) return PCG_E_DEVICE;
             }
-            if (launch<T>(Kind::Fixup, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
+            if (fixup && launch<T>(Kind::Fixup, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
         } else if (use_graph) {
             hipGraphExec_t exec;
-            if (chunk_graph<T>(P, a, bph, nrhs, K, first, profile, &exec) != PCG_OK)
+            if (chunk_graph<T>(P, a, bph, nrhs, K, first, fixup, profile, &exec) != PCG_OK)
                 return PCG_E_DEVICE;
             PCG_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
-            info.launches += (1 + bph.mains) * K + 1;
+            info.launches += (1 + bph.mains) * K + (fixup ? 1 : 0);
         } else {
-            if (issue_chunk<T>(a, bph, nrhs, K, first, s, info.launches)) return PCG_E_DEVICE;
+            if (issue_chunk<T>(a, bph, nrhs, K, first, fixup, s, info.launches)) return PCG_E_DEVICE;
         }
         ++chunks;
         if (read_states(P, a.st, host_states, nrhs, s) != PCG_OK) return PCG_E_DEVICE;
@@ -898,7 +904,9 @@ pcg_status solve_mixed(pcg_problem* P, const double* b, double* x, char* ws, con
     inner.st = st_in;
 
     ColArgs upd = outer;
-    upd.out32 = ws + w.u32;     // Update64 reads the inner solution
+    upd.out32 = ws + w.u32;     // Update64 reads the inner solution u and folds
+    upd.st_in = st_in;          // in its pending exit correction alpha p, p being
+    upd.in0 = o.preconditioner == PCG_PRECOND_LINE ? ws + w.z32 : ws + w.p32;   // where kernel A keeps it
 
     std::vector<SolverState> ho(nrhs), hi(nrhs);
     std::vector<double> r0(nrhs, 0.0), rn(nrhs, 0.0), scale(nrhs, 1.0);
@@ -973,10 +981,10 @@ pcg_status solve_mixed(pcg_problem* P, const double* b, double* x, char* ws, con
         pcg_solve_opts io = o;
         io.max_iter = 1 << 30;
         io.profile = 0;
-        pcg_status st =
-            run_fused<float>(P, PCG_F32, 1, inner, nrhs, true, io, ws, w, hi.data(), info, s);
+        pcg_status st = run_fused<float>(P, PCG_F32, 1, inner, nrhs, true, io, ws, w, hi.data(),
+                                         info, s, false);
         if (st != PCG_OK) return st;
-        // x += d / scale
+        // x += (u + alpha p) / scale
         for (int64_t i = 0; i < nrhs; ++i) {
             ho[i] = fresh_state(o.rtol, o.atol, 0, scale[i]);
             ho[i].flag = done[i] ? kConverged : kRunning;

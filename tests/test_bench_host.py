@@ -83,19 +83,19 @@ def test_whole_solve_bytes_by_enumeration():
     (bytes per unknown of each vector each launch reads or writes)."""
     n = 1000
 
-    def inner(k, e):   # one zero-start inner solve of k iterations, e bytes per value
+    def inner(k, e, fixup=True):   # a zero-start solve of k iterations, e bytes per value
         b = [2 * e] + [4 * e] * k                       # kernel B: b -> z, then r, q -> r, z
         a = [2 * e] + ([6 * e] if k >= 2 else []) + [7 * e] * max(k - 2, 0)
         fix = 3 * e if k >= 2 else 2 * e                # u += alpha p (u unset after one)
-        return sum(b) + sum(a) + fix
+        return sum(b) + sum(a) + (fix if fixup else 0)
 
     for k in (1, 2, 5, 9):
         assert bench.fp64_solve_bytes(k, n) == n * inner(k, 8)
-    for ks in ((11,), (7, 4), (9, 1, 3)):
+    for ks in ((11,), (7, 4), (9, 2, 3)):
         s = len(ks)
         residuals = (8 + 4) + (8 + 8 + 4) * s           # b [, x] in, r32 out; s + 1 of them
-        updates = (4 + 8) + (8 + 4 + 8) * (s - 1)       # u32 [, x] in, x out
-        want = sum(inner(k, 4) for k in ks) + residuals + updates
+        updates = (4 + 4 + 8) + (8 + 4 + 4 + 8) * (s - 1)   # u32, p32 [, x] in, x out
+        want = sum(inner(k, 4, fixup=False) for k in ks) + residuals + updates
         assert bench.mixed_solve_bytes(sum(ks), s, n) == n * want, ks
 
 
