@@ -193,6 +193,24 @@ def cuda_time(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def cold_time(torch, fn, n, dtype, reps, k=3):
+    """Mean ms per call of fn(x, y) cycling over k input/output vector pairs
+    of n values, so that each call reads vectors the previous calls did not
+    touch (k pairs of the main workload's size exceed the 256 MB Infinity
+    Cache)."""
+    xs = [torch.rand(n, dtype=dtype, device="cuda") for _ in range(k)]
+    ys = [torch.empty_like(xs[0]) for _ in range(k)]
+    for i in range(k):
+        fn(xs[i], ys[i])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        fn(xs[i % k], ys[i % k])
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def hbm_probe(pcg, torch, n=1 << 25, reps=10):
     """The library's streaming kernel (pcg_stream_probe) with the access mixes
     of kernel A (4 vectors in / 3 out), kernel B (2 / 2) and a copy (1 / 1),
@@ -284,18 +302,21 @@ def extras(pcg, si, torch, main):
     log("unfused: %.3f ms/solve" % ms)
 
     # operator alone: matrix-free vs assembled CSR; line preconditioner alone
-    y = torch.empty_like(b)
-    t_mf = cuda_time(torch, lambda: pcg.pcg_apply(P, pcg.PCG_F64, b, y), 50)
-    t_pc = cuda_time(torch, lambda: pcg.pcg_precond(P, pcg.PCG_F64, b, y), 50)
+    # (inputs cycled so that no call finds its vector in the caches)
+    f64 = torch.float64
+    t_mf = cold_time(torch, lambda xv, yv: pcg.pcg_apply(P, pcg.PCG_F64, xv, yv), n, f64, 60)
+    t_pc = cold_time(torch, lambda xv, yv: pcg.pcg_precond(P, pcg.PCG_F64, xv, yv), n, f64, 60)
     csr = torch.empty(pcg.pcg_csr_bytes(P, pcg.PCG_F64), dtype=torch.uint8, device="cuda")
     pcg.pcg_csr_build(P, pcg.PCG_F64, csr)
-    t_csr = cuda_time(torch, lambda: pcg.pcg_csr_apply(P, pcg.PCG_F64, csr, b, y), 20)
+    t_csr = cold_time(torch, lambda xv, yv: pcg.pcg_csr_apply(P, pcg.PCG_F64, csr, xv, yv), n,
+                      f64, 30)
     nnz_bytes = csr.numel() - 4 * (n + 1)           # values + column indices (+ padding)
     csr_bytes = nnz_bytes + 4 * (n + 1) + 16 * n    # + row offsets + x + y
     out["operator_fp64"] = dict(
         matrix_free_us=t_mf * 1e3, matrix_free_GBps=BYTES["apply"] * n / (t_mf * 1e-3) / 1e9,
         csr_us=t_csr * 1e3, csr_GBps=csr_bytes / (t_csr * 1e-3) / 1e9,
         csr_bytes_per_unknown=csr_bytes / n, csr_over_matrix_free_time=t_csr / t_mf,
+        csr_over_matrix_free_bytes=csr_bytes / (BYTES["apply"] * n),
         line_precond_us=t_pc * 1e3, line_precond_GBps=BYTES["precond"] * n / (t_pc * 1e-3) / 1e9)
     del csr
     log("operator: MF %.1f us, CSR %.1f us, precond %.1f us" % (t_mf * 1e3, t_csr * 1e3, t_pc * 1e3))
@@ -432,9 +453,9 @@ def stretched(pcg, si, torch, uniform):
     o = pcg.pcg_default_opts(x0_zero=1, graph_chunk=-1, true_residual=1)
     ws = pcg.workspace(P, o)
     ms, its, st, r = timed_solves(pcg, torch, P, b, x, ws, o, 10)
-    y = torch.empty_like(b)
-    t_mf = cuda_time(torch, lambda: pcg.pcg_apply(P, pcg.PCG_F64, b, y), 30)
-    t_pc = cuda_time(torch, lambda: pcg.pcg_precond(P, pcg.PCG_F64, b, y), 30)
+    f64 = torch.float64
+    t_mf = cold_time(torch, lambda xv, yv: pcg.pcg_apply(P, pcg.PCG_F64, xv, yv), n, f64, 30)
+    t_pc = cold_time(torch, lambda xv, yv: pcg.pcg_precond(P, pcg.PCG_F64, xv, yv), n, f64, 30)
     out = dict(ms_per_solve=ms, iterations=its, status=pcg.STATUS_NAMES[st],
                rel_res_true=r["rel_res_true"], unknowns_iter_per_s=n * its / (ms * 1e-3),
                algorithmic_GBps=BYTES["iteration"] * n * its / (ms * 1e-3) / 1e9,
@@ -948,14 +969,21 @@ def main():
         P = pcg.Problem(d)
         out = {}
         for dt, td in ((pcg.PCG_F64, torch.float64), (pcg.PCG_F32, torch.float32)):
-            xv = si.uniform_pm1_torch(21, P.n).to(td)
-            yv = torch.empty_like(xv)
-            ms_a = cuda_time(torch, lambda: pcg.pcg_apply(P, dt, xv, yv), args.steps)
-            ms_p = cuda_time(torch, lambda: pcg.pcg_precond(P, dt, xv, yv), args.steps)
-            e = xv.element_size()
+            ms_a = cold_time(torch, lambda xv, yv: pcg.pcg_apply(P, dt, xv, yv), P.n, td, args.steps)
+            ms_p = cold_time(torch, lambda xv, yv: pcg.pcg_precond(P, dt, xv, yv), P.n, td,
+                             args.steps)
+            csr = torch.empty(pcg.pcg_csr_bytes(P, dt), dtype=torch.uint8, device="cuda")
+            pcg.pcg_csr_build(P, dt, csr)
+            ms_c = cold_time(torch, lambda xv, yv: pcg.pcg_csr_apply(P, dt, csr, xv, yv), P.n, td,
+                             args.steps)
+            e = torch.empty(0, dtype=td).element_size()
+            csr_bytes = csr.numel() + 2 * e * P.n
+            del csr
             out["fp64" if dt == pcg.PCG_F64 else "fp32"] = dict(
                 apply_us=ms_a * 1e3, apply_GBps=2 * e * P.n / (ms_a * 1e-3) / 1e9,
-                precond_us=ms_p * 1e3, precond_GBps=2 * e * P.n / (ms_p * 1e-3) / 1e9)
+                precond_us=ms_p * 1e3, precond_GBps=2 * e * P.n / (ms_p * 1e-3) / 1e9,
+                csr_us=ms_c * 1e3, csr_GBps=csr_bytes / (ms_c * 1e-3) / 1e9,
+                csr_over_matrix_free=ms_c / ms_a)
         print(json.dumps(out))
         return
 

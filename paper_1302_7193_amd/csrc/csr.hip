@@ -7,6 +7,8 @@
 // and neighbours across Dirichlet faces are absent.  Row offsets follow in
 // closed form from the number of neighbours of each cell, so the assembly
 // needs no scan.
+#include <algorithm>
+
 #include "csr_layout.h"
 #include "device_common.h"
 
@@ -73,18 +75,70 @@ __global__ __launch_bounds__(kBlock) void k_csr_build(Geom g, const double* __re
     if (ip >= 0) put(ip * g.nz + k, d * wxp);
 }
 
+// y = A x from the CSR arrays.  Eight lanes share a row (a row has at most
+// seven entries): lane s of the group takes entry rowp[r] + s, so a
+// wavefront's loads of values and column indices cover the consecutive
+// entries of its eight rows in one coalesced sweep; the group adds its
+// products with two quad permutes and one swizzle across the group's halves.
+// Each wavefront takes kCsrGroups such row groups at a time, their loads
+// issued together (three dependent loads per row: offsets, entries, x).
+constexpr int kCsrLanes = 8;
+constexpr int kCsrGroups = 4;
+
+template <typename T>
+__device__ __forceinline__ T group8_sum(T v)
+{
+    v += dpp_move<kQuadXor1>(v, T(0));
+    v += dpp_move<kQuadXor2>(v, T(0));
+    // xor 4: swizzle in bit mode (and 0x1f, or 0, xor 4) within each 32 lanes
+    constexpr int kXor4 = 0x1f | (4 << 10);
+    if constexpr (sizeof(T) == 8) {
+        const int64_t b = __builtin_bit_cast(int64_t, v);
+        const int lo = __builtin_amdgcn_ds_swizzle((int)b, kXor4);
+        const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), kXor4);
+        return v + __builtin_bit_cast(T, ((int64_t)hi << 32) | (int64_t)(uint32_t)lo);
+    } else {
+        return v + __builtin_bit_cast(T, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), kXor4));
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_csr_apply(int64_t n, const T* __restrict__ val,
                                                       const int32_t* __restrict__ col,
                                                       const int32_t* __restrict__ rowp,
                                                       const T* __restrict__ x, T* __restrict__ y)
 {
-    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r >= n) return;
-    const int32_t e0 = rowp[r], e1 = rowp[r + 1];
-    T acc = T(0);
-    for (int32_t e = e0; e < e1; ++e) acc += val[e] * x[col[e]];
-    y[r] = acc;
+    constexpr int kRowsPerWave = (kWave / kCsrLanes) * kCsrGroups;
+    const int lane = threadIdx.x & (kWave - 1), slot = lane & (kCsrLanes - 1);
+    const int64_t wave = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t r0 = wave * kRowsPerWave; r0 < n; r0 += nwaves * kRowsPerWave) {
+        int64_t r[kCsrGroups];
+        int32_t e[kCsrGroups], e1[kCsrGroups];
+        T v[kCsrGroups], xv[kCsrGroups];
+        int32_t c[kCsrGroups];
+#pragma unroll
+        for (int u = 0; u < kCsrGroups; ++u) {
+            r[u] = r0 + u * (kWave / kCsrLanes) + lane / kCsrLanes;
+            const int64_t rr = r[u] < n ? r[u] : n - 1;
+            e[u] = rowp[rr] + slot;
+            e1[u] = r[u] < n ? rowp[rr + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kCsrGroups; ++u) {
+            const bool in = e[u] < e1[u];
+            const int32_t ee = in ? e[u] : 0;
+            v[u] = in ? val[ee] : T(0);
+            c[u] = in ? col[ee] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kCsrGroups; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < kCsrGroups; ++u) {
+            const T sum = group8_sum(v[u] * xv[u]);
+            if (slot == 0 && r[u] < n) y[r[u]] = sum;
+        }
+    }
 }
 
 template <typename T>
@@ -127,7 +181,9 @@ hipError_t csr_build(const Geom& g, const double* vert64, const double* hgeo, in
 hipError_t csr_apply(const Geom& g, int dtype, const void* buf, const void* x, void* y,
                      hipStream_t s)
 {
-    const dim3 grid((unsigned)((g.n + kBlock - 1) / kBlock)), block(kBlock);
+    const int64_t rows_per_block = (int64_t)(kBlock / kCsrLanes) * kCsrGroups;
+    const int64_t blocks = std::min<int64_t>((g.n + rows_per_block - 1) / rows_per_block, 1 << 20);
+    const dim3 grid((unsigned)blocks), block(kBlock);
     void* b = const_cast<void*>(buf);
     if (dtype == PCG_F64) {
         double* v; int32_t *c, *r;

@@ -35,13 +35,52 @@ int step_of(Kind k)
 
 // Column c of wavefront step `tile` (U tiles per step): the column index of
 // tile + u, or one past the grid (make_col then marks it absent) beyond t1.
-template <bool W>
+// JS (one column per wavefront): the wavefront takes U consecutive columns
+// of the step's 4U instead, so with n_y a multiple of U they lie in one row
+// of the grid and share their inner y-neighbours (load_group).
+template <bool W, int U, bool JS>
 __device__ __forceinline__ int64_t step_col(const Geom& g, int64_t tile, int u, int64_t t1,
                                             const Lane& p, int L)
 {
+    if constexpr (JS) {
+        const int c = __builtin_amdgcn_readfirstlane(
+            (int)(tile * (kBlock / kWave) + p.wave * U + u));
+        return c < t1 * (kBlock / kWave) ? int64_t(c) : g.nh;
+    }
     const int64_t tu = tile + u;
     if (tu >= t1) return g.nh;
     return W ? wave_col(tu, p) : tile_col(tu, p, L);
+}
+
+// The stencil inputs of a wavefront step's U columns.  JS: the columns are
+// consecutive in one row (see step_col), so column u's y-neighbours are
+// columns u - 1 and u + 1 of the group, already loaded, and only the
+// group's outer two are read; the loads are all issued before any use.
+template <typename T, int M, bool V, int U, bool JS>
+__device__ __forceinline__ void load_group(const Geom& g, const Col (&c)[U], int k0,
+                                           const T* __restrict__ x, StencilIn<T, M> (&in)[U])
+{
+    if constexpr (!JS) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) load_stencil<T, M, V>(g, c[u], k0, x, in[u]);
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ld<T, M, V>(x, c[u].idx, c[u].ok, k0, g.nz, in[u].xc);
+            ld<T, M, V>(x, c[u].im, c[u].ok && c[u].im >= 0, k0, g.nz, in[u].nb[0]);
+            ld<T, M, V>(x, c[u].ip, c[u].ok && c[u].ip >= 0, k0, g.nz, in[u].nb[1]);
+        }
+        ld<T, M, V>(x, c[0].jm, c[0].ok && c[0].jm >= 0, k0, g.nz, in[0].nb[2]);
+        ld<T, M, V>(x, c[U - 1].jp, c[U - 1].ok && c[U - 1].jp >= 0, k0, g.nz, in[U - 1].nb[3]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                if (u > 0) in[u].nb[2][t] = in[u - 1].xc[t];
+                if (u < U - 1) in[u].nb[3][t] = in[u + 1].xc[t];
+            }
+        }
+    }
 }
 
 // W: one column per wavefront (L = 64, column index scalar); NT: the
@@ -50,7 +89,7 @@ __device__ __forceinline__ int64_t step_col(const Geom& g, int64_t tile, int u, 
 // wavefront takes U tiles at a time and issues the loads of all of them
 // before computing any: a kernel with one input stream otherwise keeps too
 // few bytes in flight to cover the memory latency.
-template <typename T, int M, bool V, bool G, bool NT, bool W, int U>
+template <typename T, int M, bool V, bool G, bool NT, bool W, int U, bool JS>
 __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
 {
     const Geom& g = a.g;
@@ -70,9 +109,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
         StencilIn<T, M> in[U];
         T yc[U][M];
 #pragma unroll
-        for (int u = 0; u < U; ++u) c[u] = make_col<G>(g, step_col<W>(g, tile, u, t1, p, L), a.hgeo);
-#pragma unroll
-        for (int u = 0; u < U; ++u) load_stencil<T, M, V>(g, c[u], p.k0, x, in[u]);
+        for (int u = 0; u < U; ++u)
+            c[u] = make_col<G>(g, step_col<W, U, JS>(g, tile, u, t1, p, L), a.hgeo);
+        load_group<T, M, V, U, JS>(g, c, p.k0, x, in);
 #pragma unroll
         for (int u = 0; u < U; ++u) stencil_in<T, M, G>(g, c[u], p.l, L, in[u], vc, yc[u]);
 #pragma unroll
@@ -99,7 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
         Col c[U];
         T rc[U][M], zc[U][M];
 #pragma unroll
-        for (int u = 0; u < U; ++u) c[u] = make_col<G>(g, step_col<W>(g, tile, u, t1, p, L), a.hgeo);
+        for (int u = 0; u < U; ++u)
+            c[u] = make_col<G>(g, step_col<W, U, false>(g, tile, u, t1, p, L), a.hgeo);
 #pragma unroll
         for (int u = 0; u < U; ++u) ld<T, M, V, NT>(r, c[u].idx, c[u].ok, p.k0, g.nz, rc[u]);
 #pragma unroll
@@ -335,7 +375,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec_first(ColArgs a)
         Col c[U];
         T rc[U][M], zc[U][M];
 #pragma unroll
-        for (int u = 0; u < U; ++u) c[u] = make_col<G>(g, step_col<W>(g, tile, u, t1, p, L), a.hgeo);
+        for (int u = 0; u < U; ++u)
+            c[u] = make_col<G>(g, step_col<W, U, false>(g, tile, u, t1, p, L), a.hgeo);
 #pragma unroll
         for (int u = 0; u < U; ++u) ld<T, M, V, NT>(src, c[u].idx, c[u].ok, p.k0, g.nz, rc[u]);
         if (flag != kRunning) return;   // the same in every thread of the workgroup
@@ -368,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec_first(ColArgs a)
 // k_fused_prec_first.  z stays in io2 and serves as p when ColArgs::zswap
 // is set; otherwise p = z is stored.  u keeps x0 (a zero start leaves it
 // unwritten until the next launch sets u = alpha p).
-template <typename T, int M, bool V, bool G, bool NT, bool W, int U>
+template <typename T, int M, bool V, bool G, bool NT, bool W, int U, bool JS>
 __global__ __launch_bounds__(kBlock) void k_fused_apply_first(ColArgs a)
 {
     const Geom& g = a.g;
@@ -392,9 +433,9 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply_first(ColArgs a)
         StencilIn<T, M> in[U];
         T az[U][M];
 #pragma unroll
-        for (int u = 0; u < U; ++u) c[u] = make_col<G>(g, step_col<W>(g, tile, u, t1, p, L), a.hgeo);
-#pragma unroll
-        for (int u = 0; u < U; ++u) load_stencil<T, M, V>(g, c[u], p.k0, z, in[u]);
+        for (int u = 0; u < U; ++u)
+            c[u] = make_col<G>(g, step_col<W, U, JS>(g, tile, u, t1, p, L), a.hgeo);
+        load_group<T, M, V, U, JS>(g, c, p.k0, z, in);
 #pragma unroll
         for (int u = 0; u < U; ++u) stencil_in<T, M, G>(g, c[u], p.l, L, in[u], vc, az[u]);
         if (flag != kRunning) return;   // the same in every thread of the workgroup
@@ -689,16 +730,23 @@ const void* finalize_func(Kind kind)
 }
 
 template <typename T, int M, bool V, bool G, bool NT, bool W>
-const void* main_func_m(Kind kind)
+const void* main_func_m(Kind kind, bool js)
 {
+    // columns sharing y-neighbours: one column per wavefront and n_y a
+    // multiple of the step (the caller's js)
+    constexpr bool kJs = W;
     switch (kind) {
-    case Kind::Apply: return reinterpret_cast<const void*>(&k_apply<T, M, V, G, NT, W, kStepApply>);
+    case Kind::Apply:
+        if (kJs && js) return reinterpret_cast<const void*>(&k_apply<T, M, V, G, NT, W, kStepApply, kJs>);
+        return reinterpret_cast<const void*>(&k_apply<T, M, V, G, NT, W, kStepApply, false>);
     case Kind::Precond:
         return reinterpret_cast<const void*>(&k_precond<T, M, V, G, NT, W, kStepPrecond>);
     case Kind::FusedPrecFirst:
         return reinterpret_cast<const void*>(&k_fused_prec_first<T, M, V, G, NT, W, kStepFirstB>);
     case Kind::FusedApplyFirst:
-        return reinterpret_cast<const void*>(&k_fused_apply_first<T, M, V, G, NT, W, kStepFirstA>);
+        if (kJs && js)
+            return reinterpret_cast<const void*>(&k_fused_apply_first<T, M, V, G, NT, W, kStepFirstA, kJs>);
+        return reinterpret_cast<const void*>(&k_fused_apply_first<T, M, V, G, NT, W, kStepFirstA, false>);
     case Kind::InitFull: return reinterpret_cast<const void*>(&k_init<T, M, V, false, G, NT, W>);
     case Kind::InitZero: return reinterpret_cast<const void*>(&k_init<T, M, V, true, false, NT, W>);
     case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G, NT, W>);
@@ -721,16 +769,16 @@ const void* main_func_m(Kind kind)
 }
 
 template <typename T, int M, bool V, bool G>
-const void* main_func_n(Kind kind, bool nt, bool w)
+const void* main_func_n(Kind kind, bool nt, bool w, bool js)
 {
     // the nontemporal variants exist only where the hint is used: one
     // 16-byte chunk per lane and vector; one column per wavefront: L = 64
     if constexpr (M * sizeof(T) == 16) {
-        if (w) return nt ? main_func_m<T, M, V, G, true, true>(kind) : main_func_m<T, M, V, G, false, true>(kind);
-        return nt ? main_func_m<T, M, V, G, true, false>(kind) : main_func_m<T, M, V, G, false, false>(kind);
+        if (w) return nt ? main_func_m<T, M, V, G, true, true>(kind, js) : main_func_m<T, M, V, G, false, true>(kind, js);
+        return nt ? main_func_m<T, M, V, G, true, false>(kind, js) : main_func_m<T, M, V, G, false, false>(kind, js);
     } else {
-        if (w) return main_func_m<T, M, V, G, false, true>(kind);
-        return main_func_m<T, M, V, G, false, false>(kind);
+        if (w) return main_func_m<T, M, V, G, false, true>(kind, js);
+        return main_func_m<T, M, V, G, false, false>(kind, js);
     }
 }
 
@@ -741,9 +789,10 @@ const void* main_func_v(Kind kind, const ColArgs& a, bool nt)
     const bool vec = (a.g.nz % M == 0) && ((M * sizeof(T)) % 16 == 0) &&
                      ((a.g.nz * sizeof(T)) % 16 == 0);
     const bool w = a.L == kWave;
+    const bool js = w && a.g.ny % step_of(kind) == 0;
     if (a.hgeo)
-        return vec ? main_func_n<T, M, true, true>(kind, nt, w) : main_func_n<T, M, false, true>(kind, nt, w);
-    return vec ? main_func_n<T, M, true, false>(kind, nt, w) : main_func_n<T, M, false, false>(kind, nt, w);
+        return vec ? main_func_n<T, M, true, true>(kind, nt, w, js) : main_func_n<T, M, false, true>(kind, nt, w, js);
+    return vec ? main_func_n<T, M, true, false>(kind, nt, w, js) : main_func_n<T, M, false, false>(kind, nt, w, js);
 }
 
 template <typename T>
