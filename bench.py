@@ -366,6 +366,7 @@ def extras(pcg, si, torch, main):
     out["serving_512_requests"] = serving(pcg, si, torch)
     out["serving_512_requests_auto_preconditioner"] = serving(
         pcg, si, torch, preconditioner=pcg.PCG_PRECOND_AUTO)
+    out["serving_512_requests_batched"] = serving(pcg, si, torch, max_active=16, batched=True)
 
     # error of the 1024 x 1024 x 128 solutions against the oracle's FP64 solve
     log("waiting for the oracle's 1024x1024x128 FP64 solve")
@@ -555,12 +556,14 @@ def batched(pcg, si, torch, nrhs=64):
     return out
 
 
-def serving(pcg, si, torch, n_requests=512, max_active=4, preconditioner=0):
+def serving(pcg, si, torch, n_requests=512, max_active=4, preconditioner=0, batched=False):
     """Poisson arrivals (mean 200/s, seed 5) of mixed-precision solves with
     n x n x n_z grids, n in {64,128,256,512}, n_z in {32,64,128}, anisotropy
     log-uniform in [1e2,1e5], U[-1,1) right-hand sides (seed 1000 + id),
     device-resident; admitted by a 200 GB HBM budget.  The trace is replayed
-    once to warm the per-shape state, then timed."""
+    once to warm the per-shape state, then timed.  batched: one scheduler
+    advances up to max_active requests with shared multi-request launches
+    (line preconditioner) instead of one worker per request."""
     import numpy as np
     trace = si.serving_trace(n_requests, 200.0, seed=5)
     opts = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED, preconditioner=preconditioner)
@@ -572,7 +575,7 @@ def serving(pcg, si, torch, n_requests=512, max_active=4, preconditioner=0):
         xs.append(torch.empty_like(bs[-1]))
     need = max(pcg.pcg_request_bytes(d, opts) for d in descs)
     arena = torch.empty(max_active * need + (64 << 20), dtype=torch.uint8, device="cuda")
-    srv = pcg.Server(arena, 200 * 10**9, max_active)
+    srv = pcg.Server(arena, 200 * 10**9, max_active, batched=batched)
     torch.cuda.synchronize()
 
     def replay():
@@ -612,6 +615,9 @@ def serving(pcg, si, torch, n_requests=512, max_active=4, preconditioner=0):
                 trace_span_s=trace[-1]["arrival"], makespan_s=span,
                 mean_unknowns=float(nunk.mean()), max_active=max_active,
                 peak_bytes_in_use=q["peak_bytes_in_use"], budget_bytes=200 * 10**9,
+                peak_active=q["peak_active"],
+                mode="batched (shared multi-request launches)" if batched else
+                "one worker and stream per admitted request",
                 input="device-resident right-hand sides (pcg_submit_device)")
 
 
@@ -916,6 +922,8 @@ def main():
     ap.add_argument("--ops-only", action="store_true",
                     help="only the operator and the line preconditioner alone on 512x512x128 "
                          "(FP64 and FP32), --steps launches each (for profiler runs)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving replays (per-request workers and batched mode)")
     ap.add_argument("--main-only", action="store_true",
                     help="only the timed loop (for profiler runs): no extras, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -989,6 +997,11 @@ def main():
 
     if args.mixed_only or args.batched_only:
         print(json.dumps(profile_run(pcg, si, torch, args.steps, args.mixed_only)))
+        return
+
+    if args.serving_only:
+        print(json.dumps(dict(workers=serving(pcg, si, torch),
+                              batched=serving(pcg, si, torch, max_active=16, batched=True))))
         return
 
     if args.mg_only or args.rbgs_only:

@@ -341,7 +341,9 @@ pcg_status pcg_csr_apply(pcg_problem *p, int32_t dtype, const void *buf, const v
 typedef struct {
     size_t hbm_budget_bytes; /* admitted requests' bytes stay within this (and the arena) */
     int32_t max_active;      /* requests solved concurrently, 1..64                  */
-    int32_t reserved;
+    int32_t batched;         /* 0: one worker thread and stream per active request;
+                                1: one scheduler whose every launch advances all
+                                   active requests (see below)                   */
 } pcg_server_opts;
 
 typedef struct {
@@ -351,6 +353,21 @@ typedef struct {
     int32_t peak_active;     /* most requests running on the device at once */
     int32_t reserved;
 } pcg_server_stats;
+
+/* Batched mode (batched = 1): continuous batching with shared launches.  One
+ * scheduler thread runs ticks; in each, the requests at that stage get their
+ * FP64 refinement residual, then a few iterations of the two fused kernels,
+ * then the refinement update (or the FP64 exit correction), each step one
+ * launch over all of them in which every request keeps its own grid,
+ * tables, vectors, solver state and partial sums.  Requests that arrive
+ * while others run join at the next tick (admitted by budget and arena as
+ * above, up to max_active at once); finished ones leave.  Requests take a
+ * served launch shape (4 levels per lane in FP32, 2 in FP64), so a result
+ * equals that request served alone, in any mix, but may differ from
+ * pcg_solve's within rounding.  It covers the line preconditioner (AUTO
+ * resolving to it) on grids with n_z = 4, 8, 16, 32, 64 or 128; other
+ * requests are rejected (PCG_E_INVALID).  FP64 requests report
+ * rel_res_true = -1. */
 
 /* Device bytes one request needs: b, x and its workspace (0 if invalid). */
 size_t pcg_request_bytes(const pcg_problem_desc *desc, const pcg_solve_opts *opts);

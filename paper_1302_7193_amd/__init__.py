@@ -65,7 +65,7 @@ class pcg_tuning(ctypes.Structure):
 
 class pcg_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("batched", ctypes.c_int32)]
 
 
 class pcg_server_stats(ctypes.Structure):
@@ -449,9 +449,11 @@ class Server:
     """Owning handle of a pcg_server.  Keeps every submitted request's host
     arrays alive until the request is collected."""
 
-    def __init__(self, arena: torch.Tensor, hbm_budget_bytes: int, max_active: int = 4):
+    def __init__(self, arena: torch.Tensor, hbm_budget_bytes: int, max_active: int = 4,
+                 batched: bool = False):
         self.arena = arena
-        o = pcg_server_opts(hbm_budget_bytes=hbm_budget_bytes, max_active=max_active)
+        o = pcg_server_opts(hbm_budget_bytes=hbm_budget_bytes, max_active=max_active,
+                            batched=int(bool(batched)))
         h = _P()
         nbytes = arena.numel() * arena.element_size()
         _check(_lib.pcg_server_create(ctypes.byref(o), _buf(arena, nbytes, "arena"), nbytes,
@@ -469,8 +471,9 @@ class Server:
         self.close()
 
 
-def pcg_server_create(arena: torch.Tensor, hbm_budget_bytes: int, max_active: int = 4) -> Server:
-    return Server(arena, hbm_budget_bytes, max_active)
+def pcg_server_create(arena: torch.Tensor, hbm_budget_bytes: int, max_active: int = 4,
+                      batched: bool = False) -> Server:
+    return Server(arena, hbm_budget_bytes, max_active, batched)
 
 
 def pcg_server_destroy(s: Server) -> None:

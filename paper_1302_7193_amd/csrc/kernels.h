@@ -20,7 +20,7 @@ namespace {
 // kernels A and B): their loads are issued together before any arithmetic.
 constexpr int kStepApply = 4, kStepPrecond = 2, kStepFirstA = 4, kStepFirstB = 2;
 
-int step_of(Kind k)
+inline int step_of(Kind k)
 {
     switch (k) {
     case Kind::Apply: return kStepApply;
@@ -246,9 +246,8 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
 }
 
 template <typename T, int M, bool V, bool G, bool NT, bool W>
-__global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
+__device__ __forceinline__ void fused_prec_dev(const ColArgs& a, int64_t t)
 {
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
@@ -260,6 +259,12 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
                    &s->ticket, a.red_mode, tot)) {
         if (threadIdx.x == 0) finish_prec(s, tot[0], tot[1]);
     }
+}
+
+template <typename T, int M, bool V, bool G, bool NT, bool W>
+__global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
+{
+    fused_prec_dev<T, M, V, G, NT, W>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Kernel A (Alg. InterleavedApply): u += alpha p; p = z + beta p;
@@ -326,9 +331,8 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
 }
 
 template <typename T, int M, bool V, bool G, bool NT, bool W>
-__global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
+__device__ __forceinline__ void fused_apply_dev(const ColArgs& a, int64_t t)
 {
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
@@ -340,6 +344,12 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
                    &s->ticket, a.red_mode, tot)) {
         if (threadIdx.x == 0) finish_apply(s, tot[0]);
     }
+}
+
+template <typename T, int M, bool V, bool G, bool NT, bool W>
+__global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
+{
+    fused_apply_dev<T, M, V, G, NT, W>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // First launch of kernel B in a solve (iteration 0: alpha = 0, q unset),
@@ -459,11 +469,10 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply_first(ColArgs a)
 // behind r).  Runs once: the last workgroup (or the finalize launch) marks
 // it done.
 template <typename T, int M, bool V, bool NT, bool W>
-__global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
+__device__ __forceinline__ void fixup_dev(const ColArgs& a, int64_t t)
 {
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
     // stopped before the first iteration: x = x0 (zero for a zero start, which
@@ -509,6 +518,12 @@ __global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
             if (threadIdx.x == 0) s->fixed = 1;
         }
     }
+}
+
+template <typename T, int M, bool V, bool NT, bool W>
+__global__ __launch_bounds__(kBlock) void k_fixup(ColArgs a)
+{
+    fixup_dev<T, M, V, NT, W>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // FP64 true residual: ||b - A x|| into state.aux (T = double only).
@@ -591,9 +606,8 @@ __device__ __forceinline__ void residual64_body(const ColArgs& a, SolverState* s
 }
 
 template <int M, bool V, bool G, bool NT, bool W>
-__global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
+__device__ __forceinline__ void residual64_dev(const ColArgs& a, int64_t t)
 {
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
@@ -609,6 +623,12 @@ __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
             if (s->iter == 0) s->r0norm = rn;
         }
     }
+}
+
+template <int M, bool V, bool G, bool NT, bool W>
+__global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
+{
+    residual64_dev<M, V, G, NT, W>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Refinement update: x64 += (u32 + alpha p32) / scale, u32 being the inner
@@ -660,9 +680,8 @@ __device__ __forceinline__ void update64_body(const ColArgs& a, const SolverStat
 }
 
 template <int M, bool V, bool NT, bool W>
-__global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
+__device__ __forceinline__ void update64_dev(const ColArgs& a, int64_t t)
 {
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
@@ -671,12 +690,17 @@ __global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
     else update64_body<M, V, false, NT, W>(a, s, si, rhs, blk);
 }
 
+template <int M, bool V, bool NT, bool W>
+__global__ __launch_bounds__(kBlock) void k_update64(ColArgs a)
+{
+    update64_dev<M, V, NT, W>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // Mode-1 reductions: one workgroup per right-hand side totals the published
 // partial sums in the same order as mode 0 and performs the scalar step.
 template <Kind K>
-__global__ __launch_bounds__(kFinalThreads) void k_finalize(ColArgs a)
+__device__ __forceinline__ void finalize_dev(const ColArgs& a, int64_t rhs)
 {
-    const int64_t rhs = blockIdx.x;
     SolverState* s = a.st + rhs;
     const double* part = a.part + rhs * a.blocks_per_rhs * kRedSlots;
     if (K == Kind::Fixup) {
@@ -704,7 +728,13 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(ColArgs a)
     }
 }
 
-bool has_finalize(Kind k)
+template <Kind K>
+__global__ __launch_bounds__(kFinalThreads) void k_finalize(ColArgs a)
+{
+    finalize_dev<K>(a, blockIdx.x);
+}
+
+inline bool has_finalize(Kind k)
 {
     return k == Kind::FusedPrec || k == Kind::FusedApply || k == Kind::FusedPrecFirst ||
            k == Kind::FusedApplyFirst || k == Kind::Fixup ||
@@ -712,7 +742,7 @@ bool has_finalize(Kind k)
            k == Kind::MgSmoothFinal || k == Kind::RbRedFinal;
 }
 
-const void* finalize_func(Kind kind)
+inline const void* finalize_func(Kind kind)
 {
     switch (kind) {
     case Kind::FusedPrec:
@@ -817,7 +847,7 @@ const void* main_func(Kind kind, const ColArgs& a, int64_t batch)
 }  // namespace
 
 // Kernels dominated by the line solve run with their own launch shape.
-static bool line_solve_kind(Kind k)
+static inline bool line_solve_kind(Kind k)
 {
     return k == Kind::FusedPrec || k == Kind::FusedPrecFirst || k == Kind::Precond ||
            k == Kind::MgPre ||

@@ -1,4 +1,5 @@
-"""Serving runtime on the GPU, through the C ABI: results identical alone and
+"""Serving runtime on the GPU, through the C ABI, with per-request workers and
+in batched mode (shared multi-request launches): results identical alone and
 in a concurrent mix of different grids (line, multigrid, block Gauss-Seidel
 and automatically chosen preconditioners; and identical to a direct solve),
 admission by HBM budget, rejection of requests that can never fit,
@@ -32,11 +33,11 @@ def requests(precision=pcg.PCG_PREC_MIXED, preconditioner=pcg.PCG_PRECOND_LINE):
     return out, pcg.pcg_default_opts(precision=precision, preconditioner=preconditioner)
 
 
-def serve(reqs, opts, max_active, budget=None, one_at_a_time=False):
+def serve(reqs, opts, max_active, budget=None, one_at_a_time=False, batched=False):
     need = max(pcg.pcg_request_bytes(d, opts) for d, _ in reqs)
     arena = torch.empty(sum(pcg.pcg_request_bytes(d, opts) for d, _ in reqs) + (1 << 20),
                         dtype=torch.uint8, device="cuda")
-    srv = pcg.Server(arena, budget or arena.numel(), max_active)
+    srv = pcg.Server(arena, budget or arena.numel(), max_active, batched=batched)
     xs, res = [None] * len(reqs), [None] * len(reqs)
     try:
         if one_at_a_time:
@@ -201,5 +202,79 @@ def test_zero_right_hand_side_served_as_zero():
         xt = torch.full_like(bt, float("nan"))
         st, r = pcg.pcg_wait(srv, pcg.pcg_submit_device(srv, d, bt, xt, opts))
         assert st == pcg.PCG_OK and not xt.cpu().numpy().any()
+    finally:
+        srv.close()
+
+
+# ------------------------------------------------------------ batched mode --
+
+BATCH_SHAPES = [(32, 32, 32, 1e2), (48, 40, 64, 1e4), (16, 16, 128, 1e5), (64, 64, 32, 3e3),
+                (24, 20, 128, 1e3), (40, 40, 16, 1e2), (20, 36, 64, 5e4), (32, 32, 32, 1e2),
+                (96, 64, 64, 2e2), (8, 8, 8, 1e3)]
+
+
+def batch_requests(precision):
+    out = []
+    for rid, (nx, ny, nz, g2) in enumerate(BATCH_SHAPES):
+        d = pcg.pcg_desc_from_ratio(nx, ny, nz, 1.05, g2, pcg.PCG_BC_DIRICHLET)
+        out.append((d, si.rhs_uniform(nx, ny, nz, 1000 + rid)))
+    return out, pcg.pcg_default_opts(precision=precision)
+
+
+@pytest.mark.parametrize("precision", [pcg.PCG_PREC_MIXED, pcg.PCG_PREC_FP64])
+def test_batched_results_identical_alone_and_in_the_mix(precision):
+    """Batched mode: every request's result is bitwise the same served alone
+    and sharing launches with nine others (different grids and
+    anisotropies, requests joining and leaving between ticks), and within
+    the tolerance by the oracle's assembled matrix."""
+    reqs, opts = batch_requests(precision)
+    print("batched", precision, flush=True)
+    alone, ra, _, _ = serve(reqs, opts, max_active=1, one_at_a_time=True, batched=True)
+    mixed, rm, stats, _ = serve(reqs, opts, max_active=8, batched=True)
+    print("batched: peak requests sharing launches %d" % stats["peak_active"])
+    assert stats["completed"] == len(reqs) and stats["peak_active"] >= 2
+    for i, (d, b) in enumerate(reqs):
+        np.testing.assert_array_equal(alone[i], mixed[i])
+        assert ra[i]["iterations"] == rm[i]["iterations"]
+        g = oracle.Grid(d.nx, d.ny, d.nz, d.dx, d.dy, d.height, d.grading, d.k_h, d.k_v,
+                        False, False)
+        A = oracle.assemble(g)
+        true = oracle.residual_norm(A, b, mixed[i]) / np.linalg.norm(b)
+        assert true < 1.05e-8, (i, true)
+
+
+def test_batched_device_io_zero_rhs_and_rejections():
+    """Batched mode with device-resident b and x equals host requests; a
+    zero right-hand side gives x = 0; grids and preconditioners the
+    multi-request kernels do not cover are rejected at submission."""
+    reqs, opts = batch_requests(pcg.PCG_PREC_MIXED)
+    host, _, _, _ = serve(reqs[:4], opts, max_active=4, batched=True)
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    srv = pcg.Server(arena, arena.numel(), 4, batched=True)
+    try:
+        outs, tickets = [], []
+        for d, b in reqs[:4]:
+            bt = torch.from_numpy(b).cuda()
+            xt = torch.full_like(bt, float("nan"))
+            outs.append(xt)
+            tickets.append(pcg.pcg_submit_device(srv, d, bt, xt, opts))
+        z = torch.zeros(reqs[0][1].size, dtype=torch.float64, device="cuda")
+        xz = torch.full_like(z, float("nan"))
+        tickets.append(pcg.pcg_submit_device(srv, reqs[0][0], z, xz, opts))
+        for t in tickets:
+            st, r = pcg.pcg_wait(srv, t)
+            assert st == pcg.PCG_OK, r
+        for i in range(4):
+            np.testing.assert_array_equal(outs[i].cpu().numpy(), host[i])
+        assert not xz.cpu().numpy().any()
+        bad = pcg.pcg_desc_from_ratio(16, 16, 100, 1.05, 1e3, pcg.PCG_BC_DIRICHLET)
+        bb = np.zeros(16 * 16 * 100)
+        with pytest.raises(pcg.PCGError) as e:
+            pcg.pcg_submit(srv, bad, bb, np.zeros_like(bb), opts)
+        assert e.value.status == pcg.PCG_E_INVALID
+        mg = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED, preconditioner=pcg.PCG_PRECOND_MG)
+        d0, b0 = reqs[0]
+        with pytest.raises(pcg.PCGError):
+            pcg.pcg_submit(srv, d0, b0, np.zeros_like(b0), mg)
     finally:
         srv.close()
