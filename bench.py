@@ -367,6 +367,7 @@ def extras(pcg, si, torch, main):
     out["serving_512_requests_auto_preconditioner"] = serving(
         pcg, si, torch, preconditioner=pcg.PCG_PRECOND_AUTO)
     out["serving_512_requests_batched"] = serving(pcg, si, torch, max_active=16, batched=True)
+    out["serving_2048_small_requests"] = serving_small(pcg, si, torch)
 
     # error of the 1024 x 1024 x 128 solutions against the oracle's FP64 solve
     log("waiting for the oracle's 1024x1024x128 FP64 solve")
@@ -556,16 +557,18 @@ def batched(pcg, si, torch, nrhs=64):
     return out
 
 
-def serving(pcg, si, torch, n_requests=512, max_active=4, preconditioner=0, batched=False):
-    """Poisson arrivals (mean 200/s, seed 5) of mixed-precision solves with
-    n x n x n_z grids, n in {64,128,256,512}, n_z in {32,64,128}, anisotropy
-    log-uniform in [1e2,1e5], U[-1,1) right-hand sides (seed 1000 + id),
-    device-resident; admitted by a 200 GB HBM budget.  The trace is replayed
-    once to warm the per-shape state, then timed.  batched: one scheduler
-    advances up to max_active requests with shared multi-request launches
-    (line preconditioner) instead of one worker per request."""
+def serving(pcg, si, torch, n_requests=512, max_active=4, preconditioner=0, batched=False,
+            rate=200.0, sizes=(64, 128, 256, 512), levels=(32, 64, 128)):
+    """Poisson arrivals (mean `rate`/s, seed 5) of mixed-precision solves with
+    n x n x n_z grids, n in `sizes` ({64,128,256,512}), n_z in `levels`
+    ({32,64,128}), anisotropy log-uniform in [1e2,1e5], U[-1,1) right-hand
+    sides (seed 1000 + id), device-resident; admitted by a 200 GB HBM budget.
+    The trace is replayed once to warm the per-shape state, then timed.
+    batched: one scheduler advances up to max_active requests with shared
+    multi-request launches (line preconditioner) instead of one worker per
+    request."""
     import numpy as np
-    trace = si.serving_trace(n_requests, 200.0, seed=5)
+    trace = si.serving_trace(n_requests, rate, seed=5, sizes=sizes, levels=levels)
     opts = pcg.pcg_default_opts(precision=pcg.PCG_PREC_MIXED, preconditioner=preconditioner)
     descs, bs, xs = [], [], []
     for r in trace:
@@ -619,6 +622,16 @@ def serving(pcg, si, torch, n_requests=512, max_active=4, preconditioner=0, batc
                 mode="batched (shared multi-request launches)" if batched else
                 "one worker and stream per admitted request",
                 input="device-resident right-hand sides (pcg_submit_device)")
+
+
+def serving_small(pcg, si, torch):
+    """Many small requests at a rate no single-request path keeps up with:
+    2048 mixed-precision solves on 32 x 32 or 64 x 64 grids with 32 or 64
+    levels, Poisson arrivals at 20000/s, served by per-request workers (8)
+    and in batched mode (64 requests per launch)."""
+    kw = dict(n_requests=2048, rate=20000.0, sizes=(32, 64), levels=(32, 64))
+    return dict(workers=serving(pcg, si, torch, max_active=8, **kw),
+                batched=serving(pcg, si, torch, max_active=64, batched=True, **kw))
 
 
 def profile_run(pcg, si, torch, steps, mixed_1024):
@@ -1001,7 +1014,8 @@ def main():
 
     if args.serving_only:
         print(json.dumps(dict(workers=serving(pcg, si, torch),
-                              batched=serving(pcg, si, torch, max_active=16, batched=True))))
+                              batched=serving(pcg, si, torch, max_active=16, batched=True),
+                              small=serving_small(pcg, si, torch))))
         return
 
     if args.mg_only or args.rbgs_only:
