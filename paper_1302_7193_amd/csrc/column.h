@@ -112,9 +112,11 @@ __device__ __forceinline__ T segment_carry(T P, T Q, int l, int L)
     return Qx + Px * cr;
 }
 
+// Column indices, and element offsets col * n_z within one right-hand side,
+// fit 32 bits: problems have fewer than 2^31 unknowns.
 struct Col {
-    int64_t idx;
-    int64_t im, ip, jm, jp;  // neighbour columns, -1 across a Dirichlet face
+    int32_t idx;
+    int32_t im, ip, jm, jp;  // neighbour columns, -1 across a Dirichlet face
     int i, j;                // horizontal position
     int cls;                 // column class: 3 * (#Dirichlet x faces) + #Dirichlet y faces
     double alpha_t;          // alpha_T = sum of alpha_{T,T'}, Dirichlet faces twice
@@ -136,14 +138,14 @@ __device__ __forceinline__ Col make_col_ij(const Geom& g, int i, int j, bool ok,
     if (!ok) i = j = 0;
     o.i = i;
     o.j = j;
-    const int64_t cc = (int64_t)i * g.ny + j;
+    const int32_t cc = i * g.ny + j;
     o.idx = cc;
     int cx = 0, cy = 0;
     if (i > 0) o.im = cc - g.ny;
-    else if (g.per_x) o.im = cc + (int64_t)(g.nx - 1) * g.ny;
+    else if (g.per_x) o.im = cc + (g.nx - 1) * g.ny;
     else { o.im = -1; ++cx; }
     if (i < g.nx - 1) o.ip = cc + g.ny;
-    else if (g.per_x) o.ip = cc - (int64_t)(g.nx - 1) * g.ny;
+    else if (g.per_x) o.ip = cc - (g.nx - 1) * g.ny;
     else { o.ip = -1; ++cx; }
     if (j > 0) o.jm = cc - 1;
     else if (g.per_y) o.jm = cc + (g.ny - 1);
@@ -217,9 +219,13 @@ __device__ __forceinline__ void ld(const T* __restrict__ v, int64_t col, bool ok
 {
     if (V) {
         const bool in = ok && k0 < nz;
-        const uint32_t kk = uint32_t(k0 < nz ? k0 : nz - M);
-        const T* base = v + (ok ? col : int64_t(0)) * nz;
-        const T* p = static_cast<const T*>(__builtin_assume_aligned(base + kk, kChunkAlign<T, M>));
+        // the lane's part of the address as a 32-bit byte offset (a column
+        // holds < 2^32 bytes): with a uniform column the load then takes a
+        // scalar base and one offset register shared by every column
+        const uint32_t kb = uint32_t(k0 < nz ? k0 : nz - M) * uint32_t(sizeof(T));
+        const T* base = v + uint32_t(ok ? col : int64_t(0)) * uint32_t(nz);
+        const T* p = static_cast<const T*>(__builtin_assume_aligned(
+            reinterpret_cast<const char*>(base) + kb, kChunkAlign<T, M>));
 #pragma unroll
         for (int t = 0; t < M; ++t) o[t] = ld1<NT>(p + t);
 #pragma unroll
@@ -239,8 +245,10 @@ __device__ __forceinline__ void st(T* __restrict__ v, int64_t col, bool ok, int 
 {
     if (V) {
         if (ok && k0 < nz) {
-            T* base = v + col * nz;
-            T* p = static_cast<T*>(__builtin_assume_aligned(base + k0, kChunkAlign<T, M>));
+            T* base = v + uint32_t(col) * uint32_t(nz);
+            T* p = static_cast<T*>(__builtin_assume_aligned(
+                reinterpret_cast<char*>(base) + uint32_t(k0) * uint32_t(sizeof(T)),
+                kChunkAlign<T, M>));
 #pragma unroll
             for (int t = 0; t < M; ++t) st1<NT>(p + t, o[t]);
         }
@@ -642,10 +650,23 @@ __device__ __forceinline__ void line_solve(const Geom& g, const Col& c, int l, i
 __device__ __forceinline__ void block_tiles(const Geom& g, int L, int64_t blk, int64_t nblk,
                                             int64_t& t0, int64_t& t1)
 {
-    const int64_t cols = (int64_t)(kWave / L) * (kBlock / kWave);
-    const int64_t ntiles = (g.nh + cols - 1) / cols;
-    t0 = blk * ntiles / nblk;
-    t1 = (blk + 1) * ntiles / nblk;
+    // tiles and workgroups number < 2^31: 32-bit divisions; the first
+    // ntiles mod nblk workgroups take one tile more
+    const uint32_t cols = uint32_t(kWave / L) * uint32_t(kBlock / kWave);
+    const uint32_t ntiles = (uint32_t(g.nh) + cols - 1) / cols;
+    const uint32_t b = uint32_t(blk), nb = uint32_t(nblk);
+    const uint32_t q = ntiles / nb, r = ntiles - q * nb;
+    t0 = int64_t(b) * q + (b < r ? b : r);
+    t1 = t0 + q + (b < r ? 1 : 0);
+}
+
+// Right-hand side and workgroup within it of launch workgroup t (grids have
+// fewer than 2^31 workgroups: a 32-bit division).
+__device__ __forceinline__ void split_rhs(int64_t t, int64_t bpr, int64_t& rhs, int64_t& blk)
+{
+    const uint32_t r = uint32_t(t) / uint32_t(bpr);
+    rhs = r;
+    blk = t - int64_t(r) * bpr;
 }
 
 struct Lane {

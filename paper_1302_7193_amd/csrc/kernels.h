@@ -18,7 +18,7 @@ namespace {
 // Tiles a wavefront takes at a time in the kernels with a single input
 // stream (the operator and the preconditioner alone, the first launches of
 // kernels A and B): their loads are issued together before any arithmetic.
-constexpr int kStepApply = 4, kStepPrecond = 2, kStepFirstA = 4, kStepFirstB = 2;
+constexpr int kStepApply = 4, kStepPrecond = 4, kStepFirstA = 4, kStepFirstB = 4;
 
 inline int step_of(Kind k)
 {
@@ -50,6 +50,29 @@ __device__ __forceinline__ int64_t step_col(const Geom& g, int64_t tile, int u, 
     const int64_t tu = tile + u;
     if (tu >= t1) return g.nh;
     return W ? wave_col(tu, p) : tile_col(tu, p, L);
+}
+
+// The geometry of a wavefront step's U columns.  JS: consecutive columns of
+// one grid row (n_y a multiple of U, the step's first column a multiple of
+// U), so one division by n_y places all of them.
+template <bool G, bool W, int U, bool JS>
+__device__ __forceinline__ void step_cols(const Geom& g, int64_t tile, int64_t t1, const Lane& p,
+                                          int L, const double* hgeo, Col (&c)[U])
+{
+    static_assert(!JS || (kBlock / kWave) % U == 0, "a step's first column must be a multiple of U");
+    if constexpr (JS) {
+        const int64_t c0 = step_col<W, U, true>(g, tile, 0, t1, p, L);
+        const int64_t lim = t1 * (kBlock / kWave) < g.nh ? t1 * (kBlock / kWave) : g.nh;
+        const uint32_t cc = c0 < lim ? uint32_t(c0) : 0u;
+        const uint32_t i = cc / uint32_t(g.ny);
+        const int j0 = int(cc - i * uint32_t(g.ny));
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = make_col_ij<G>(g, int(i), j0 + u, c0 + u < lim, hgeo);
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            c[u] = make_col<G>(g, step_col<W, U, false>(g, tile, u, t1, p, L), hgeo);
+    }
 }
 
 // The stencil inputs of a wavefront step's U columns.  JS: the columns are
@@ -95,7 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     if (a.st && a.st[rhs].flag != kRunning) return;   // inside a solve: stop when done
     const T* x = static_cast<const T*>(a.in0) + rhs * g.n;
     T* y = static_cast<T*>(a.io0) + rhs * g.n;
@@ -108,9 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(ColArgs a)
         Col c[U];
         StencilIn<T, M> in[U];
         T yc[U][M];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            c[u] = make_col<G>(g, step_col<W, U, JS>(g, tile, u, t1, p, L), a.hgeo);
+        step_cols<G, W, U, JS>(g, tile, t1, p, L, a.hgeo, c);
         load_group<T, M, V, U, JS>(g, c, p.k0, x, in);
 #pragma unroll
         for (int u = 0; u < U; ++u) stencil_in<T, M, G>(g, c[u], p.l, L, in[u], vc, yc[u]);
@@ -125,7 +147,8 @@ __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     if (a.st && a.st[rhs].flag != kRunning) return;
     const T* r = static_cast<const T*>(a.in0) + rhs * g.n;
     T* z = static_cast<T*>(a.io0) + rhs * g.n;
@@ -137,9 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_precond(ColArgs a)
     for (int64_t tile = t0; tile < t1; tile += U) {
         Col c[U];
         T rc[U][M], zc[U][M];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            c[u] = make_col<G>(g, step_col<W, U, false>(g, tile, u, t1, p, L), a.hgeo);
+        step_cols<G, W, U, false>(g, tile, t1, p, L, a.hgeo, c);
 #pragma unroll
         for (int u = 0; u < U; ++u) ld<T, M, V, NT>(r, c[u].idx, c[u].ok, p.k0, g.nz, rc[u]);
 #pragma unroll
@@ -156,7 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     const int64_t off = rhs * g.n;
     T* x = static_cast<T*>(a.io0) + off;
     const T* b = static_cast<const T*>(a.in1) + off;
@@ -248,7 +270,8 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
 template <typename T, int M, bool V, bool G, bool NT, bool W>
 __device__ __forceinline__ void fused_prec_dev(const ColArgs& a, int64_t t)
 {
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[2] = {0.0, 0.0};
@@ -333,7 +356,8 @@ __device__ __forceinline__ void fused_apply_body(const ColArgs& a, SolverState* 
 template <typename T, int M, bool V, bool G, bool NT, bool W>
 __device__ __forceinline__ void fused_apply_dev(const ColArgs& a, int64_t t)
 {
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[1] = {0.0};
@@ -367,7 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec_first(ColArgs a)
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st + rhs;
     const int32_t flag = s->flag;
     const int64_t off = rhs * g.n;
@@ -384,9 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec_first(ColArgs a)
     for (int64_t tile = t0; tile < t1; tile += U) {
         Col c[U];
         T rc[U][M], zc[U][M];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            c[u] = make_col<G>(g, step_col<W, U, false>(g, tile, u, t1, p, L), a.hgeo);
+        step_cols<G, W, U, false>(g, tile, t1, p, L, a.hgeo, c);
 #pragma unroll
         for (int u = 0; u < U; ++u) ld<T, M, V, NT>(src, c[u].idx, c[u].ok, p.k0, g.nz, rc[u]);
         if (flag != kRunning) return;   // the same in every thread of the workgroup
@@ -425,7 +448,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply_first(ColArgs a)
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st + rhs;
     const int32_t flag = s->flag;
     const int64_t off = rhs * g.n;
@@ -442,9 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply_first(ColArgs a)
         Col c[U];
         StencilIn<T, M> in[U];
         T az[U][M];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            c[u] = make_col<G>(g, step_col<W, U, JS>(g, tile, u, t1, p, L), a.hgeo);
+        step_cols<G, W, U, JS>(g, tile, t1, p, L, a.hgeo, c);
         load_group<T, M, V, U, JS>(g, c, p.k0, z, in);
 #pragma unroll
         for (int u = 0; u < U; ++u) stencil_in<T, M, G>(g, c[u], p.l, L, in[u], vc, az[u]);
@@ -473,7 +495,8 @@ __device__ __forceinline__ void fixup_dev(const ColArgs& a, int64_t t)
 {
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st + rhs;
     // stopped before the first iteration: x = x0 (zero for a zero start, which
     // nothing has written yet -- also after a breakdown in the first kernel)
@@ -533,7 +556,8 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st + rhs;
     const double* x = static_cast<const double*>(a.in0) + rhs * g.n;
     const double* b = static_cast<const double*>(a.in1) + rhs * g.n;
@@ -608,7 +632,8 @@ __device__ __forceinline__ void residual64_body(const ColArgs& a, SolverState* s
 template <int M, bool V, bool G, bool NT, bool W>
 __device__ __forceinline__ void residual64_dev(const ColArgs& a, int64_t t)
 {
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[1] = {0.0};
@@ -682,7 +707,8 @@ __device__ __forceinline__ void update64_body(const ColArgs& a, const SolverStat
 template <int M, bool V, bool NT, bool W>
 __device__ __forceinline__ void update64_dev(const ColArgs& a, int64_t t)
 {
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     const SolverState* si = a.st_in + rhs;

@@ -47,7 +47,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_pre(ColArgs a)
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st ? a.st + rhs : nullptr;
     if (s && s->flag != kRunning) return;
     const int64_t off = rhs * g.n;
@@ -103,7 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(ColArgs a)
     const Geom& gf = a.g2;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     if (a.st && a.st[rhs].flag != kRunning) return;
     const T* r = static_cast<const T*>(a.in0) + rhs * gf.n;
     const T* z = static_cast<const T*>(a.in1) + rhs * gf.n;
@@ -149,7 +151,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_post(ColArgs a)
     const Geom& gc = a.g2;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st ? a.st + rhs : nullptr;
     if (s && s->flag != kRunning) return;
     const int64_t off = rhs * g.n;

@@ -57,7 +57,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_first(ColArgs a)
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st ? a.st + rhs : nullptr;
     if (s && s->flag != kRunning) return;
     const int64_t off = rhs * g.n;
@@ -116,7 +117,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(ColArgs a)
     const Geom& g = a.g;
     const int L = W ? kWave : a.L;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t rhs = t / a.blocks_per_rhs, blk = t - rhs * a.blocks_per_rhs;
+    int64_t rhs, blk;
+    split_rhs(t, a.blocks_per_rhs, rhs, blk);
     SolverState* s = a.st ? a.st + rhs : nullptr;
     if (s && s->flag != kRunning) return;
     const int64_t off = rhs * g.n;
