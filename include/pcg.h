@@ -93,7 +93,9 @@ typedef struct {
     int32_t profile;      /* 1: time every fused kernel with HIP events
                              (event records between the launches, or event
                              nodes inside the graph chunks); single
-                             right-hand side; fills the *_kernel_* fields */
+                             right-hand side; fills the *_kernel_* fields;
+                             2: kernel A only (half the events; the
+                             precond fields stay 0)                        */
     int32_t true_residual;/* 1: also compute ||b - A x|| / ||r0|| in FP64    */
     int32_t x0_zero;      /* 1: start from x0 = 0 without reading x          */
     int32_t preconditioner; /* PCG_PRECOND_LINE (default), _MG or _RBGS       */

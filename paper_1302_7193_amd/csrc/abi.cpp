@@ -132,6 +132,10 @@ pcg_status check_opts(const pcg_solve_opts& o)
         set_error("graph_chunk must be -1, 0 or positive");
         return PCG_E_INVALID;
     }
+    if (o.profile < 0 || o.profile > 2) {
+        set_error("profile must be 0, 1 or 2");
+        return PCG_E_INVALID;
+    }
     if (o.preconditioner < PCG_PRECOND_LINE || o.preconditioner > PCG_PRECOND_AUTO ||
         o.mg_levels < 0) {
         set_error("preconditioner must be PCG_PRECOND_LINE, _MG, _RBGS or _AUTO, mg_levels >= 0");

@@ -454,13 +454,14 @@ void key_launch(GraphKey& k, const KernelLaunch& l)
 // The chunk as an explicitly built HIP graph (kernel nodes in sequence).  No
 // stream capture is involved, so building is independent of what other host
 // threads do with their streams.
-// profiled: event record nodes around every kernel A and kernel B's launches
-// up to its last main kernel, events P->gevents[4i .. 4i+3] for iteration i.
+// profiled: event record nodes around every kernel A (events
+// P->gevents[4i], [4i+1] for iteration i) and, when 1, kernel B's launches up
+// to its last main kernel ([4i+2], [4i+3]); 2: kernel A only.
 // first: the chunk that starts a solve (its first kernel A is the
 // first-launch kernel).
 template <typename T>
 pcg_status chunk_graph(pcg_problem* P, const ColArgs& a, const Phase& bph,
-                       int64_t nrhs, int K, bool first, bool fixup, bool profiled,
+                       int64_t nrhs, int K, bool first, bool fixup, int profiled,
                        hipGraphExec_t* out)
 {
     if (profiled) {
@@ -489,9 +490,9 @@ pcg_status chunk_graph(pcg_problem* P, const ColArgs& a, const Phase& bph,
         }
         if (profiled) marks.emplace_back(a_main + 1, P->gevents[4 * i + 1]);   // before its finalize
         const size_t b0 = seq.size();
-        if (profiled) marks.emplace_back(b0, P->gevents[4 * i + 2]);
+        if (profiled == 1) marks.emplace_back(b0, P->gevents[4 * i + 2]);
         seq.insert(seq.end(), bph.k.begin(), bph.k.end());
-        if (profiled) marks.emplace_back(b0 + bph.last_main + 1, P->gevents[4 * i + 3]);
+        if (profiled == 1) marks.emplace_back(b0 + bph.last_main + 1, P->gevents[4 * i + 3]);
     }
     if (fixup && !add(Kind::Fixup)) {
         set_error("graph: no kernel for this shape (internal)");
@@ -499,7 +500,7 @@ pcg_status chunk_graph(pcg_problem* P, const ColArgs& a, const Phase& bph,
     }
     GraphKey key;
     key.reserve(1 + seq.size() * 48);
-    key.push_back(profiled ? 1 : 0);
+    key.push_back((uint64_t)profiled);
     for (const KernelLaunch& l : seq) key_launch(key, l);
     const uint64_t now = ++P->graph_clock;
     auto it = P->graphs.find(key);
@@ -589,7 +590,7 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_
     a.zswap = o.preconditioner == PCG_PRECOND_LINE ? 1 : 0;
     Phase bph;
     if (b_phase<T>(P, dtype, a, nrhs, o, ws, w, bph) != PCG_OK) return PCG_E_DEVICE;
-    const bool profile = o.profile != 0 && nrhs == 1;
+    const int profile = nrhs == 1 ? o.profile : 0;   // 1: kernels A and B, 2: A only
     int K = o.graph_chunk > 0 ? o.graph_chunk : P->last_iters[prec_slot];
     if (K <= 0) K = 8;
     K = std::min(K, std::max(1, o.max_iter));
@@ -642,7 +643,7 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_
         tms.push_back(Timing{kind_a, i, 0.f});
         return PCG_OK;
     };
-    if (profile) {
+    if (profile == 1) {
         if (timed(bph_first, 0) != PCG_OK) return PCG_E_DEVICE;
     } else if (issue_phase(bph_first, s, info.launches) != PCG_OK) {
         return PCG_E_DEVICE;
@@ -655,7 +656,9 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_
         if (profile && !use_graph) {
             for (int i = 0; i < K; ++i) {
                 if (timed((first && i == 0) ? aph_first : aph, 1) != PCG_OK) return PCG_E_DEVICE;
-                if (timed(bph, 0) != PCG_OK) return PCG_E_DEVICE;
+                if (profile == 1 ? timed(bph, 0) != PCG_OK
+                                 : issue_phase(bph, s, info.launches) != PCG_OK)
+                    return PCG_E_DEVICE;
             }
             if (fixup && launch<T>(Kind::Fixup, a, nrhs, s, info.launches)) return PCG_E_DEVICE;
         } else if (use_graph) {
@@ -674,9 +677,10 @@ pcg_status run_fused(pcg_problem* P, int dtype, int prec_slot, const ColArgs& a_
                 float ma = 0.f, mb = 0.f;
                 PCG_HIP(hipEventElapsedTime(&ma, P->gevents[4 * i], P->gevents[4 * i + 1]),
                         "hipEventElapsedTime");
+                tms.push_back(Timing{1, -1, ma});
+                if (profile != 1) continue;
                 PCG_HIP(hipEventElapsedTime(&mb, P->gevents[4 * i + 2], P->gevents[4 * i + 3]),
                         "hipEventElapsedTime");
-                tms.push_back(Timing{1, -1, ma});
                 tms.push_back(Timing{0, -1, mb});
             }
         }

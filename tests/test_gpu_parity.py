@@ -241,11 +241,19 @@ def test_graph_and_direct_launches_bitwise_equal():
     xp, _, rp = gpu_solve(d, b, graph_chunk=0, profile=1)
     # profiled graph chunks: event nodes inside the graph, several replays
     xq, _, rq = gpu_solve(d, b, graph_chunk=2, profile=1)
+    # kernel A timed alone, graph chunks and direct launches
+    xa, _, ra = gpu_solve(d, b, graph_chunk=2, profile=2)
+    xe, _, re_ = gpu_solve(d, b, graph_chunk=0, profile=2)
     assert rg["iterations"] == rd["iterations"] == rp["iterations"] == rq["iterations"]
-    assert np.array_equal(xg, xd) and np.array_equal(xg, xp) and np.array_equal(xg, xq)
+    assert ra["iterations"] == re_["iterations"] == rg["iterations"]
+    for x in (xd, xp, xq, xa, xe):
+        assert np.array_equal(xg, x)
     for r in (rp, rq):
         assert r["n_apply_kernel"] == r["iterations"] and r["n_precond_kernel"] == r["iterations"] + 1
         assert r["ms_apply_kernel"] > 0 and r["ms_precond_kernel"] > 0
+    for r in (ra, re_):
+        assert r["n_apply_kernel"] == r["iterations"] and r["n_precond_kernel"] == 0
+        assert r["ms_apply_kernel"] > 0 and r["ms_precond_kernel"] == 0
 
 
 def test_repeated_solves_bitwise_reproducible():
