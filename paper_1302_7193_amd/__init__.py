@@ -308,15 +308,22 @@ def pcg_mg_precond(p: Problem, dtype: int, r, z, ws, mg_levels: int = 0, stream=
                   "pcg_mg_precond")
 
 
+def _check_ws(status: int, where: str) -> int:
+    """_check, with a workspace the library found too small (it checks the
+    size itself, so the binding does not query it per call) as ValueError."""
+    if status == PCG_E_NOMEM and "workspace" in pcg_last_error():
+        raise ValueError("%s: %s" % (where, pcg_last_error()))
+    return _check(status, where)
+
+
 def pcg_solve(p: Problem, b, x, ws, opts: pcg_solve_opts | None = None, stream=None):
     """Returns (status, result dict)."""
     opts = opts or pcg_default_opts()
-    need = pcg_workspace_bytes(p, opts, 1)
     res = pcg_result()
-    st = _check(_lib.pcg_solve(p.handle, _vec(b, p.n, torch.float64, "b"),
-                               _vec(x, p.n, torch.float64, "x"), _buf(ws, need, "workspace"),
-                               ws.numel() * ws.element_size(), ctypes.byref(opts),
-                               ctypes.byref(res), _stream(stream)), "pcg_solve")
+    st = _check_ws(_lib.pcg_solve(p.handle, _vec(b, p.n, torch.float64, "b"),
+                                  _vec(x, p.n, torch.float64, "x"), _buf(ws, 0, "workspace"),
+                                  ws.numel() * ws.element_size(), ctypes.byref(opts),
+                                  ctypes.byref(res), _stream(stream)), "pcg_solve")
     return st, res.as_dict()
 
 
@@ -335,13 +342,13 @@ def pcg_solve_batched(p: Problem, nrhs: int, b, x, ws, opts: pcg_solve_opts | No
                       stream=None):
     """Returns (status, [result dict per right-hand side])."""
     opts = opts or pcg_default_opts()
-    need = pcg_workspace_bytes(p, opts, nrhs)
     res = (pcg_result * nrhs)()
-    st = _check(_lib.pcg_solve_batched(p.handle, nrhs, _vec(b, nrhs * p.n, torch.float64, "b"),
-                                       _vec(x, nrhs * p.n, torch.float64, "x"),
-                                       _buf(ws, need, "workspace"), ws.numel() * ws.element_size(),
-                                       ctypes.byref(opts), res, _stream(stream)),
-                "pcg_solve_batched")
+    st = _check_ws(_lib.pcg_solve_batched(p.handle, nrhs,
+                                          _vec(b, nrhs * p.n, torch.float64, "b"),
+                                          _vec(x, nrhs * p.n, torch.float64, "x"),
+                                          _buf(ws, 0, "workspace"), ws.numel() * ws.element_size(),
+                                          ctypes.byref(opts), res, _stream(stream)),
+                   "pcg_solve_batched")
     return st, [r.as_dict() for r in res]
 
 

@@ -97,13 +97,15 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (&out)[NV])
 }
 
 // Fixed-order total of the nblk published partial sums, computed as if by
-// kFinalThreads virtual threads: virtual thread v adds slots v, v + 1024, ...
-// in order, virtual wavefronts add their 64 lanes by shuffles, and the 16
-// wavefront sums are added in order.  A workgroup of BS threads plays
-// 1024 / BS virtual threads per thread, so the finalize launch (1024
-// threads) and the in-kernel mode (256 threads) produce identical bits.
-// Every thread gets the totals.  COHERENT: device-scope atomic loads
-// (partials written by other workgroups of the running kernel).
+// kFinalThreads virtual threads.  The slots are read in 16-byte steps (two
+// slots of a one-value reduction, one slot of a two-value one): virtual
+// thread v adds steps v, v + 1024, ... in order (a step's slots in order),
+// virtual wavefronts add their 64 lanes by shuffles, and the 16 wavefront
+// sums are added in order.  A workgroup of BS threads plays 1024 / BS
+// virtual threads per thread, so the finalize launch (1024 threads) and the
+// in-kernel mode (256 threads) produce identical bits.  Every thread gets
+// the totals.  COHERENT: device-scope atomic loads (partials written by
+// other workgroups of the running kernel).
 constexpr int kFinalThreads = 1024;
 
 template <int NV, bool COHERENT, int BS>
@@ -111,42 +113,65 @@ __device__ __forceinline__ void sum_partials(const double* part, int64_t nblk, d
 {
     constexpr int R = kFinalThreads / BS;
     constexpr int kWavesV = kFinalThreads / kWave;
+    constexpr int S = 2 / NV;          // slots per 16-byte step
     __shared__ double sm[kWavesV][NV];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t full = nblk / S;     // steps whose slots all exist
+    const int64_t steps = (nblk + S - 1) / S;
     double acc[R][NV];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) acc[r][i] = 0.0;
         const int64_t v = threadIdx.x + (int64_t)r * BS;
-        auto load = [&](int64_t b, int i) {
-            const double* q = &part[b * NV + i];
-            return COHERENT ? __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *q;
+        // the two doubles of step b
+        auto load2 = [&](int64_t b, double (&o)[2]) {
+            const double* q = part + 2 * b;
+            if constexpr (COHERENT) {
+                o[0] = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                o[1] = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                const double2 d = *reinterpret_cast<const double2*>(q);
+                o[0] = d.x;
+                o[1] = d.y;
+            }
+        };
+        auto add2 = [&](const double (&o)[2]) {
+            if constexpr (NV == 1) {
+                acc[r][0] += o[0];
+                acc[r][0] += o[1];
+            } else {
+                acc[r][0] += o[0];
+                acc[r][1] += o[1];
+            }
         };
         int64_t b = v;
-        // U slots' loads in flight, added in slot order: the latency of
+        // U steps' loads in flight, added in step order: the latency of
         // reading partials written by other XCDs sets the finalize launch's
         // time (32 in flight); inside a main kernel (COHERENT) 8 keep its
         // registers low
         auto chunk = [&](auto U_) {
             constexpr int U = decltype(U_)::value;
-            for (; b + (U - 1) * (int64_t)kFinalThreads < nblk; b += U * (int64_t)kFinalThreads) {
-                double t[U][NV];
+            for (; b + (U - 1) * (int64_t)kFinalThreads < full; b += U * (int64_t)kFinalThreads) {
+                double t[U][2];
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+                for (int u = 0; u < U; ++u) load2(b + (int64_t)u * kFinalThreads, t[u]);
 #pragma unroll
-                    for (int i = 0; i < NV; ++i) t[u][i] = load(b + (int64_t)u * kFinalThreads, i);
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int i = 0; i < NV; ++i) acc[r][i] += t[u][i];
+                for (int u = 0; u < U; ++u) add2(t[u]);
             }
         };
         if constexpr (!COHERENT) chunk(std::integral_constant<int, 32>{});
         chunk(std::integral_constant<int, 8>{});
-        for (; b < nblk; b += kFinalThreads) {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) acc[r][i] += load(b, i);
+        for (; b < steps; b += kFinalThreads) {
+            if (b < full) {
+                double t[2];
+                load2(b, t);
+                add2(t);
+            } else {   // the last slot of an odd count (one-value reductions)
+                acc[r][0] += COHERENT ? __hip_atomic_load(part + 2 * b, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                      : part[2 * b];
+            }
         }
 #pragma unroll
         for (int i = 0; i < NV; ++i) acc[r][i] = wave_sum(acc[r][i]);
