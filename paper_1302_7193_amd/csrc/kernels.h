@@ -19,6 +19,7 @@ namespace {
 // stream (the operator and the preconditioner alone, the first launches of
 // kernels A and B): their loads are issued together before any arithmetic.
 constexpr int kStepApply = 4, kStepPrecond = 4, kStepFirstA = 4, kStepFirstB = 4;
+constexpr int kStepResidual = 4;   // the FP64 refinement residual (a stencil too)
 
 inline int step_of(Kind k)
 {
@@ -27,6 +28,7 @@ inline int step_of(Kind k)
     case Kind::Precond: return kStepPrecond;
     case Kind::FusedApplyFirst: return kStepFirstA;
     case Kind::FusedPrecFirst: return kStepFirstB;
+    case Kind::Residual64: return kStepResidual;
     default: return 1;
     }
 }
@@ -591,7 +593,7 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(ColArgs a)
 // not read), ||r64|| into state.rnorm (state.r0norm on the first call), FP32
 // copy r32 = r64 * scale.  The FP32 vectors take the FP64 launch shape:
 // chunks of M floats, aligned to their size whenever the FP64 ones are.
-template <int M, bool V, bool ZERO, bool G, bool NT, bool W>
+template <int M, bool V, bool ZERO, bool G, bool NT, bool W, int U, bool JS>
 __device__ __forceinline__ void residual64_body(const ColArgs& a, SolverState* s, int64_t rhs,
                                                 int64_t blk, double (&acc)[1])
 {
@@ -606,30 +608,39 @@ __device__ __forceinline__ void residual64_body(const ColArgs& a, SolverState* s
     const VertCoef<double, M> vc = load_vert<double, M, V>(g, vert, p.k0);
     int64_t t0, t1;
     block_tiles(g, L, blk, a.blocks_per_rhs, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        const Col c = make_col<G>(g, W ? wave_col(tile, p) : tile_col(tile, p, L), a.hgeo);
-        double ax[M], bc[M];
-        float rc[M];
-        StencilIn<double, M> in;
-        ld<double, M, V, NT>(b, c.idx, c.ok, p.k0, g.nz, bc);
+    // U tiles per wavefront step, their loads issued together (see k_apply)
+    for (int64_t tile = t0; tile < t1; tile += U) {
+        Col c[U];
+        double ax[U][M], bc[U][M];
+        step_cols<G, W, U, JS>(g, tile, t1, p, L, a.hgeo, c);
+#pragma unroll
+        for (int u = 0; u < U; ++u) ld<double, M, V, NT>(b, c[u].idx, c[u].ok, p.k0, g.nz, bc[u]);
         if constexpr (ZERO) {
 #pragma unroll
-            for (int i = 0; i < M; ++i) ax[i] = 0.0;
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int i = 0; i < M; ++i) ax[u][i] = 0.0;
         } else {
-            load_stencil<double, M, V>(g, c, p.k0, x, in);
-            stencil_in<double, M, G>(g, c, p.l, L, in, vc, ax);
+            StencilIn<double, M> in[U];
+            load_group<double, M, V, U, JS>(g, c, p.k0, x, in);
+#pragma unroll
+            for (int u = 0; u < U; ++u) stencil_in<double, M, G>(g, c[u], p.l, L, in[u], vc, ax[u]);
         }
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-            const double d = bc[i] - ax[i];
-            acc[0] += d * d;
-            rc[i] = float(d * scale);
+        for (int u = 0; u < U; ++u) {
+            float rc[M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const double d = bc[u][i] - ax[u][i];
+                acc[0] += d * d;
+                rc[i] = float(d * scale);
+            }
+            st<float, M, V, NT>(r32, c[u].idx, c[u].ok, p.k0, g.nz, rc);
         }
-        st<float, M, V, NT>(r32, c.idx, c.ok, p.k0, g.nz, rc);
     }
 }
 
-template <int M, bool V, bool G, bool NT, bool W>
+template <int M, bool V, bool G, bool NT, bool W, int U = 1, bool JS = false>
 __device__ __forceinline__ void residual64_dev(const ColArgs& a, int64_t t)
 {
     int64_t rhs, blk;
@@ -637,8 +648,8 @@ __device__ __forceinline__ void residual64_dev(const ColArgs& a, int64_t t)
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[1] = {0.0};
-    if (a.x0_zero) residual64_body<M, V, true, G, NT, W>(a, s, rhs, blk, acc);
-    else residual64_body<M, V, false, G, NT, W>(a, s, rhs, blk, acc);
+    if (a.x0_zero) residual64_body<M, V, true, G, NT, W, U, JS>(a, s, rhs, blk, acc);
+    else residual64_body<M, V, false, G, NT, W, U, JS>(a, s, rhs, blk, acc);
     double tot[1];
     if (publish<1>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
                        &s->ticket, a.red_mode, tot)) {
@@ -650,10 +661,10 @@ __device__ __forceinline__ void residual64_dev(const ColArgs& a, int64_t t)
     }
 }
 
-template <int M, bool V, bool G, bool NT, bool W>
+template <int M, bool V, bool G, bool NT, bool W, int U, bool JS>
 __global__ __launch_bounds__(kBlock) void k_residual64(ColArgs a)
 {
-    residual64_dev<M, V, G, NT, W>(a, xcd_remap(blockIdx.x, gridDim.x));
+    residual64_dev<M, V, G, NT, W, U, JS>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Refinement update: x64 += (u32 + alpha p32) / scale, u32 being the inner
@@ -813,8 +824,11 @@ const void* main_func_m(Kind kind, bool js)
             return reinterpret_cast<const void*>(&k_true_residual<M, V, G, NT, W>);
         return nullptr;
     case Kind::Residual64:
-        if constexpr (sizeof(T) == 8)
-            return reinterpret_cast<const void*>(&k_residual64<M, V, G, NT, W>);
+        if constexpr (sizeof(T) == 8) {
+            if (kJs && js)
+                return reinterpret_cast<const void*>(&k_residual64<M, V, G, NT, W, kStepResidual, kJs>);
+            return reinterpret_cast<const void*>(&k_residual64<M, V, G, NT, W, kStepResidual, false>);
+        }
         return nullptr;
     case Kind::Update64:
         if constexpr (sizeof(T) == 8)
