@@ -119,18 +119,57 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(ColArgs a)
         T acc[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[i] = T(0);
-        // two children at a time: all four at once held 137 VGPRs (3 waves
-        // per SIMD) and ran 1 % slower over the V-cycle
-#pragma unroll 2
-        for (int child = 0; child < 4; ++child) {
-            const Col c = make_col_ij<G>(gf, 2 * cp.i + (child >> 1), 2 * cp.j + (child & 1),
-                                         cp.ok, a.hgeo2);
-            T zf[M], az[M], rf[M];
-            ld<T, M, V>(z, c.idx, c.ok, p.k0, gf.nz, zf);
-            stencil<T, M, V, G>(gf, c, p.l, L, p.k0, z, zf, vc, az);
-            ld<T, M, V, NT>(r, c.idx, c.ok, p.k0, gf.nz, rf);
+        if constexpr (M * sizeof(T) <= 16) {   // one 16-byte chunk per lane and vector
+            // the 2x2 children (child = 2 di + dj) and their z: a child's
+            // neighbours towards its siblings are those siblings (a coarse
+            // level has at least 4 cells per direction), so besides them only
+            // the eight outer neighbours are loaded: 12 columns of z, not 20
+            Col c[4];
+            T zf[4][M];
 #pragma unroll
-            for (int i = 0; i < M; ++i) acc[i] += rf[i] - az[i];
+            for (int ch = 0; ch < 4; ++ch) {
+                c[ch] = make_col_ij<G>(gf, 2 * cp.i + (ch >> 1), 2 * cp.j + (ch & 1), cp.ok,
+                                       a.hgeo2);
+                ld<T, M, V>(z, c[ch].idx, c[ch].ok, p.k0, gf.nz, zf[ch]);
+            }
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) {
+                const int di = ch >> 1, dj = ch & 1;
+                T az[M], rf[M];
+                stencil_nb<T, M, G>(gf, c[ch], p.l, L, zf[ch], vc,
+                                    [&](int dir, int64_t col, bool ok, T (&o)[M]) {
+                                        // direction 0..3: i-1, i+1, j-1, j+1
+                                        const int sib = dir == 0 ? (di == 1 ? ch - 2 : -1)
+                                                      : dir == 1 ? (di == 0 ? ch + 2 : -1)
+                                                      : dir == 2 ? (dj == 1 ? ch - 1 : -1)
+                                                                 : (dj == 0 ? ch + 1 : -1);
+                                        if (sib >= 0) {
+#pragma unroll
+                                            for (int i = 0; i < M; ++i) o[i] = zf[sib][i];
+                                        } else {
+                                            ld<T, M, V>(z, col, ok, p.k0, gf.nz, o);
+                                        }
+                                    },
+                                    az);
+                ld<T, M, V, NT>(r, c[ch].idx, c[ch].ok, p.k0, gf.nz, rf);
+#pragma unroll
+                for (int i = 0; i < M; ++i) acc[i] += rf[i] - az[i];
+            }
+        } else {
+            // two children at a time, each loading its own neighbours (with
+            // more levels per lane the shared form above holds too many
+            // registers: all four children at once held 137 VGPRs)
+#pragma unroll 2
+            for (int ch = 0; ch < 4; ++ch) {
+                const Col c = make_col_ij<G>(gf, 2 * cp.i + (ch >> 1), 2 * cp.j + (ch & 1),
+                                             cp.ok, a.hgeo2);
+                T zf[M], az[M], rf[M];
+                ld<T, M, V>(z, c.idx, c.ok, p.k0, gf.nz, zf);
+                stencil<T, M, V, G>(gf, c, p.l, L, p.k0, z, zf, vc, az);
+                ld<T, M, V, NT>(r, c.idx, c.ok, p.k0, gf.nz, rf);
+#pragma unroll
+                for (int i = 0; i < M; ++i) acc[i] += rf[i] - az[i];
+            }
         }
         st<T, M, V>(rc_out, cp.idx, cp.ok, p.k0, gc.nz, acc);
     }
