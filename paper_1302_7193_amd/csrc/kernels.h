@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_init(ColArgs a)
 // kernel wrote it, or b is r itself), or, with the line preconditioner
 // (ColArgs::zswap), the second launch reads b again.
 // W: one column per wavefront (L = 64, column index scalar).
-template <typename T, int M, bool V, bool FIRST, bool G, bool NT, bool W>
+template <typename T, int M, bool V, bool FIRST, bool G, bool NT, bool W, bool CZ = false>
 __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s, int64_t rhs,
                                                 int64_t blk, double (&acc)[2])
 {
@@ -265,11 +265,13 @@ __device__ __forceinline__ void fused_prec_body(const ColArgs& a, SolverState* s
         line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, rc, zc);
 #pragma unroll
         for (int i = 0; i < M; ++i) acc[1] += double(rc[i]) * double(zc[i]);
-        st<T, M, V, NT>(z, c.idx, c.ok, p.k0, g.nz, zc);
+        // CZ: z without the nontemporal hint (ColArgs::cache_z): kernel A
+        // reads it next
+        st<T, M, V, NT && !CZ>(z, c.idx, c.ok, p.k0, g.nz, zc);
     }
 }
 
-template <typename T, int M, bool V, bool G, bool NT, bool W>
+template <typename T, int M, bool V, bool G, bool NT, bool W, bool CZ = false>
 __device__ __forceinline__ void fused_prec_dev(const ColArgs& a, int64_t t)
 {
     int64_t rhs, blk;
@@ -277,8 +279,8 @@ __device__ __forceinline__ void fused_prec_dev(const ColArgs& a, int64_t t)
     SolverState* s = a.st + rhs;
     if (s->flag != kRunning) return;
     double acc[2] = {0.0, 0.0};
-    if (s->iter == 0) fused_prec_body<T, M, V, true, G, NT, W>(a, s, rhs, blk, acc);
-    else fused_prec_body<T, M, V, false, G, NT, W>(a, s, rhs, blk, acc);
+    if (s->iter == 0) fused_prec_body<T, M, V, true, G, NT, W, CZ>(a, s, rhs, blk, acc);
+    else fused_prec_body<T, M, V, false, G, NT, W, CZ>(a, s, rhs, blk, acc);
     double tot[2];
     if (publish<2>(acc, a.part + rhs * a.blocks_per_rhs * kRedSlots, blk, a.blocks_per_rhs,
                    &s->ticket, a.red_mode, tot)) {
@@ -286,10 +288,10 @@ __device__ __forceinline__ void fused_prec_dev(const ColArgs& a, int64_t t)
     }
 }
 
-template <typename T, int M, bool V, bool G, bool NT, bool W>
+template <typename T, int M, bool V, bool G, bool NT, bool W, bool CZ>
 __global__ __launch_bounds__(kBlock) void k_fused_prec(ColArgs a)
 {
-    fused_prec_dev<T, M, V, G, NT, W>(a, xcd_remap(blockIdx.x, gridDim.x));
+    fused_prec_dev<T, M, V, G, NT, W, CZ>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Kernel A (Alg. InterleavedApply): u += alpha p; p = z + beta p;
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(ColArgs a)
 // its loads need not wait for the solver flag: the flag (set only for a
 // right-hand side of a batch that is already done) is read alongside them
 // and checked before anything is stored.
-template <typename T, int M, bool V, bool G, bool NT, bool W, int U>
+template <typename T, int M, bool V, bool G, bool NT, bool W, int U, bool CZ>
 __global__ __launch_bounds__(kBlock) void k_fused_prec_first(ColArgs a)
 {
     const Geom& g = a.g;
@@ -427,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_prec_first(ColArgs a)
         for (int u = 0; u < U; ++u) {
 #pragma unroll
             for (int i = 0; i < M; ++i) acc[1] += double(rc[u][i]) * double(zc[u][i]);
-            st<T, M, V, NT>(z, c[u].idx, c[u].ok, p.k0, g.nz, zc[u]);
+            st<T, M, V, NT && !CZ>(z, c[u].idx, c[u].ok, p.k0, g.nz, zc[u]);   // CZ: fused_prec_body
         }
     }
     if (flag != kRunning) return;
@@ -797,7 +799,7 @@ inline const void* finalize_func(Kind kind)
 }
 
 template <typename T, int M, bool V, bool G, bool NT, bool W>
-const void* main_func_m(Kind kind, bool js)
+const void* main_func_m(Kind kind, bool js, bool cz)
 {
     // columns sharing y-neighbours: one column per wavefront and n_y a
     // multiple of the step (the caller's js)
@@ -809,14 +811,18 @@ const void* main_func_m(Kind kind, bool js)
     case Kind::Precond:
         return reinterpret_cast<const void*>(&k_precond<T, M, V, G, NT, W, kStepPrecond>);
     case Kind::FusedPrecFirst:
-        return reinterpret_cast<const void*>(&k_fused_prec_first<T, M, V, G, NT, W, kStepFirstB>);
+        if (NT && cz)
+            return reinterpret_cast<const void*>(&k_fused_prec_first<T, M, V, G, NT, W, kStepFirstB, true>);
+        return reinterpret_cast<const void*>(&k_fused_prec_first<T, M, V, G, NT, W, kStepFirstB, false>);
     case Kind::FusedApplyFirst:
         if (kJs && js)
             return reinterpret_cast<const void*>(&k_fused_apply_first<T, M, V, G, NT, W, kStepFirstA, kJs>);
         return reinterpret_cast<const void*>(&k_fused_apply_first<T, M, V, G, NT, W, kStepFirstA, false>);
     case Kind::InitFull: return reinterpret_cast<const void*>(&k_init<T, M, V, false, G, NT, W>);
     case Kind::InitZero: return reinterpret_cast<const void*>(&k_init<T, M, V, true, false, NT, W>);
-    case Kind::FusedPrec: return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G, NT, W>);
+    case Kind::FusedPrec:
+        if (NT && cz) return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G, NT, W, true>);
+        return reinterpret_cast<const void*>(&k_fused_prec<T, M, V, G, NT, W, false>);
     case Kind::FusedApply: return reinterpret_cast<const void*>(&k_fused_apply<T, M, V, G, NT, W>);
     case Kind::Fixup: return reinterpret_cast<const void*>(&k_fixup<T, M, V, NT, W>);
     case Kind::TrueResidual:
@@ -839,16 +845,16 @@ const void* main_func_m(Kind kind, bool js)
 }
 
 template <typename T, int M, bool V, bool G>
-const void* main_func_n(Kind kind, bool nt, bool w, bool js)
+const void* main_func_n(Kind kind, bool nt, bool w, bool js, bool cz)
 {
     // the nontemporal variants exist only where the hint is used: one
     // 16-byte chunk per lane and vector; one column per wavefront: L = 64
     if constexpr (M * sizeof(T) == 16) {
-        if (w) return nt ? main_func_m<T, M, V, G, true, true>(kind, js) : main_func_m<T, M, V, G, false, true>(kind, js);
-        return nt ? main_func_m<T, M, V, G, true, false>(kind, js) : main_func_m<T, M, V, G, false, false>(kind, js);
+        if (w) return nt ? main_func_m<T, M, V, G, true, true>(kind, js, cz) : main_func_m<T, M, V, G, false, true>(kind, js, cz);
+        return nt ? main_func_m<T, M, V, G, true, false>(kind, js, cz) : main_func_m<T, M, V, G, false, false>(kind, js, cz);
     } else {
-        if (w) return main_func_m<T, M, V, G, false, true>(kind, js);
-        return main_func_m<T, M, V, G, false, false>(kind, js);
+        if (w) return main_func_m<T, M, V, G, false, true>(kind, js, cz);
+        return main_func_m<T, M, V, G, false, false>(kind, js, cz);
     }
 }
 
@@ -861,8 +867,8 @@ const void* main_func_v(Kind kind, const ColArgs& a, bool nt)
     const bool w = a.L == kWave;
     const bool js = w && a.g.ny % step_of(kind) == 0;
     if (a.hgeo)
-        return vec ? main_func_n<T, M, true, true>(kind, nt, w, js) : main_func_n<T, M, false, true>(kind, nt, w, js);
-    return vec ? main_func_n<T, M, true, false>(kind, nt, w, js) : main_func_n<T, M, false, false>(kind, nt, w, js);
+        return vec ? main_func_n<T, M, true, true>(kind, nt, w, js, a.cache_z != 0) : main_func_n<T, M, false, true>(kind, nt, w, js, a.cache_z != 0);
+    return vec ? main_func_n<T, M, true, false>(kind, nt, w, js, a.cache_z != 0) : main_func_n<T, M, false, false>(kind, nt, w, js, a.cache_z != 0);
 }
 
 template <typename T>
@@ -910,6 +916,7 @@ int column_launches(Kind kind, const ColArgs& a0, int64_t batch, KernelLaunch ou
         const int64_t tiles = (a.g.nh + cols - 1) / cols;
         a.blocks_per_rhs = std::max<int64_t>(1, std::min(a.blocks_per_rhs, (tiles + U - 1) / U));
     }
+    a.cache_z = a.g.n * batch * (int64_t)sizeof(T) <= kCacheZBytes ? 1 : 0;
     out[0].func = main_func<T>(kind, a, batch);
     if (!out[0].func) return 0;
     out[0].grid = dim3((unsigned)(a.blocks_per_rhs * batch));
