@@ -252,13 +252,15 @@ def hbm_probe(pcg, torch, n=1 << 25, reps=10):
     """The library's streaming kernel (pcg_stream_probe) with the access mixes
     of kernel A (4 vectors in / 3 out), kernel B (2 / 2) and a copy (1 / 1),
     on vectors of the main workload's size (n FP64 values): the best over
-    workgroup counts, with and without the nontemporal hint.  The practical
-    ceiling beside the 8 TB/s peak."""
+    workgroup counts and the probe's nontemporal patterns (none, every
+    access, all but the first vector's reads -- kernel A's -- and all but the
+    last vector's writes -- kernel B's).  The practical ceiling beside the
+    8 TB/s peak."""
     vecs = [torch.full((n,), 1.0 + k, dtype=torch.float64, device="cuda") for k in range(7)]
     out = {}
     for name, nr, nw in (("copy", 1, 1), ("kernel_b_mix", 2, 2), ("kernel_a_mix", 4, 3)):
         best = None
-        for nt in (False, True):
+        for nt in (0, 1, 2, 3):
             for blocks in (4096, 16384, 65536):
                 ms = cuda_time(torch, lambda: pcg.pcg_stream_probe(vecs[:nr], vecs[nr:nr + nw],
                                                                    nt, blocks), reps)

@@ -416,8 +416,11 @@ void pcg_server_destroy(pcg_server *s);
  * measures what a kernel that only streams attains, the practical ceiling
  * beside that peak.  One kernel streams n_read (1..4) vectors in and n_write
  * (1..3) out, each `bytes` long (a positive multiple of 16), 16 bytes per
- * lane and access, with the nontemporal hint on every access when
- * nontemporal = 1.  vectors: host array of n_read + n_write device pointers
+ * lane and access, with the nontemporal hint on no access (nontemporal = 0),
+ * on every access (1), on every access but the reads of the first vector
+ * (2: kernel A's pattern, whose stencil input is re-read as neighbour
+ * columns) or on every access but the writes of the last vector (3: kernel
+ * B's, whose z the next kernel reads).  vectors: host array of n_read + n_write device pointers
  * (16-byte aligned, caller-owned), the read ones first; a written vector may
  * not overlap any other.  Written vector k receives sum_i v_i * 2^-(i+k)
  * elementwise.  blocks: workgroups (0: 16384), each streaming one contiguous

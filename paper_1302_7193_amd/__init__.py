@@ -363,10 +363,12 @@ def pcg_csr_build(p: Problem, dtype: int, buf, stream=None) -> int:
                   "pcg_csr_build")
 
 
-def pcg_stream_probe(reads, writes, nontemporal: bool = True, blocks: int = 0, stream=None) -> int:
+def pcg_stream_probe(reads, writes, nontemporal: int = 1, blocks: int = 0, stream=None) -> int:
     """HBM probe: stream the CUDA tensors `reads` in and `writes` out (all of
     one byte size); written tensor k receives sum_i reads[i] * 2^-(i+k)
-    (as FP64 pairs).  Asynchronous on `stream`."""
+    (as FP64 pairs).  nontemporal: 0 none, 1 every access, 2 all but the
+    first vector's reads, 3 all but the last vector's writes (a bool is 0 or
+    1).  Asynchronous on `stream`."""
     vecs = list(reads) + list(writes)
     if not vecs:
         raise ValueError("no vectors")
@@ -375,7 +377,7 @@ def pcg_stream_probe(reads, writes, nontemporal: bool = True, blocks: int = 0, s
         if _buf(t, nbytes, "probe vector") and t.numel() * t.element_size() != nbytes:
             raise ValueError("probe vectors must have one byte size")
     arr = (ctypes.c_void_p * len(vecs))(*[t.data_ptr() for t in vecs])
-    return _check(_lib.pcg_stream_probe(len(reads), len(writes), arr, nbytes, int(bool(nontemporal)),
+    return _check(_lib.pcg_stream_probe(len(reads), len(writes), arr, nbytes, int(nontemporal),
                                         blocks, _stream(stream)), "pcg_stream_probe")
 
 

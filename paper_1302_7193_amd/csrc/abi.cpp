@@ -723,9 +723,9 @@ pcg_status pcg_stream_probe(int32_t n_read, int32_t n_write, void* const* vector
                             int32_t nontemporal, int64_t blocks, void* stream)
 {
     if (n_read < 1 || n_read > 4 || n_write < 1 || n_write > 3 || !vectors || bytes == 0 ||
-        bytes % 16 != 0 || (nontemporal != 0 && nontemporal != 1) || blocks < 0) {
+        bytes % 16 != 0 || nontemporal < 0 || nontemporal > 3 || blocks < 0) {
         set_error("pcg_stream_probe: 1..4 read and 1..3 written vectors, bytes a positive "
-                  "multiple of 16, nontemporal 0 or 1, blocks >= 0");
+                  "multiple of 16, nontemporal 0..3, blocks >= 0");
         return PCG_E_INVALID;
     }
     const int nv = n_read + n_write;
@@ -743,7 +743,7 @@ pcg_status pcg_stream_probe(int32_t n_read, int32_t n_write, void* const* vector
             }
         }
     }
-    const hipError_t e = stream_probe(n_read, n_write, vectors, bytes, nontemporal != 0,
+    const hipError_t e = stream_probe(n_read, n_write, vectors, bytes, nontemporal,
                                       blocks > 0 ? blocks : kDefaultCap,
                                       static_cast<hipStream_t>(stream));
     if (e != hipSuccess) {

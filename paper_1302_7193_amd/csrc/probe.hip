@@ -5,8 +5,12 @@
 // B reads two and writes two; a plain copy reads one and writes one.  The
 // probe streams n_read vectors in and n_write out, 16 bytes per lane and
 // access, with the workgroup-contiguous ranges the column kernels use, two
-// 256-thread strips in flight per vector, and (optionally) the nontemporal
-// hint on every access.  It does no other arithmetic than the combination
+// 256-thread strips in flight per vector, and the nontemporal hint on no
+// access, on every access, or on every access but the reads of the first
+// vector (kernel A's pattern: its stencil input is re-read as neighbour
+// columns) or the writes of the last (kernel B's: the next kernel reads z).
+// The pattern matters: kernel A's mix ran at 5.6 TB/s with every access
+// nontemporal and at 6.5-7.0 TB/s with its own pattern.  It does no other arithmetic than the combination
 // that keeps the loads alive: w_k = sum_i c_ik v_i with fixed coefficients.
 #include <hip/hip_runtime.h>
 
@@ -47,7 +51,9 @@ __device__ __forceinline__ void pst(double2* p, double2 v)
 constexpr int kProbeStrips = 2;   // 256-thread strips in flight per vector
 
 // Output k is sum_i v_i * 2^-(i + k): a fixed linear map the tests rebuild.
-template <int NR, int NW, bool NT>
+// MODE: 0 no hint, 1 every access, 2 all but the first vector's reads,
+// 3 all but the last vector's writes.
+template <int NR, int NW, int MODE>
 __global__ __launch_bounds__(kBlock) void k_stream_probe(ProbeArgs a)
 {
     const int64_t per = (a.n16 + gridDim.x - 1) / gridDim.x;
@@ -59,7 +65,12 @@ __global__ __launch_bounds__(kBlock) void k_stream_probe(ProbeArgs a)
         for (int u = 0; u < kProbeStrips; ++u) {
             const int64_t i = base + u * kBlock + threadIdx.x;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) v[u][r] = i < i1 ? pld<NT>(a.in[r] + i) : double2{0.0, 0.0};
+            for (int r = 0; r < NR; ++r) {
+                if (MODE == 1 || (MODE == 2 && r > 0) || MODE == 3)
+                    v[u][r] = i < i1 ? pld<true>(a.in[r] + i) : double2{0.0, 0.0};
+                else
+                    v[u][r] = i < i1 ? pld<false>(a.in[r] + i) : double2{0.0, 0.0};
+            }
         }
 #pragma unroll
         for (int u = 0; u < kProbeStrips; ++u) {
@@ -74,33 +85,41 @@ __global__ __launch_bounds__(kBlock) void k_stream_probe(ProbeArgs a)
                     s.x += c * v[u][r].x;
                     s.y += c * v[u][r].y;
                 }
-                pst<NT>(a.out[w] + i, s);
+                if (MODE == 1 || MODE == 2 || (MODE == 3 && w < NW - 1))
+                    pst<true>(a.out[w] + i, s);
+                else
+                    pst<false>(a.out[w] + i, s);
             }
         }
     }
 }
 
 template <int NR, int NW>
-const void* probe_func(bool nt)
+const void* probe_func(int mode)
 {
-    return nt ? reinterpret_cast<const void*>(&k_stream_probe<NR, NW, true>)
-              : reinterpret_cast<const void*>(&k_stream_probe<NR, NW, false>);
+    switch (mode) {
+    case 0: return reinterpret_cast<const void*>(&k_stream_probe<NR, NW, 0>);
+    case 1: return reinterpret_cast<const void*>(&k_stream_probe<NR, NW, 1>);
+    case 2: return reinterpret_cast<const void*>(&k_stream_probe<NR, NW, 2>);
+    case 3: return reinterpret_cast<const void*>(&k_stream_probe<NR, NW, 3>);
+    default: return nullptr;
+    }
 }
 
 template <int NR>
-const void* probe_func_r(int nw, bool nt)
+const void* probe_func_r(int nw, int mode)
 {
     switch (nw) {
-    case 1: return probe_func<NR, 1>(nt);
-    case 2: return probe_func<NR, 2>(nt);
-    case 3: return probe_func<NR, 3>(nt);
+    case 1: return probe_func<NR, 1>(mode);
+    case 2: return probe_func<NR, 2>(mode);
+    case 3: return probe_func<NR, 3>(mode);
     default: return nullptr;
     }
 }
 
 }  // namespace
 
-hipError_t stream_probe(int n_read, int n_write, void* const* vectors, size_t bytes, bool nt,
+hipError_t stream_probe(int n_read, int n_write, void* const* vectors, size_t bytes, int nt,
                         int64_t blocks, hipStream_t s)
 {
     ProbeArgs a{};

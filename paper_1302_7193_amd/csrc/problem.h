@@ -124,7 +124,7 @@ private:
 };
 
 // HBM probe (probe.hip): n_read vectors streamed in, n_write out.
-hipError_t stream_probe(int n_read, int n_write, void* const* vectors, size_t bytes, bool nt,
+hipError_t stream_probe(int n_read, int n_write, void* const* vectors, size_t bytes, int nt,
                         int64_t blocks, hipStream_t s);
 
 }  // namespace pcg

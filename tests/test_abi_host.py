@@ -152,7 +152,8 @@ def test_stream_probe_rejects_bad_arguments_before_touching_a_device(lib):
     buf = (ctypes.c_void_p * 7)(*[0x10000 * (k + 1) for k in range(7)])
     for nr, nw, nbytes, nt, blocks in ((0, 1, 1024, 1, 0), (5, 1, 1024, 1, 0), (1, 0, 1024, 1, 0),
                                        (1, 4, 1024, 1, 0), (1, 1, 0, 1, 0), (1, 1, 1000, 1, 0),
-                                       (1, 1, 1024, 2, 0), (1, 1, 1024, 1, -1)):
+                                       (1, 1, 1024, 4, 0), (1, 1, 1024, -1, 0),
+                                       (1, 1, 1024, 1, -1)):
         assert f(nr, nw, buf, nbytes, nt, blocks, None) == pcg.PCG_E_INVALID, (nr, nw, nbytes)
     assert f(1, 1, None, 1024, 1, 0, None) == pcg.PCG_E_INVALID
     bad = (ctypes.c_void_p * 2)(0x10000, 0x20008)            # misaligned

@@ -16,7 +16,7 @@ import synth_inputs as si  # noqa: E402
 
 
 @pytest.mark.parametrize("nr,nw", [(1, 1), (2, 2), (4, 3), (3, 1)])
-@pytest.mark.parametrize("nt", [True, False])
+@pytest.mark.parametrize("nt", [0, 1, 2, 3])
 @pytest.mark.parametrize("blocks", [0, 3])
 def test_probe_writes_its_linear_map(nr, nw, nt, blocks):
     n = 2 * 12345                       # FP64 values: 12345 16-byte elements
