@@ -94,13 +94,15 @@ def solve_roofline(bytes_per_solve, ms_per_solve):
 
 KERNEL_PATTERN = {
     "fused_apply": r"k_fused_apply<double, \d+, (true|false), false, (true|false), (true|false)>",
-    "fused_prec": r"k_fused_prec<double, \d+, (true|false), false, (true|false), (true|false)>",
+    "fused_prec": r"k_fused_prec<double, \d+, (true|false), false, (true|false), (true|false), "
+                  r"(true|false)>",
     # the first launch of each in a solve runs its own kernel
     "fused_apply_first": r"k_fused_apply_first<double, \d+, (true|false), false, (true|false), "
                          r"(true|false), \d+, (true|false)>",
     "fused_prec_first": r"k_fused_prec_first<double, \d+, (true|false), false, (true|false), "
-                        r"(true|false), \d+>"}
+                        r"(true|false), \d+, (true|false)>"}
 STREAM_BYTES = 64 << 20       # vectors at least this large use nontemporal accesses
+CACHE_Z_BYTES = 384 << 20     # ... and kernel B stores z cached up to this size
 
 
 def kernel_symbol(kernel, lanes_per_column, n, nz, elem=8, stretched=False, nrhs=1):
@@ -115,8 +117,11 @@ def kernel_symbol(kernel, lanes_per_column, n, nz, elem=8, stretched=False, nrhs
     nt = n * nrhs * elem >= STREAM_BYTES and m * elem == 16
     t = "double" if elem == 8 else "float"
     b = lambda v: str(v).lower()
-    return "k_%s<%s, %d, %s, %s, %s, %s>" % (kernel, t, m, b(vec), b(stretched), b(nt),
-                                             b(lanes_per_column == 64))
+    sym = "k_%s<%s, %d, %s, %s, %s, %s" % (kernel, t, m, b(vec), b(stretched), b(nt),
+                                           b(lanes_per_column == 64))
+    if kernel == "fused_prec":   # z stored cached (nontemporal instances only)
+        sym += ", %s" % b(nt and n * nrhs * elem <= CACHE_Z_BYTES)
+    return sym + ">"
 
 
 def log(*a):
@@ -147,7 +152,8 @@ def measured_traffic(kernel: str, workload_tag: str, symbol: str):
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-    # a first-launch kernel's name carries two more template arguments
+    # a first-launch kernel's name carries more template arguments (its step,
+    # and kernel B's cache policy for z, which follows the general kernel's)
     stored = kv.get("kernel", "")
     if kv.get("kernel_source_sha256_16") != kernel_source_hash() or not (
             stored == symbol or (kernel.endswith("_first") and stored.startswith(symbol[:-1] + ","))):
@@ -163,8 +169,15 @@ def solve_mean_traffic(kernel, iterations, symbol):
     solve of `iterations` iterations, as the event timings are: the first
     launch (its own kernel) and the others (A: k - 1 of them, B: k), each
     from its committed counter summary; None unless both are current."""
+    args = symbol[symbol.index("<") + 1:-1].split(", ")
+    head, cz = args[:6], args[6:]      # kernel B: its z cache policy last
     first = measured_traffic(kernel + "_first", "512x512x128",
-                             symbol.replace("k_" + kernel + "<", "k_" + kernel + "_first<"))
+                             "k_%s_first<%s>" % (kernel, ", ".join(head)))
+    if first is not None and cz:
+        path = os.path.join(ROOT, "profiles", "traffic_%s_first_512x512x128.txt" % kernel)
+        stored = [ln.split("=", 1)[1].strip() for ln in open(path) if ln.startswith("kernel =")]
+        if not stored or not stored[0].endswith(", %s>" % cz[0]):
+            first = None
     rest = measured_traffic(kernel, "512x512x128", symbol)
     if first is None or rest is None:
         return None

@@ -33,7 +33,10 @@ def test_kernel_symbol_for_launch_shapes():
             == "k_fused_apply<double, 2, true, false, true, true>")
     # FP32 at 32 lanes: 4 levels per lane = 16 bytes, streamed
     assert (bench.kernel_symbol("fused_prec", 32, 1024 * 1024 * 128, 128, elem=4)
-            == "k_fused_prec<float, 4, true, false, true, false>")
+            == "k_fused_prec<float, 4, true, false, true, false, false>")
+    # kernel B stores z cached when the z vector takes at most 384 MiB
+    assert (bench.kernel_symbol("fused_prec", 64, N, 128)
+            == "k_fused_prec<double, 2, true, false, true, true, true>")
     # small vectors stay in the caches; a ragged column has no vector path
     assert (bench.kernel_symbol("fused_apply", 8, 64 * 64 * 33, 33)
             == "k_fused_apply<double, 8, false, false, false, false>")
