@@ -111,7 +111,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_first(ColArgs a)
 // One later half-sweep over the columns of colour RED (reads r = a.in0 and
 // the other colour of z = a.io2, writes this colour of z).  FINAL (red):
 // R = <r,r>, kappa = <r,z> over all columns, exit test, beta.
-template <typename T, int M, bool V, bool G, bool RED, bool FINAL, bool NT, bool W>
+// CZ: z stored without the nontemporal hint (ColArgs::cache_z), in the black
+// half-sweep and the final red one: kernel A reads z next.
+template <typename T, int M, bool V, bool G, bool RED, bool FINAL, bool NT, bool W,
+          bool CZ = false>
 __global__ __launch_bounds__(kBlock) void k_rb_sweep(ColArgs a)
 {
     const Geom& g = a.g;
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(ColArgs a)
 #pragma unroll
             for (int i = 0; i < M; ++i) h[i] = rc[i] - h[i];
             line_solve<T, M, V, G>(g, c, p.l, L, p.k0, lu, sc, h, zc);
-            st<T, M, V, NT>(z, c.idx, c.ok, p.k0, g.nz, zc);
+            st<T, M, V, NT && !CZ>(z, c.idx, c.ok, p.k0, g.nz, zc);
         } else {
             ld<T, M, V>(z, c.idx, c.ok, p.k0, g.nz, zc);
         }
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(ColArgs a)
 }
 
 template <typename T, int M, bool V, bool G, bool NT, bool W>
-const void* rb_func_m(Kind kind)
+const void* rb_func_m(Kind kind, bool cz)
 {
     switch (kind) {
     case Kind::RbFirst:
@@ -173,25 +176,27 @@ const void* rb_func_m(Kind kind)
     case Kind::RbFirstFused:
         return reinterpret_cast<const void*>(&k_rb_first<T, M, V, G, true, NT, W>);
     case Kind::RbBlack:
+        if (NT && cz) return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, false, false, NT, W, true>);
         return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, false, false, NT, W>);
     case Kind::RbRed:
         return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, true, false, NT, W>);
     case Kind::RbRedFinal:
+        if (NT && cz) return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, true, true, NT, W, true>);
         return reinterpret_cast<const void*>(&k_rb_sweep<T, M, V, G, true, true, NT, W>);
     default: return nullptr;
     }
 }
 
 template <typename T, int M, bool V, bool G>
-const void* rb_func_n(Kind kind, bool nt, bool w)
+const void* rb_func_n(Kind kind, bool nt, bool w, bool cz)
 {
     // the nontemporal variants exist only where the hint is used: one
     // 16-byte chunk per lane and vector
     if constexpr (M * sizeof(T) == 16) {
-        if (w) return nt ? rb_func_m<T, M, V, G, true, true>(kind) : rb_func_m<T, M, V, G, false, true>(kind);
-        return nt ? rb_func_m<T, M, V, G, true, false>(kind) : rb_func_m<T, M, V, G, false, false>(kind);
+        if (w) return nt ? rb_func_m<T, M, V, G, true, true>(kind, cz) : rb_func_m<T, M, V, G, false, true>(kind, cz);
+        return nt ? rb_func_m<T, M, V, G, true, false>(kind, cz) : rb_func_m<T, M, V, G, false, false>(kind, cz);
     } else {
-        return w ? rb_func_m<T, M, V, G, false, true>(kind) : rb_func_m<T, M, V, G, false, false>(kind);
+        return w ? rb_func_m<T, M, V, G, false, true>(kind, cz) : rb_func_m<T, M, V, G, false, false>(kind, cz);
     }
 }
 
@@ -201,8 +206,8 @@ const void* rb_func_v(Kind kind, const ColArgs& a, bool nt)
     const bool vec = (a.g.nz % M == 0) && ((M * sizeof(T)) % 16 == 0) &&
                      ((a.g.nz * sizeof(T)) % 16 == 0);
     const bool w = a.L == kWave;
-    if (a.hgeo) return vec ? rb_func_n<T, M, true, true>(kind, nt, w) : rb_func_n<T, M, false, true>(kind, nt, w);
-    return vec ? rb_func_n<T, M, true, false>(kind, nt, w) : rb_func_n<T, M, false, false>(kind, nt, w);
+    if (a.hgeo) return vec ? rb_func_n<T, M, true, true>(kind, nt, w, a.cache_z != 0) : rb_func_n<T, M, false, true>(kind, nt, w, a.cache_z != 0);
+    return vec ? rb_func_n<T, M, true, false>(kind, nt, w, a.cache_z != 0) : rb_func_n<T, M, false, false>(kind, nt, w, a.cache_z != 0);
 }
 
 }  // namespace
