@@ -8,6 +8,7 @@
 // closed form from the number of neighbours of each cell, so the assembly
 // needs no scan.
 #include <algorithm>
+#include <type_traits>
 
 #include "csr_layout.h"
 #include "device_common.h"
@@ -75,69 +76,72 @@ __global__ __launch_bounds__(kBlock) void k_csr_build(Geom g, const double* __re
     if (ip >= 0) put(ip * g.nz + k, d * wxp);
 }
 
-// y = A x from the CSR arrays.  Eight lanes share a row (a row has at most
-// seven entries): lane s of the group takes entry rowp[r] + s, so a
-// wavefront's loads of values and column indices cover the consecutive
-// entries of its eight rows in one coalesced sweep; the group adds its
-// products with two quad permutes and one swizzle across the group's halves.
-// Each wavefront takes kCsrGroups such row groups at a time, their loads
-// issued together (three dependent loads per row: offsets, entries, x).
-constexpr int kCsrLanes = 8;
-constexpr int kCsrGroups = 4;
+// y = A x from the CSR arrays, streamed through LDS (the CSR-stream scheme of
+// Greathouse and Daga, SC 2014).  A workgroup takes kCsrRows consecutive
+// rows; their entries are consecutive in the value and column arrays, so its
+// lanes read them with 16-byte loads in one coalesced sweep (from the
+// 16-byte boundary at or below the first entry), gather x for the entries of
+// the rows, and write the products to LDS.  After a barrier lane t adds the
+// products of row t in entry order and writes y.  Every load of the sweep is
+// issued before any gather: a row has at most seven entries, so the sweep's
+// length and the number of its steps per lane are bounded at compile time.
+constexpr int kCsrRows = kBlock;
+constexpr int kCsrMaxEntries = 7 * kCsrRows;
 
 template <typename T>
-__device__ __forceinline__ T group8_sum(T v)
-{
-    v += dpp_move<kQuadXor1>(v, T(0));
-    v += dpp_move<kQuadXor2>(v, T(0));
-    // xor 4: swizzle in bit mode (and 0x1f, or 0, xor 4) within each 32 lanes
-    constexpr int kXor4 = 0x1f | (4 << 10);
-    if constexpr (sizeof(T) == 8) {
-        const int64_t b = __builtin_bit_cast(int64_t, v);
-        const int lo = __builtin_amdgcn_ds_swizzle((int)b, kXor4);
-        const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), kXor4);
-        return v + __builtin_bit_cast(T, ((int64_t)hi << 32) | (int64_t)(uint32_t)lo);
-    } else {
-        return v + __builtin_bit_cast(T, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), kXor4));
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_csr_apply(int64_t n, const T* __restrict__ val,
+__global__ __launch_bounds__(kBlock) void k_csr_apply(int32_t n, const T* __restrict__ val,
                                                       const int32_t* __restrict__ col,
                                                       const int32_t* __restrict__ rowp,
                                                       const T* __restrict__ x, T* __restrict__ y)
 {
-    constexpr int kRowsPerWave = (kWave / kCsrLanes) * kCsrGroups;
-    const int lane = threadIdx.x & (kWave - 1), slot = lane & (kCsrLanes - 1);
-    const int64_t wave = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
-    for (int64_t r0 = wave * kRowsPerWave; r0 < n; r0 += nwaves * kRowsPerWave) {
-        int64_t r[kCsrGroups];
-        int32_t e[kCsrGroups], e1[kCsrGroups];
-        T v[kCsrGroups], xv[kCsrGroups];
-        int32_t c[kCsrGroups];
+    constexpr int V = 16 / sizeof(T);                        // entries per 16-byte load
+    constexpr int kSteps = (kCsrMaxEntries + V - 1 + kBlock * V - 1) / (kBlock * V);
+    using VT = std::conditional_t<sizeof(T) == 8, double2, float4>;
+    using CT = std::conditional_t<sizeof(T) == 8, int2, int4>;
+    __shared__ T prod[kCsrMaxEntries];
+    __shared__ int32_t off[kCsrRows + 1];
+    const int t = threadIdx.x;
+    const int32_t r0 = (int32_t)blockIdx.x * kCsrRows;
+    const int32_t rows = min(kCsrRows, n - r0);
+    const int32_t e0 = rowp[r0], e1 = rowp[r0 + rows];
+    if (t < rows) off[t] = rowp[r0 + t] - e0;
+    if (t == 0) off[rows] = e1 - e0;
+    // the sweep: [e0 rounded down to V, e1) in steps of kBlock * V entries;
+    // the arrays' sections are padded to 256 bytes, so a 16-byte load that
+    // starts below e1 stays inside its section
+    const int32_t a0 = e0 & ~(V - 1);
+    T v[kSteps][V];
+    int32_t c[kSteps][V];
 #pragma unroll
-        for (int u = 0; u < kCsrGroups; ++u) {
-            r[u] = r0 + u * (kWave / kCsrLanes) + lane / kCsrLanes;
-            const int64_t rr = r[u] < n ? r[u] : n - 1;
-            e[u] = rowp[rr] + slot;
-            e1[u] = r[u] < n ? rowp[rr + 1] : 0;
+    for (int s = 0; s < kSteps; ++s) {
+        const int32_t e = a0 + (s * kBlock + t) * V;
+        if (e < e1) {
+            const VT vv = *reinterpret_cast<const VT*>(val + e);
+            const CT cv = *reinterpret_cast<const CT*>(col + e);
+            if constexpr (V == 2) {
+                v[s][0] = vv.x; v[s][1] = vv.y;
+                c[s][0] = cv.x; c[s][1] = cv.y;
+            } else {
+                v[s][0] = vv.x; v[s][1] = vv.y; v[s][2] = vv.z; v[s][3] = vv.w;
+                c[s][0] = cv.x; c[s][1] = cv.y; c[s][2] = cv.z; c[s][3] = cv.w;
+            }
         }
+    }
 #pragma unroll
-        for (int u = 0; u < kCsrGroups; ++u) {
-            const bool in = e[u] < e1[u];
-            const int32_t ee = in ? e[u] : 0;
-            v[u] = in ? val[ee] : T(0);
-            c[u] = in ? col[ee] : 0;
+    for (int s = 0; s < kSteps; ++s) {
+        const int32_t e = a0 + (s * kBlock + t) * V;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            // entries outside the rows (before e0, at or after e1) are not
+            // this workgroup's; their column slots may be padding
+            if (e + q >= e0 && e + q < e1) prod[e + q - e0] = v[s][q] * x[c[s][q]];
         }
-#pragma unroll
-        for (int u = 0; u < kCsrGroups; ++u) xv[u] = x[c[u]];
-#pragma unroll
-        for (int u = 0; u < kCsrGroups; ++u) {
-            const T sum = group8_sum(v[u] * xv[u]);
-            if (slot == 0 && r[u] < n) y[r[u]] = sum;
-        }
+    }
+    __syncthreads();
+    if (t < rows) {
+        T sum = T(0);
+        for (int32_t e = off[t]; e < off[t + 1]; ++e) sum += prod[e];
+        y[r0 + t] = sum;
     }
 }
 
@@ -181,19 +185,20 @@ hipError_t csr_build(const Geom& g, const double* vert64, const double* hgeo, in
 hipError_t csr_apply(const Geom& g, int dtype, const void* buf, const void* x, void* y,
                      hipStream_t s)
 {
-    const int64_t rows_per_block = (int64_t)(kBlock / kCsrLanes) * kCsrGroups;
-    const int64_t blocks = std::min<int64_t>((g.n + rows_per_block - 1) / rows_per_block, 1 << 20);
-    const dim3 grid((unsigned)blocks), block(kBlock);
+    // n * 7 < 2^31 (checked when the problem is made): every row and entry
+    // index fits in 32 bits
+    const int32_t n = (int32_t)g.n;
+    const dim3 grid((unsigned)((n + kCsrRows - 1) / kCsrRows)), block(kBlock);
     void* b = const_cast<void*>(buf);
     if (dtype == PCG_F64) {
         double* v; int32_t *c, *r;
         sections<double>(g, b, v, c, r);
-        hipLaunchKernelGGL((k_csr_apply<double>), grid, block, 0, s, g.n, v, c, r,
+        hipLaunchKernelGGL((k_csr_apply<double>), grid, block, 0, s, n, v, c, r,
                            static_cast<const double*>(x), static_cast<double*>(y));
     } else {
         float* v; int32_t *c, *r;
         sections<float>(g, b, v, c, r);
-        hipLaunchKernelGGL((k_csr_apply<float>), grid, block, 0, s, g.n, v, c, r,
+        hipLaunchKernelGGL((k_csr_apply<float>), grid, block, 0, s, n, v, c, r,
                            static_cast<const float*>(x), static_cast<float*>(y));
     }
     return hipGetLastError();
