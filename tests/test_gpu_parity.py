@@ -388,6 +388,33 @@ def test_full_size_periodic_workload_sampled():
     assert true < 1.05e-8
 
 
+@pytest.mark.parametrize("dtype", [pcg.PCG_F64, pcg.PCG_F32])
+def test_full_size_csr_comparator(dtype):
+    """The CSR comparator at the benchmark's size (512 x 512 x 128 periodic,
+    131 072 workgroups of 256 rows): every row offset equals the oracle's
+    assembly and every output element the oracle's CSR product, within the
+    same bound as on the small grids."""
+    d, g, A, _ = _periodic_512()
+    p = pcg.Problem(d)
+    tdt, u = DT[dtype]
+    print("full-size csr", dtype, flush=True)
+    buf = torch.empty(pcg.pcg_csr_bytes(p, dtype), dtype=torch.uint8, device="cuda")
+    pcg.pcg_csr_build(p, dtype, buf)
+    x = cuda(si.uniform_pm1(23, p.n), tdt)
+    y = torch.empty_like(x)
+    pcg.pcg_csr_apply(p, dtype, buf, x, y)
+    torch.cuda.synchronize()
+    xr = x.double().cpu().numpy()
+    bound = 64 * u * oracle.CSR(A.n, A.row_ptr, A.col, np.abs(A.val)).matvec(np.abs(xr))
+    err = np.abs(y.double().cpu().numpy() - A.matvec(xr))
+    assert np.all(err <= bound + 1e-300), float(np.max(err / (bound + 1e-300)))
+    vs = 8 if dtype == pcg.PCG_F64 else 4
+    al = lambda v: (v + 255) // 256 * 256
+    nnz = A.val.size
+    rowp = buf[al(vs * nnz) + al(4 * nnz):].view(torch.int32)[: p.n + 1].cpu().numpy()
+    np.testing.assert_array_equal(rowp, A.row_ptr.astype(np.int32))
+
+
 def test_full_size_periodic_equal_iterations():
     """The headline workload in the benchmark's launch configuration (zero
     start, adaptive HIP-graph chunks with event nodes, the committed tuning:
