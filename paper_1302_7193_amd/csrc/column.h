@@ -55,8 +55,8 @@ namespace {
 template <int D, bool UP, typename T>
 __device__ __forceinline__ void scan_step(T& P, T& Q, int l, int L)
 {
-    const T Pn = dpp_move<UP ? kRowShr + D : kRowShl + D>(P, T(1));
-    const T Qn = dpp_move<UP ? kRowShr + D : kRowShl + D>(Q, T(0));
+    const T Pn = dpp_move<UP ? kRowShr + D : kRowShl + D, 1>(P);
+    const T Qn = dpp_move<UP ? kRowShr + D : kRowShl + D>(Q);
     // segments of 16 lanes or more are whole rows: the lanes whose partner
     // lies outside the segment are exactly those past the row edge, which
     // already received the identity
@@ -79,8 +79,8 @@ __device__ __forceinline__ T segment_carry(T P, T Q, int l, int L)
     if (L > 8) scan_step<8, UP>(P, Q, l, L);
     // (P, Q) now composes the lanes from the row's (or segment's) edge to
     // this lane; the neighbour's composition, identity at an edge
-    T Px = dpp_move<UP ? kRowShr + 1 : kRowShl + 1>(P, T(1));
-    T Qx = dpp_move<UP ? kRowShr + 1 : kRowShl + 1>(Q, T(0));
+    T Px = dpp_move<UP ? kRowShr + 1 : kRowShl + 1, 1>(P);
+    T Qx = dpp_move<UP ? kRowShr + 1 : kRowShl + 1>(Q);
     if (L < 16 && (UP ? l == 0 : l == L - 1)) {   // (a row edge for L >= 16)
         Px = T(1);
         Qx = T(0);
@@ -332,8 +332,8 @@ __device__ __forceinline__ void stencil_nb(const Geom& g, const Col& c, int l, i
     nb(2, c.jm, c.ok && c.jm >= 0, xjm);
     nb(3, c.jp, c.ok && c.jp >= 0, xjp);
 
-    T below = dpp_move<kWaveShr1>(xc[M - 1], T(0));
-    T above = dpp_move<kWaveShl1>(xc[0], T(0));
+    T below = dpp_move<kWaveShr1>(xc[M - 1]);
+    T above = dpp_move<kWaveShl1>(xc[0]);
     if (l == 0) below = T(0);
     if (l == L - 1) above = T(0);
 
@@ -490,8 +490,8 @@ template <int D>
 __device__ __forceinline__ void mobius_step(double& e00, double& e01, double& e10, double& e11,
                                             int l)
 {
-    const double f00 = dpp_move<kRowShr + D>(e00, 1.0), f01 = dpp_move<kRowShr + D>(e01, 0.0);
-    const double f10 = dpp_move<kRowShr + D>(e10, 0.0), f11 = dpp_move<kRowShr + D>(e11, 1.0);
+    const double f00 = dpp_move<kRowShr + D, 1>(e00), f01 = dpp_move<kRowShr + D>(e01);
+    const double f10 = dpp_move<kRowShr + D>(e10), f11 = dpp_move<kRowShr + D, 1>(e11);
     if (l >= D) {
         const double n00 = e00 * f00 + e01 * f10, n01 = e00 * f01 + e01 * f11;
         const double n10 = e10 * f00 + e11 * f10, n11 = e10 * f01 + e11 * f11;
@@ -545,8 +545,8 @@ __device__ __forceinline__ void gen_factors(const Col& c, int l, int L, int k0, 
     if (L > 4) mobius_step<4>(e00, e01, e10, e11, l);
     if (L > 8) mobius_step<8>(e00, e01, e10, e11, l);
     // the lanes below this one within its row (identity at a row start) ...
-    const double x00 = dpp_move<kRowShr + 1>(e00, 1.0), x01 = dpp_move<kRowShr + 1>(e01, 0.0);
-    const double x10 = dpp_move<kRowShr + 1>(e10, 0.0), x11 = dpp_move<kRowShr + 1>(e11, 1.0);
+    const double x00 = dpp_move<kRowShr + 1, 1>(e00), x01 = dpp_move<kRowShr + 1>(e01);
+    const double x10 = dpp_move<kRowShr + 1>(e10), x11 = dpp_move<kRowShr + 1, 1>(e11);
     // ... applied to what the rows below it in the segment make of
     // delta_{-1} = (1, 0), from the rows' products
     double v0 = 1.0, v1 = 0.0;

@@ -29,20 +29,31 @@ constexpr int kRowShr = 0x110, kRowShl = 0x100, kWaveShr1 = 0x138, kWaveShl1 = 0
 constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kRowRor = 0x120;
 
 // Lane i receives x from the lane CTRL names; lanes without a source lane
-// (past the row or wavefront edge) receive id.
-template <int CTRL, typename T>
-__device__ __forceinline__ T dpp_move(T x, T id)
+// (past the row or wavefront edge) receive the identity ONE ? 1 : 0.  A
+// 32-bit half whose identity bits are zero is moved with the zero fill for
+// missing source lanes (bound_ctrl), so its destination needs no
+// initialisation; only the high half of a floating-point 1 keeps an old
+// value.
+template <int CTRL>
+__device__ __forceinline__ int dpp_half(int x, int id_bits)
 {
+    if (id_bits == 0) return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
+    return __builtin_amdgcn_update_dpp(id_bits, x, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL, int ONE = 0, typename T>
+__device__ __forceinline__ T dpp_move(T x)
+{
+    static_assert(ONE == 0 || ONE == 1, "identity 0 or 1");
     if constexpr (sizeof(T) == 8) {
-        const int64_t xb = __builtin_bit_cast(int64_t, x), ib = __builtin_bit_cast(int64_t, id);
-        const int lo = __builtin_amdgcn_update_dpp((int)ib, (int)xb, CTRL, 0xF, 0xF, false);
-        const int hi =
-            __builtin_amdgcn_update_dpp((int)(ib >> 32), (int)(xb >> 32), CTRL, 0xF, 0xF, false);
+        const int64_t xb = __builtin_bit_cast(int64_t, x);
+        const int64_t ib = ONE ? __builtin_bit_cast(int64_t, T(1)) : 0;
+        const int lo = dpp_half<CTRL>((int)xb, (int)ib);
+        const int hi = dpp_half<CTRL>((int)(xb >> 32), (int)(ib >> 32));
         return __builtin_bit_cast(T, ((int64_t)hi << 32) | (int64_t)(uint32_t)lo);
     } else {
-        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, id),
-                                                                 __builtin_bit_cast(int, x), CTRL,
-                                                                 0xF, 0xF, false));
+        const int ib = ONE ? __builtin_bit_cast(int, T(1)) : 0;
+        return __builtin_bit_cast(T, dpp_half<CTRL>(__builtin_bit_cast(int, x), ib));
     }
 }
 
@@ -66,10 +77,10 @@ __device__ __forceinline__ T read_lane(T x, int lane)
 // sums), then the four rows' sums from lanes 0, 16, 32, 48.
 __device__ __forceinline__ double wave_sum(double v)
 {
-    v += dpp_move<kQuadXor1>(v, 0.0);
-    v += dpp_move<kQuadXor2>(v, 0.0);
-    v += dpp_move<kRowRor + 4>(v, 0.0);
-    v += dpp_move<kRowRor + 8>(v, 0.0);
+    v += dpp_move<kQuadXor1>(v);
+    v += dpp_move<kQuadXor2>(v);
+    v += dpp_move<kRowRor + 4>(v);
+    v += dpp_move<kRowRor + 8>(v);
     return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
